@@ -1,0 +1,178 @@
+/*
+ * idsketch: CountSketch / TensorSketch interpolative decomposition on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method (Malik & Becker, "Fast randomized matrix and tensor
+ * interpolative decomposition using CountSketch"):
+ *   matrix ID  A ~= A[:, J] P      (problem statement, Section 1.3.1)
+ *     Algorithm 2: draw a CountSketch S, form Y = S A implicitly, then run
+ *     Algorithm 1 (rank-K column-pivoted QR of Y, J from the pivots,
+ *     P = [I, R11^{-1} R12] Pi^T) on Y.  This library optionally inserts a
+ *     Gaussian projection Y = G (S A) between the two stages.
+ *   tensor ID  X_hat = sum_k lambda_hat_k X^(j_k)   (Section 1.3.2, eq. X*)
+ *     Algorithm 3: TensorSketch Y = T M of the implicit matrix
+ *     M = (Khatri-Rao of the factors) diag(lambda) via per-mode CountSketch,
+ *     FFT, Hadamard product and inverse FFT; Algorithm 1 on Y; then
+ *     lambda_hat_k = lambda_{j_k} sum_r p_kr.
+ *
+ * Conventions shared by every entry point
+ *   - Every array argument is a DEVICE pointer on the current HIP device,
+ *     owned by the caller, unless stated otherwise.  The library never
+ *     allocates or frees user-visible memory; scratch space comes from the
+ *     caller's workspace (size from the matching *_workspace_size call,
+ *     256-byte aligned).
+ *   - All calls are asynchronous on `stream` (a hipStream_t passed as void*;
+ *     NULL = the default stream).  Argument errors are detected on the host
+ *     and returned before anything is launched.  Results (including k_eff)
+ *     are valid once the stream has been synchronised.
+ *   - Indices are 0-based (the paper's [m] = {1..m}).  Dense matrices are
+ *     row-major unless stated otherwise.
+ *   - Random maps: the CountSketch bucket h(i) and sign D_ii of row i come
+ *     from a counter-based SplitMix64 stream (Steele, Lea & Flood 2014):
+ *       key   = mix64(seed XOR mix64(tag))
+ *       z_i   = mix64(key + (i+1) * 0x9e3779b97f4a7c15)
+ *       h(i)  = (hi32(z_i) * L) >> 32,   D_ii = bit0(z_i) ? -1 : +1
+ *     TensorSketch mode n uses tag (tag_base + n + 1).
+ *   - Errors: a nonzero ids_status; ids_last_error() gives a message for the
+ *     calling thread.
+ */
+#ifndef IDSKETCH_H
+#define IDSKETCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ids_status;
+enum {
+    IDS_OK = 0,
+    IDS_EINVAL = 1,      /* bad sizes, null pointers, unsupported shapes */
+    IDS_EDTYPE = 2,      /* unsupported dtype combination */
+    IDS_EWORKSPACE = 3,  /* workspace missing, too small or misaligned */
+    IDS_EHIP = 4,        /* a HIP runtime call failed (message has details) */
+    IDS_ETIMEOUT = 5     /* a device-wide barrier gave up (never expected) */
+};
+
+/* element types */
+enum { IDS_F64 = 0, IDS_F32 = 1, IDS_BF16 = 2 };
+/* matrix formats */
+enum { IDS_DENSE = 0, IDS_CSR = 1 };
+/* ids_sketch_cfg.flags */
+#define IDS_HASH_FULLRANK 1u /* modified map h~ = f o pi (Remark 2, Prop. 4) */
+
+typedef struct {
+    int32_t fmt;            /* IDS_DENSE: row-major m x n, leading dim ld (elements)
+                               IDS_CSR:   rowptr[m+1] (int64), colind[nnz] (int32,
+                                          in [0,n); duplicates are summed), val[nnz] */
+    int32_t dtype;          /* dense: IDS_F64, IDS_F32 or IDS_BF16; CSR: IDS_F64 */
+    int64_t m, n, ld, nnz;
+    const void* val;
+    const int64_t* rowptr;
+    const int32_t* colind;
+} ids_matrix;
+
+typedef struct {
+    int64_t l1;             /* CountSketch height L1 (1 <= l1 <= 32768)           */
+    int64_t l;              /* final sketch height; l == l1: no projection (the   */
+                            /* paper's Algorithm 2 exactly); l < l1: Y = G (S A)  */
+    uint64_t seed, tag;     /* random-map stream                                   */
+    uint32_t flags;         /* IDS_HASH_FULLRANK                                   */
+    int32_t acc;            /* CountSketch accumulation: IDS_F64 or IDS_F32        */
+                            /* (F64 input requires IDS_F64)                        */
+    int32_t proj;           /* projection arithmetic: IDS_F64 (FP64 MFMA) or       */
+                            /* IDS_F32 (FP32 MFMA); must equal acc                 */
+    const void* G;          /* l x l1 row-major Gaussian, element type = proj;     */
+                            /* ignored when l == l1                                */
+    const int64_t* fr_pi;   /* IDS_HASH_FULLRANK: permutation pi of [0, m)        */
+    const int32_t* fr_x;    /* IDS_HASH_FULLRANK: x[q] in [0, l1) for q >= l1     */
+} ids_sketch_cfg;
+
+/*
+ * id_sketch -- Algorithm 2, "draw S" and "compute Y = S A implicitly"
+ * (CountSketch, Section 1.4), optionally followed by the Gaussian projection
+ * of the sketch (Section 1.3.1).
+ *   A      matrix descriptor (device data).
+ *   cfg    sketch configuration.
+ *   Y      output, l x n, COLUMN-major with leading dimension ldy >= l
+ *          (entry (i, j) at Y[j*ldy + i]); element type ydt = cfg->acc.
+ * Workspace: ids_sketch_workspace_size().  Deterministic: the same inputs
+ * give bitwise-identical Y (rows of a bucket are added in increasing row
+ * order, the order of the textbook definition).
+ */
+ids_status ids_sketch_workspace_size(const ids_matrix* A, const ids_sketch_cfg* cfg,
+                                     size_t* bytes);
+ids_status id_sketch(const ids_matrix* A, const ids_sketch_cfg* cfg, void* Y, int32_t ydt,
+                     int64_t ldy, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * id_project -- the projection step alone: Y = G Y1 with G l x q row-major,
+ * Y1 q x n row-major (leading dim ld1), Y l x n column-major (leading dim
+ * ldy).  dtype IDS_F64 (FP64 MFMA) or IDS_F32 (FP32 MFMA); G, Y1, Y share it.
+ */
+ids_status id_project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void* G,
+                      const void* Y1, int64_t ld1, void* Y, int64_t ldy, void* stream);
+
+/*
+ * id_select -- Algorithm 1 on a sketch Y (l x n): rank-k column-pivoted QR
+ * (greedy largest trailing column norm, ties to the smallest column index,
+ * norms recomputed in FP64 every step), J from the pivots, and
+ * P = [I, R11^{-1} R12] Pi^T in the original column order (P[:, J[t]] = e_t).
+ *   Y      entry (i, j) at Y[i*rs + j*cs]; ydt IDS_F64 or IDS_F32 (FP32 is
+ *          widened to FP64 on load; all arithmetic is FP64).
+ *   k      1 <= k < n and k <= l; l <= 4096; n at most what fits the
+ *          register-resident factorisation (IDS_EINVAL otherwise).
+ *   J      int64[k]   chosen columns (entries >= k_eff are set to -1).
+ *   P      double[k*n] row-major (rows >= k_eff are zero).
+ *   k_eff  int64[1]   number of pivots taken: k unless a zero trailing norm
+ *          (rank deficiency) stopped the factorisation early.
+ */
+ids_status ids_select_workspace_size(int64_t l, int64_t n, int64_t k, size_t* bytes);
+ids_status id_select(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t rs, int64_t cs,
+                     int64_t k, int64_t* J, double* P, int64_t* k_eff, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/*
+ * tensor_id -- Algorithm 3 for an N-way CP tensor (eq. def-X-tensor) with R
+ * terms, in FP64.
+ *   factors  host array of N device pointers; factor n is I_n x R COLUMN-major
+ *            (entry (i, r) at factors[n][r*ld[n] + i], ld[n] >= dims[n]).
+ *   lambda   double[R] s-values.
+ *   Jlen     TensorSketch length L (power of two, 16 <= Jlen <= 4096).
+ *   k        target rank, k < R, k <= Jlen.
+ *   Y        optional output (may be NULL): the sketch T M, Jlen x R
+ *            column-major (leading dimension Jlen).
+ *   J, P, k_eff  as in id_select; lambda_hat double[k] (entries >= k_eff
+ *            are zero).
+ * Random maps h_n, s_n: stream (seed, tag n + 1) over [0, I_n) into Jlen.
+ */
+ids_status ids_tensor_workspace_size(int32_t N, const int64_t* dims, int64_t R, int64_t k,
+                                     int64_t Jlen, size_t* bytes);
+ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* const* factors,
+                     const int64_t* ld, const double* lambda, int64_t k, int64_t Jlen,
+                     uint64_t seed, double* Y, int64_t* J, double* P, double* lambda_hat,
+                     int64_t* k_eff, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Stage timing.  While enabled, every call records a pair of HIP events on its
+ * stream around each stage ("plan", "countsketch", "project", "cpqr", "trsm",
+ * "tensorsketch", "lambda_hat").  ids_profile_read waits for the recorded
+ * events and returns the summed elapsed milliseconds and the number of
+ * recorded launches of a stage; ids_profile_reset waits for and recycles them.
+ * Intended for measurement; off by default.
+ */
+void ids_profile_enable(int on);
+ids_status ids_profile_read(const char* stage, double* total_ms, int64_t* count);
+void ids_profile_reset(void);
+
+/* Human-readable name of a status code, and the calling thread's last error
+ * message (empty string when the last call succeeded). */
+const char* ids_status_string(ids_status s);
+const char* ids_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IDSKETCH_H */

@@ -1,0 +1,269 @@
+"""idsketch: CountSketch / TensorSketch interpolative decomposition on MI355X.
+
+Thin Python binding over the C-ABI library ``libidsketch.so`` (declared in
+``include/idsketch.h``).  It only marshals arguments: torch tensors provide
+device memory and the current HIP stream, and every step of the computation
+runs in the library's HIP kernels.  There is no fallback: if the library is
+missing or no GPU is present, calls raise.
+
+Method (Malik & Becker, "Fast randomized matrix and tensor interpolative
+decomposition using CountSketch"):
+  * :func:`id_sketch`  -- Algorithm 2, CountSketch Y1 = S A (Section 1.4), with
+    an optional Gaussian projection Y = G Y1 (Section 1.3.1).
+  * :func:`id_select`  -- Algorithm 1 on a sketch: rank-k column-pivoted QR,
+    J and P = [I, R11^{-1} R12] Pi^T.
+  * :func:`matrix_id`  -- the two above in sequence.
+  * :func:`tensor_id`  -- Algorithm 3: TensorSketch, Algorithm 1,
+    lambda_hat_k = lambda_{j_k} sum_r p_kr.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["lib", "lib_path", "profile_enable", "profile_read", "profile_reset", "id_sketch", "id_project", "id_select", "matrix_id", "tensor_id",
+           "IdsError", "F64", "F32", "BF16", "HASH_FULLRANK", "EXPORTED"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libidsketch.so")
+
+F64, F32, BF16 = 0, 1, 2
+DENSE, CSR = 0, 1
+HASH_FULLRANK = 1
+
+EXPORTED = ["ids_sketch_workspace_size", "id_sketch", "id_project", "ids_select_workspace_size",
+            "id_select", "ids_tensor_workspace_size", "tensor_id", "ids_profile_enable", "ids_profile_read",
+            "ids_profile_reset", "ids_status_string", "ids_last_error"]
+
+c_i64 = ctypes.c_int64
+c_i32 = ctypes.c_int32
+c_u64 = ctypes.c_uint64
+c_u32 = ctypes.c_uint32
+c_vp = ctypes.c_void_p
+c_sz = ctypes.c_size_t
+
+
+class IdsMatrix(ctypes.Structure):
+    _fields_ = [("fmt", c_i32), ("dtype", c_i32), ("m", c_i64), ("n", c_i64), ("ld", c_i64),
+                ("nnz", c_i64), ("val", c_vp), ("rowptr", c_vp), ("colind", c_vp)]
+
+
+class IdsSketchCfg(ctypes.Structure):
+    _fields_ = [("l1", c_i64), ("l", c_i64), ("seed", c_u64), ("tag", c_u64), ("flags", c_u32),
+                ("acc", c_i32), ("proj", c_i32), ("G", c_vp), ("fr_pi", c_vp), ("fr_x", c_vp)]
+
+
+class IdsError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libidsketch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(lib_path):
+            raise ImportError(f"{lib_path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(lib_path)
+        P = ctypes.POINTER
+        L.ids_sketch_workspace_size.argtypes = [P(IdsMatrix), P(IdsSketchCfg), P(c_sz)]
+        L.id_sketch.argtypes = [P(IdsMatrix), P(IdsSketchCfg), c_vp, c_i32, c_i64, c_vp, c_sz, c_vp]
+        L.id_project.argtypes = [c_i32, c_i64, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp]
+        L.ids_select_workspace_size.argtypes = [c_i64, c_i64, c_i64, P(c_sz)]
+        L.id_select.argtypes = [c_vp, c_i32, c_i64, c_i64, c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]
+        L.ids_tensor_workspace_size.argtypes = [c_i32, c_vp, c_i64, c_i64, c_i64, P(c_sz)]
+        L.tensor_id.argtypes = [c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_u64, c_vp, c_vp, c_vp,
+                                c_vp, c_vp, c_vp, c_sz, c_vp]
+        L.ids_profile_enable.argtypes = [c_i32]
+        L.ids_profile_enable.restype = None
+        L.ids_profile_read.argtypes = [ctypes.c_char_p, P(ctypes.c_double), P(c_i64)]
+        L.ids_profile_read.restype = c_i32
+        L.ids_profile_reset.argtypes = []
+        L.ids_profile_reset.restype = None
+        L.ids_status_string.restype = ctypes.c_char_p
+        L.ids_status_string.argtypes = [c_i32]
+        L.ids_last_error.restype = ctypes.c_char_p
+        L.ids_last_error.argtypes = []
+        for fn in ("ids_sketch_workspace_size", "id_sketch", "id_project", "ids_select_workspace_size",
+                   "id_select", "ids_tensor_workspace_size", "tensor_id"):
+            getattr(L, fn).restype = c_i32
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        L = lib()
+        raise IdsError(f"{what}: {L.ids_status_string(status).decode()} -- {L.ids_last_error().decode()}")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise IdsError("idsketch needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream(torch, stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return c_vp(s.cuda_stream)
+
+
+def _dt(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.bfloat16:
+        return BF16
+    raise IdsError(f"unsupported dtype {t.dtype}")
+
+
+def _tdt(code: int):
+    import torch
+    return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}[code]
+
+
+def _workspace(torch, nbytes: int, device, stream=None):
+    if nbytes == 0:
+        return None, 0
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    if stream is not None:
+        buf.record_stream(stream)  # keep the block reserved until `stream` is done
+    ptr = buf.data_ptr()
+    pad = (-ptr) % 256
+    return (buf, ptr + pad), int(nbytes)
+
+
+def _matrix_desc(A):
+    """Dense torch matrix (row-major, unit column stride) or CSR tuple
+    (rowptr int64, colind int32, val float64, n)."""
+    if isinstance(A, tuple):
+        rowptr, colind, val, n = A
+        assert rowptr.dtype.is_floating_point is False
+        d = IdsMatrix(CSR, F64, rowptr.numel() - 1, int(n), 0, val.numel(), c_vp(val.data_ptr()),
+                      c_vp(rowptr.data_ptr()), c_vp(colind.data_ptr()))
+        return d, val.device
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise IdsError("dense A must be a 2-D tensor with unit column stride (row-major)")
+    d = IdsMatrix(DENSE, _dt(A), A.shape[0], A.shape[1], A.stride(0), 0, c_vp(A.data_ptr()), None, None)
+    return d, A.device
+
+
+def profile_enable(on: bool = True):
+    """Record HIP events around every stage of subsequent calls."""
+    lib().ids_profile_enable(1 if on else 0)
+
+
+def profile_read(stage: str):
+    """(total milliseconds, number of launches) recorded for a stage."""
+    ms = ctypes.c_double(0.0)
+    cnt = c_i64(0)
+    _check(lib().ids_profile_read(stage.encode(), ctypes.byref(ms), ctypes.byref(cnt)), "ids_profile_read")
+    return ms.value, cnt.value
+
+
+def profile_reset():
+    lib().ids_profile_reset()
+
+
+def id_sketch(A, l1: int, l: int | None = None, *, seed: int = 0, tag: int = 0, G=None, acc: int | None = None,
+              fullrank=None, stream=None):
+    """Y = (G) S A, returned as an l x n view of a column-major buffer."""
+    torch = _torch()
+    desc, dev = _matrix_desc(A)
+    if l is None:
+        l = l1
+    if acc is None:
+        acc = F64 if desc.dtype == F64 else F32
+    flags = 0
+    pi = x = None
+    if fullrank is not None:
+        pi, x = fullrank
+        flags |= HASH_FULLRANK
+    cfg = IdsSketchCfg(l1, l, seed, tag, flags, acc, acc, c_vp(G.data_ptr()) if G is not None else None,
+                       c_vp(pi.data_ptr()) if pi is not None else None, c_vp(x.data_ptr()) if x is not None else None)
+    if G is not None and l < l1:
+        if _dt(G) != acc or tuple(G.shape) != (l, l1) or not G.is_contiguous():
+            raise IdsError("G must be a contiguous l x l1 tensor of the accumulation dtype")
+    nbytes = c_sz(0)
+    _check(lib().ids_sketch_workspace_size(ctypes.byref(desc), ctypes.byref(cfg), ctypes.byref(nbytes)),
+           "ids_sketch_workspace_size")
+    ws, wsb = _workspace(torch, nbytes.value, dev, stream)
+    Yb = torch.empty((desc.n, l), dtype=_tdt(acc), device=dev)
+    _check(lib().id_sketch(ctypes.byref(desc), ctypes.byref(cfg), c_vp(Yb.data_ptr()), acc, l,
+                           c_vp(ws[1]) if ws else None, wsb, _stream(torch, stream)), "id_sketch")
+    return Yb.t()
+
+
+def id_project(G, Y1, stream=None):
+    """Y = G Y1 (G l x q, Y1 q x n, both row-major), returned l x n column-major."""
+    torch = _torch()
+    l, q = G.shape
+    q2, n = Y1.shape
+    if q2 != q or G.dtype != Y1.dtype or not G.is_contiguous() or Y1.stride(1) != 1:
+        raise IdsError("shape/dtype/layout mismatch")
+    Yb = torch.empty((n, l), dtype=G.dtype, device=G.device)
+    _check(lib().id_project(_dt(G), l, q, n, c_vp(G.data_ptr()), c_vp(Y1.data_ptr()), Y1.stride(0),
+                            c_vp(Yb.data_ptr()), l, _stream(torch, stream)), "id_project")
+    return Yb.t()
+
+
+def id_select(Y, k: int, stream=None):
+    """Algorithm 1 on a sketch Y (l x n, any strides).  Returns (J, P, k_eff)
+    where J (int64[k]), P (float64 k x n) and k_eff (int64[1]) are device tensors."""
+    torch = _torch()
+    l, n = Y.shape
+    nbytes = c_sz(0)
+    _check(lib().ids_select_workspace_size(l, n, k, ctypes.byref(nbytes)), "ids_select_workspace_size")
+    ws, wsb = _workspace(torch, nbytes.value, Y.device, stream)
+    J = torch.empty(k, dtype=torch.int64, device=Y.device)
+    P = torch.empty((k, n), dtype=torch.float64, device=Y.device)
+    keff = torch.empty(1, dtype=torch.int64, device=Y.device)
+    _check(lib().id_select(c_vp(Y.data_ptr()), _dt(Y), l, n, Y.stride(0), Y.stride(1), k, c_vp(J.data_ptr()),
+                           c_vp(P.data_ptr()), c_vp(keff.data_ptr()), c_vp(ws[1]) if ws else None, wsb,
+                           _stream(torch, stream)), "id_select")
+    return J, P, keff
+
+
+def matrix_id(A, k: int, l1: int, l: int | None = None, *, seed: int = 0, tag: int = 0, G=None,
+              acc: int | None = None, fullrank=None, stream=None):
+    """Algorithm 2 (+ optional projection), then Algorithm 1.  Returns dict."""
+    Y = id_sketch(A, l1, l, seed=seed, tag=tag, G=G, acc=acc, fullrank=fullrank, stream=stream)
+    J, P, keff = id_select(Y, k, stream=stream)
+    return dict(Y=Y, J=J, P=P, k_eff=keff)
+
+
+def tensor_id(factors, lam, k: int, Jlen: int, *, seed: int = 0, return_Y: bool = False, stream=None):
+    """Algorithm 3.  factors: list of I_n x R float64 device tensors with unit
+    row stride (column-major, e.g. ``F.t().contiguous().t()``)."""
+    torch = _torch()
+    N = len(factors)
+    R = factors[0].shape[1]
+    for f in factors:
+        if f.dtype != torch.float64 or f.stride(0) != 1 or f.shape[1] != R:
+            raise IdsError("factors must be float64, column-major (stride(0) == 1), I_n x R")
+    dims = (c_i64 * N)(*[f.shape[0] for f in factors])
+    ld = (c_i64 * N)(*[f.stride(1) for f in factors])
+    fptr = (c_vp * N)(*[f.data_ptr() for f in factors])
+    dev = factors[0].device
+    nbytes = c_sz(0)
+    _check(lib().ids_tensor_workspace_size(N, ctypes.cast(dims, c_vp), R, k, Jlen, ctypes.byref(nbytes)),
+           "ids_tensor_workspace_size")
+    ws, wsb = _workspace(torch, nbytes.value, dev, stream)
+    Y = torch.empty((R, Jlen), dtype=torch.float64, device=dev) if return_Y else None
+    J = torch.empty(k, dtype=torch.int64, device=dev)
+    P = torch.empty((k, R), dtype=torch.float64, device=dev)
+    lh = torch.empty(k, dtype=torch.float64, device=dev)
+    keff = torch.empty(1, dtype=torch.int64, device=dev)
+    _check(lib().tensor_id(N, ctypes.cast(dims, c_vp), R, ctypes.cast(fptr, c_vp), ctypes.cast(ld, c_vp),
+                           c_vp(lam.data_ptr()), k, Jlen, seed, c_vp(Y.data_ptr()) if Y is not None else None,
+                           c_vp(J.data_ptr()), c_vp(P.data_ptr()), c_vp(lh.data_ptr()), c_vp(keff.data_ptr()),
+                           c_vp(ws[1]) if ws else None, wsb, _stream(torch, stream)), "tensor_id")
+    out = dict(J=J, P=P, lambda_hat=lh, k_eff=keff)
+    if Y is not None:
+        out["Y"] = Y.t()
+    return out

@@ -1,0 +1,397 @@
+// C-ABI layer of idsketch: argument validation, workspace carving and launch
+// sequencing.  Declarations and contracts: include/idsketch.h.
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ids {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+ids_status check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string(what) + ": " + hipGetErrorString(e));
+        return IDS_EHIP;
+    }
+    return IDS_OK;
+}
+
+size_t lds_limit() {
+    static std::mutex mu;
+    static std::unordered_map<int, size_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
+    cache[dev] = (size_t)v;
+    return (size_t)v;
+}
+
+// ---------------------------------------------------------------------------
+// stage timing (HIP events recorded around each stage on its stream)
+// ---------------------------------------------------------------------------
+static const char* kProfNames[PK_COUNT] = {"plan", "countsketch", "project", "cpqr",
+                                           "trsm", "tensorsketch", "lambda_hat"};
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+};
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_recs;
+static std::vector<hipEvent_t> g_pool;
+
+static hipEvent_t prof_event() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ProfScope::ProfScope(int k, hipStream_t s) : kind(k), st(s), a(nullptr), on(false) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_prof_on) return;
+    a = prof_event();
+    if (a && hipEventRecord(a, st) == hipSuccess) on = true;
+}
+
+ProfScope::~ProfScope() {
+    if (!on) return;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    hipEvent_t b = prof_event();
+    if (b && hipEventRecord(b, st) == hipSuccess) g_recs.push_back({kind, a, b});
+}
+
+static ids_status fail(ids_status s, const std::string& msg) {
+    set_error(msg);
+    return s;
+}
+
+static size_t esize(int32_t dt) { return dt == IDS_F64 ? 8 : dt == IDS_F32 ? 4 : 2; }
+
+static bool aligned256(const void* p) { return ((uintptr_t)p & 255) == 0; }
+
+static ids_status check_ws(void* ws, size_t ws_bytes, size_t need) {
+    if (need == 0) return IDS_OK;
+    if (!ws) return fail(IDS_EWORKSPACE, "workspace is NULL but " + std::to_string(need) + " bytes are needed");
+    if (!aligned256(ws)) return fail(IDS_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(IDS_EWORKSPACE,
+                    "workspace too small: " + std::to_string(ws_bytes) + " < " + std::to_string(need) + " bytes");
+    return IDS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sketch
+// ---------------------------------------------------------------------------
+static ids_status validate_sketch(const ids_matrix* A, const ids_sketch_cfg* c) {
+    if (!A || !c) return fail(IDS_EINVAL, "A and cfg must be non-NULL");
+    if (A->m < 1 || A->n < 1) return fail(IDS_EINVAL, "matrix must be at least 1 x 1");
+    if (A->m >= (int64_t(1) << 31) - 1) return fail(IDS_EINVAL, "m must be < 2^31 - 1");
+    if (A->fmt == IDS_DENSE) {
+        if (!A->val) return fail(IDS_EINVAL, "dense A: val is NULL");
+        if (A->ld < A->n) return fail(IDS_EINVAL, "dense A: ld < n");
+        if (A->dtype != IDS_F64 && A->dtype != IDS_F32 && A->dtype != IDS_BF16)
+            return fail(IDS_EDTYPE, "dense A: dtype must be IDS_F64, IDS_F32 or IDS_BF16");
+    } else if (A->fmt == IDS_CSR) {
+        if (!A->val || !A->rowptr || !A->colind) return fail(IDS_EINVAL, "CSR A: rowptr, colind and val required");
+        if (A->dtype != IDS_F64) return fail(IDS_EDTYPE, "CSR A: dtype must be IDS_F64");
+        if (A->nnz < 0) return fail(IDS_EINVAL, "CSR A: nnz < 0");
+        if (A->n >= (int64_t(1) << 31)) return fail(IDS_EINVAL, "CSR A: n must be < 2^31");
+    } else {
+        return fail(IDS_EINVAL, "unknown matrix format");
+    }
+    if (c->l1 < 1 || c->l1 > 32768) return fail(IDS_EINVAL, "l1 must be in [1, 32768]");
+    if (c->l < 1 || c->l > c->l1) return fail(IDS_EINVAL, "l must be in [1, l1]");
+    if (c->acc != IDS_F64 && c->acc != IDS_F32) return fail(IDS_EDTYPE, "acc must be IDS_F64 or IDS_F32");
+    if (A->dtype == IDS_F64 && c->acc != IDS_F64) return fail(IDS_EDTYPE, "FP64 input needs FP64 accumulation");
+    if (A->fmt == IDS_CSR && c->acc != IDS_F64) return fail(IDS_EDTYPE, "CSR input needs FP64 accumulation");
+    if (c->l < c->l1) {
+        if (c->proj != c->acc) return fail(IDS_EDTYPE, "proj must equal acc");
+        if (!c->G) return fail(IDS_EINVAL, "G is required when l < l1");
+    }
+    if (c->flags & ~IDS_HASH_FULLRANK) return fail(IDS_EINVAL, "unknown flag bits");
+    if ((c->flags & IDS_HASH_FULLRANK) && (!c->fr_pi || !c->fr_x))
+        return fail(IDS_EINVAL, "IDS_HASH_FULLRANK needs fr_pi and fr_x");
+    if (sizeof(int32_t) * (size_t)c->l1 > lds_limit()) return fail(IDS_EINVAL, "l1 too large for the LDS histogram");
+    return IDS_OK;
+}
+
+struct SketchLayout {
+    PlanShape ps;
+    size_t plan, y1, bop, total;
+};
+
+static SketchLayout sketch_layout(const ids_matrix* A, const ids_sketch_cfg* c) {
+    SketchLayout L;
+    L.ps = plan_shape(A->m, c->l1);
+    L.plan = plan_bytes(L.ps);
+    L.y1 = (c->l < c->l1) ? align256(esize(c->acc) * (size_t)c->l1 * A->n) : 0;
+    L.bop = (A->fmt == IDS_CSR) ? align256(sizeof(int32_t) * (size_t)A->m) : 0;
+    L.total = L.plan + L.y1 + L.bop;
+    return L;
+}
+
+}  // namespace ids
+
+using namespace ids;
+
+extern "C" {
+
+const char* ids_status_string(ids_status s) {
+    switch (s) {
+        case IDS_OK: return "IDS_OK";
+        case IDS_EINVAL: return "IDS_EINVAL";
+        case IDS_EDTYPE: return "IDS_EDTYPE";
+        case IDS_EWORKSPACE: return "IDS_EWORKSPACE";
+        case IDS_EHIP: return "IDS_EHIP";
+        case IDS_ETIMEOUT: return "IDS_ETIMEOUT";
+        default: return "IDS_UNKNOWN";
+    }
+}
+
+const char* ids_last_error(void) { return g_err.c_str(); }
+
+void ids_profile_enable(int on) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = on != 0;
+}
+
+ids_status ids_profile_read(const char* stage, double* total_ms, int64_t* count) {
+    g_err.clear();
+    if (!stage || !total_ms || !count) return fail(IDS_EINVAL, "stage, total_ms and count must be non-NULL");
+    int kind = -1;
+    for (int k = 0; k < PK_COUNT; ++k)
+        if (std::string(stage) == kProfNames[k]) kind = k;
+    if (kind < 0) return fail(IDS_EINVAL, std::string("unknown stage ") + stage);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (auto& r : g_recs) {
+        if (r.kind != kind) continue;
+        if (hipEventSynchronize(r.b) != hipSuccess) return fail(IDS_EHIP, "hipEventSynchronize failed");
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return fail(IDS_EHIP, "hipEventElapsedTime failed");
+        tot += ms;
+        ++cnt;
+    }
+    *total_ms = tot;
+    *count = cnt;
+    return IDS_OK;
+}
+
+void ids_profile_reset(void) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto& r : g_recs) {
+        hipEventSynchronize(r.b);
+        g_pool.push_back(r.a);
+        g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+}
+
+ids_status ids_sketch_workspace_size(const ids_matrix* A, const ids_sketch_cfg* cfg, size_t* bytes) {
+    g_err.clear();
+    if (!bytes) return fail(IDS_EINVAL, "bytes is NULL");
+    ids_status s = validate_sketch(A, cfg);
+    if (s) return s;
+    *bytes = sketch_layout(A, cfg).total;
+    return IDS_OK;
+}
+
+ids_status id_sketch(const ids_matrix* A, const ids_sketch_cfg* c, void* Y, int32_t ydt, int64_t ldy, void* ws,
+                     size_t ws_bytes, void* stream) {
+    g_err.clear();
+    ids_status s = validate_sketch(A, c);
+    if (s) return s;
+    if (!Y) return fail(IDS_EINVAL, "Y is NULL");
+    if (ydt != c->acc) return fail(IDS_EDTYPE, "ydt must equal cfg->acc");
+    if (ldy < c->l) return fail(IDS_EINVAL, "ldy < l");
+    SketchLayout L = sketch_layout(A, c);
+    if ((s = check_ws(ws, ws_bytes, L.total))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char* p = (char*)ws;
+    PlanBufs pb = plan_carve(L.ps, p);
+    void* Y1 = p;
+    p += L.y1;
+    int32_t* bop = (int32_t*)p;
+
+    const bool proj = c->l < c->l1;
+    const uint64_t key = stream_key(c->seed, c->tag);
+    {
+        ProfScope ps(PK_PLAN, st);
+        s = plan_build(L.ps, key, (c->flags & IDS_HASH_FULLRANK) ? c->fr_pi : nullptr,
+                       (c->flags & IDS_HASH_FULLRANK) ? c->fr_x : nullptr, pb, st);
+    }
+    if (s) return s;
+    // CountSketch destination: row-major Y1 workspace (projection follows) or
+    // the caller's column-major Y directly.
+    void* dst = proj ? Y1 : Y;
+    const int64_t rs = proj ? A->n : 1;
+    const int64_t cs = proj ? 1 : ldy;
+    {
+        ProfScope ps(PK_CS, st);
+        if (A->fmt == IDS_DENSE)
+            s = cs_dense(A->dtype, c->acc, A->val, A->ld, A->n, pb, c->l1, dst, rs, cs, st);
+        else
+            s = cs_csr(A->rowptr, A->colind, (const double*)A->val, A->m, A->n, pb, c->l1, (double*)dst, rs, cs,
+                       bop, st);
+    }
+    if (s) return s;
+    if (proj) {
+        ProfScope ps(PK_PROJ, st);
+        s = project(c->acc, c->l, c->l1, A->n, c->G, Y1, A->n, Y, ldy, st);
+    }
+    return s;
+}
+
+ids_status id_project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void* G, const void* Y1, int64_t ld1,
+                      void* Y, int64_t ldy, void* stream) {
+    g_err.clear();
+    if (!G || !Y1 || !Y) return fail(IDS_EINVAL, "G, Y1 and Y must be non-NULL");
+    if (l < 1 || q < 1 || n < 1) return fail(IDS_EINVAL, "sizes must be positive");
+    if (ld1 < n || ldy < l) return fail(IDS_EINVAL, "leading dimension too small");
+    if (dtype != IDS_F64 && dtype != IDS_F32) return fail(IDS_EDTYPE, "dtype must be IDS_F64 or IDS_F32");
+    return project(dtype, l, q, n, G, Y1, ld1, Y, ldy, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// select
+// ---------------------------------------------------------------------------
+static ids_status validate_select(int64_t l, int64_t n, int64_t k) {
+    if (l < 1 || n < 2) return fail(IDS_EINVAL, "need l >= 1 and n >= 2");
+    if (k < 1 || k >= n) return fail(IDS_EINVAL, "k must satisfy 1 <= k < n");
+    if (k > l) return fail(IDS_EINVAL, "k must be <= l");
+    if (l > 4096) return fail(IDS_EINVAL, "l must be <= 4096");
+    return IDS_OK;
+}
+
+ids_status ids_select_workspace_size(int64_t l, int64_t n, int64_t k, size_t* bytes) {
+    g_err.clear();
+    if (!bytes) return fail(IDS_EINVAL, "bytes is NULL");
+    ids_status s = validate_select(l, n, k);
+    if (s) return s;
+    SelectPlan sp;
+    if ((s = select_plan(l, n, k, sp))) return s;
+    *bytes = select_bytes(sp);
+    return IDS_OK;
+}
+
+ids_status id_select(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t rs, int64_t cs, int64_t k, int64_t* J,
+                     double* P, int64_t* k_eff, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    ids_status s = validate_select(l, n, k);
+    if (s) return s;
+    if (!Y || !J || !P || !k_eff) return fail(IDS_EINVAL, "Y, J, P and k_eff must be non-NULL");
+    if (ydt != IDS_F64 && ydt != IDS_F32) return fail(IDS_EDTYPE, "Y dtype must be IDS_F64 or IDS_F32");
+    if (rs < 1 || cs < 1) return fail(IDS_EINVAL, "strides must be positive");
+    SelectPlan sp;
+    if ((s = select_plan(l, n, k, sp))) return s;
+    if ((s = check_ws(ws, ws_bytes, select_bytes(sp)))) return s;
+    return select_run(sp, Y, ydt, rs, cs, J, P, k_eff, (char*)ws, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// tensor
+// ---------------------------------------------------------------------------
+struct TensorLayout {
+    PlanShape ps[8];
+    size_t plans, tw, y, sel, total;
+    SelectPlan sp;
+};
+
+static ids_status validate_tensor(int32_t N, const int64_t* dims, int64_t R, int64_t k, int64_t Jlen) {
+    if (N < 1 || N > 8) return fail(IDS_EINVAL, "N must be in [1, 8]");
+    if (!dims) return fail(IDS_EINVAL, "dims is NULL");
+    for (int n = 0; n < N; ++n)
+        if (dims[n] < 1 || dims[n] >= (int64_t(1) << 31) - 1) return fail(IDS_EINVAL, "dims[n] out of range");
+    if (R < 2) return fail(IDS_EINVAL, "R must be >= 2");
+    if (Jlen < 16 || Jlen > 4096 || (Jlen & (Jlen - 1))) return fail(IDS_EINVAL, "Jlen must be a power of two in [16, 4096]");
+    if (k < 1 || k >= R || k > Jlen) return fail(IDS_EINVAL, "k must satisfy 1 <= k < R and k <= Jlen");
+    return IDS_OK;
+}
+
+static ids_status tensor_layout(int32_t N, const int64_t* dims, int64_t R, int64_t k, int64_t Jlen,
+                                TensorLayout& T) {
+    T.plans = 0;
+    for (int n = 0; n < N; ++n) {
+        T.ps[n] = plan_shape(dims[n], Jlen);
+        T.plans += plan_bytes(T.ps[n]);
+    }
+    T.tw = align256(sizeof(double2) * (size_t)Jlen);
+    T.y = align256(sizeof(double) * (size_t)Jlen * R);
+    ids_status s = select_plan(Jlen, R, k, T.sp);
+    if (s) return s;
+    T.sel = select_bytes(T.sp);
+    T.total = T.plans + T.tw + T.y + T.sel;
+    return IDS_OK;
+}
+
+ids_status ids_tensor_workspace_size(int32_t N, const int64_t* dims, int64_t R, int64_t k, int64_t Jlen,
+                                     size_t* bytes) {
+    g_err.clear();
+    if (!bytes) return fail(IDS_EINVAL, "bytes is NULL");
+    ids_status s = validate_tensor(N, dims, R, k, Jlen);
+    if (s) return s;
+    TensorLayout T;
+    if ((s = tensor_layout(N, dims, R, k, Jlen, T))) return s;
+    *bytes = T.total;
+    return IDS_OK;
+}
+
+ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* const* factors, const int64_t* ld,
+                     const double* lambda, int64_t k, int64_t Jlen, uint64_t seed, double* Y, int64_t* J, double* P,
+                     double* lambda_hat, int64_t* k_eff, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    ids_status s = validate_tensor(N, dims, R, k, Jlen);
+    if (s) return s;
+    if (!factors || !ld || !lambda || !J || !P || !lambda_hat || !k_eff)
+        return fail(IDS_EINVAL, "factors, ld, lambda, J, P, lambda_hat and k_eff must be non-NULL");
+    for (int n = 0; n < N; ++n) {
+        if (!factors[n]) return fail(IDS_EINVAL, "factors[n] is NULL");
+        if (ld[n] < dims[n]) return fail(IDS_EINVAL, "ld[n] < dims[n]");
+    }
+    if (ts_lds_bytes(Jlen) > lds_limit()) return fail(IDS_EINVAL, "Jlen too large for the LDS FFT on this device");
+    TensorLayout T;
+    if ((s = tensor_layout(N, dims, R, k, Jlen, T))) return s;
+    if ((s = check_ws(ws, ws_bytes, T.total))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    char* p = (char*)ws;
+    PlanBufs pb[8];
+    for (int n = 0; n < N; ++n) pb[n] = plan_carve(T.ps[n], p);
+    double2* tw = (double2*)p;
+    p += T.tw;
+    double* Yw = (double*)p;
+    p += T.y;
+    char* sel = p;
+    double* Yout = Y ? Y : Yw;
+    {
+        ProfScope ps(PK_PLAN, st);
+        for (int n = 0; n < N; ++n)
+            if ((s = plan_build(T.ps[n], stream_key(seed, (uint64_t)n + 1), nullptr, nullptr, pb[n], st))) return s;
+        if ((s = twiddles(Jlen, tw, st))) return s;
+    }
+    {
+        ProfScope ps(PK_TS, st);
+        if ((s = tensorsketch(N, dims, R, factors, ld, lambda, Jlen, pb, tw, Yout, st))) return s;
+    }
+    if ((s = select_run(T.sp, Yout, IDS_F64, 1, Jlen, J, P, k_eff, sel, st))) return s;
+    ProfScope ps(PK_LHAT, st);
+    return ids::lambda_hat(k, R, P, J, k_eff, lambda, lambda_hat, st);
+}
+
+}  // extern "C"

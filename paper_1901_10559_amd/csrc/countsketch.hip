@@ -1,0 +1,439 @@
+// CountSketch Y1 = S A = Phi D A (Section 1.4; Algorithm 2, "compute the
+// sketch implicitly") for dense row-major and CSR matrices on gfx950.
+//
+// Design (bucket owner, no atomics for dense input):
+//   1. plan: every row i gets (h(i), D_ii) from the counter-based hash; a
+//      stable counting sort groups the signed row codes by bucket, rows of a
+//      bucket in increasing order (plan_count -> plan_scan -> plan_place).
+//   2. dense gather: workgroup (panel, bucket) walks the rows of its bucket and
+//      accumulates them in registers, 16-byte loads per lane, several rows in
+//      flight, then writes its slice of Y1 once.  Every entry of Y1 is the sum
+//      of its bucket's signed rows in increasing row order, i.e. the same
+//      sequence of additions as the textbook definition, so the result is
+//      deterministic (and bit-identical to a sequential FP64 evaluation when
+//      the accumulation type is FP64).
+//   3. CSR: workgroup (bucket, row chunk) scatters the stored entries of its
+//      rows into an LDS copy of the bucket's Y1 row (FP64 LDS atomics), then
+//      adds it to Y1 in HBM.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ids {
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct PlanArgs {
+    int64_t m;
+    uint32_t L;
+    uint64_t key;
+    const int64_t* fr_pi;  // modified hash (optional)
+    const int32_t* fr_x;
+    int32_t seg_rows;      // rows per wave segment (multiple of 64)
+    int32_t nseg;
+    int32_t* seg;          // L x nseg counts -> offsets (bucket-major)
+    int32_t* off;          // L + 1
+    int32_t* rows;         // m signed row codes
+};
+
+__device__ __forceinline__ void plan_hash(const PlanArgs& a, int64_t i, uint32_t& b, bool& neg) {
+    hash_row(a.key, i, a.L, b, neg);
+    if (a.fr_pi) {
+        int64_t q = a.fr_pi[i];
+        b = (q < (int64_t)a.L) ? (uint32_t)q : (uint32_t)a.fr_x[q];
+    }
+}
+
+// one wave per segment; LDS histogram of L counters
+__global__ __launch_bounds__(64) void plan_count_kernel(PlanArgs a) {
+    extern __shared__ int32_t hist[];
+    const int s = blockIdx.x;
+    const int lane = threadIdx.x;
+    for (uint32_t b = lane; b < a.L; b += 64) hist[b] = 0;
+    __syncthreads();
+    const int64_t r0 = (int64_t)s * a.seg_rows;
+    const int64_t r1 = min(a.m, r0 + a.seg_rows);
+    for (int64_t i = r0 + lane; i < r1; i += 64) {
+        uint32_t b;
+        bool neg;
+        plan_hash(a, i, b, neg);
+        atomicAdd(&hist[b], 1);
+    }
+    __syncthreads();
+    for (uint32_t b = lane; b < a.L; b += 64) a.seg[(int64_t)b * a.nseg + s] = hist[b];
+}
+
+// exclusive scan of the L x nseg count matrix in bucket-major order
+__global__ __launch_bounds__(1024) void plan_scan_kernel(PlanArgs a) {
+    __shared__ int32_t part[1024];
+    const int64_t N = (int64_t)a.L * a.nseg;
+    const int t = threadIdx.x;
+    const int64_t per = (N + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = min(N, b0 + per);
+    int32_t s = 0;
+    for (int64_t q = b0; q < b1; ++q) s += a.seg[q];
+    part[t] = s;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over 1024 partials
+    for (int o = 1; o < 1024; o <<= 1) {
+        int32_t v = (t >= o) ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int32_t run = (t == 0) ? 0 : part[t - 1];
+    for (int64_t q = b0; q < b1; ++q) {
+        int32_t c = a.seg[q];
+        a.seg[q] = run;
+        if (q % a.nseg == 0) a.off[q / a.nseg] = run;
+        run += c;
+    }
+    if (t == 0) a.off[a.L] = (int32_t)a.m;
+}
+
+// one wave per segment: stable placement (rows of a bucket in increasing order)
+__global__ __launch_bounds__(64) void plan_place_kernel(PlanArgs a) {
+    extern __shared__ int32_t run[];
+    const int s = blockIdx.x;
+    const int lane = threadIdx.x;
+    for (uint32_t b = lane; b < a.L; b += 64) run[b] = a.seg[(int64_t)b * a.nseg + s];
+    __syncthreads();
+    const int64_t r0 = (int64_t)s * a.seg_rows;
+    const int64_t r1 = min(a.m, r0 + a.seg_rows);
+    for (int64_t c0 = r0; c0 < r1; c0 += 64) {
+        const int64_t i = c0 + lane;
+        const bool valid = i < r1;
+        uint32_t b = 0xffffffffu;
+        bool neg = false;
+        if (valid) plan_hash(a, i, b, neg);
+        int rank = 0, same = 0;
+#pragma unroll 8
+        for (int q = 0; q < 64; ++q) {
+            uint32_t bq = __shfl(b, q, 64);
+            int eq = (bq == b) ? 1 : 0;
+            rank += (q < lane) ? eq : 0;
+            same += eq;
+        }
+        int32_t base = 0;
+        if (valid) base = run[b];
+        __syncthreads();
+        if (valid) {
+            a.rows[base + rank] = encode_row(i, neg);
+            if (rank == same - 1) run[b] = base + same;
+        }
+        __syncthreads();
+    }
+}
+
+ids_status plan_build(const PlanShape& ps, uint64_t key, const int64_t* fr_pi, const int32_t* fr_x,
+                      const PlanBufs& pb, hipStream_t st) {
+    PlanArgs a;
+    a.m = ps.m;
+    a.L = (uint32_t)ps.L;
+    a.key = key;
+    a.fr_pi = fr_pi;
+    a.fr_x = fr_x;
+    a.seg_rows = ps.seg_rows;
+    a.nseg = ps.nseg;
+    a.seg = pb.seg;
+    a.off = pb.off;
+    a.rows = pb.rows;
+    size_t lds = sizeof(int32_t) * (size_t)ps.L;
+    hipLaunchKernelGGL(plan_count_kernel, dim3(ps.nseg), dim3(64), lds, st, a);
+    hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(plan_place_kernel, dim3(ps.nseg), dim3(64), lds, st, a);
+    return check_launch("countsketch plan");
+}
+
+PlanShape plan_shape(int64_t m, int64_t L) {
+    PlanShape ps;
+    ps.m = m;
+    ps.L = L;
+    // keep the L x nseg count matrix at most ~4M entries
+    int64_t seg = 1024;
+    int64_t need = (m * L + (int64_t(1) << 22) - 1) >> 22;
+    if (need > seg) seg = need;
+    seg = (seg + 63) / 64 * 64;
+    ps.seg_rows = (int32_t)seg;
+    ps.nseg = (int32_t)((m + seg - 1) / seg);
+    if (ps.nseg < 1) ps.nseg = 1;
+    return ps;
+}
+
+size_t plan_bytes(const PlanShape& ps) {
+    return align256(sizeof(int32_t) * (size_t)ps.L * ps.nseg) + align256(sizeof(int32_t) * (ps.L + 1)) +
+           align256(sizeof(int32_t) * (size_t)ps.m);
+}
+
+PlanBufs plan_carve(const PlanShape& ps, char*& p) {
+    PlanBufs pb;
+    pb.seg = (int32_t*)p;
+    p += align256(sizeof(int32_t) * (size_t)ps.L * ps.nseg);
+    pb.off = (int32_t*)p;
+    p += align256(sizeof(int32_t) * (ps.L + 1));
+    pb.rows = (int32_t*)p;
+    p += align256(sizeof(int32_t) * (size_t)ps.m);
+    return pb;
+}
+
+// ---------------------------------------------------------------------------
+// dense gather
+// ---------------------------------------------------------------------------
+template <typename T, int VEC>
+struct VecLoad;
+template <>
+struct VecLoad<double, 2> {
+    using V = double2;
+    __device__ static void get(const V& v, double* o) { o[0] = v.x; o[1] = v.y; }
+};
+template <>
+struct VecLoad<float, 4> {
+    using V = float4;
+    __device__ static void get(const V& v, float* o) { o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w; }
+};
+template <>
+struct VecLoad<uint16_t, 8> {
+    using V = uint4;
+    __device__ static void get(const V& v, uint16_t* o) {
+        o[0] = v.x & 0xffff; o[1] = v.x >> 16; o[2] = v.y & 0xffff; o[3] = v.y >> 16;
+        o[4] = v.z & 0xffff; o[5] = v.z >> 16; o[6] = v.w & 0xffff; o[7] = v.w >> 16;
+    }
+};
+
+template <typename ACC, typename T>
+__device__ __forceinline__ ACC to_acc(T v) { return (ACC)v; }
+template <>
+__device__ __forceinline__ float to_acc<float, uint16_t>(uint16_t v) { return bf16_to_f32(v); }
+template <>
+__device__ __forceinline__ double to_acc<double, uint16_t>(uint16_t v) { return (double)bf16_to_f32(v); }
+
+constexpr int CS_THREADS = 256;
+constexpr int CS_UNROLL = 8;
+
+template <typename T, typename ACC, int VEC>
+__global__ __launch_bounds__(CS_THREADS) void cs_dense_kernel(const T* __restrict__ A, int64_t lda,
+                                                                int64_t n, const int32_t* __restrict__ off,
+                                                                const int32_t* __restrict__ rows,
+                                                                ACC* __restrict__ Y, int64_t rs, int64_t cs) {
+    const int b = blockIdx.y;
+    const int64_t v = (int64_t)blockIdx.x * CS_THREADS + threadIdx.x;
+    const int64_t c0 = v * VEC;
+    if (c0 >= n) return;
+    const int nvalid = (int)min<int64_t>(VEC, n - c0);
+    const int beg = off[b], end = off[b + 1];
+    ACC acc[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) acc[e] = (ACC)0;
+
+    bool done = false;
+    if constexpr (VEC > 1) {
+        if (nvalid == VEC) {
+            done = true;
+            using VL = VecLoad<T, VEC>;
+            using V = typename VL::V;
+            int p = beg;
+            for (; p + CS_UNROLL <= end; p += CS_UNROLL) {
+                int32_t code[CS_UNROLL];
+#pragma unroll
+                for (int u = 0; u < CS_UNROLL; ++u) code[u] = rows[p + u];
+                V raw[CS_UNROLL];
+#pragma unroll
+                for (int u = 0; u < CS_UNROLL; ++u) {
+                    int64_t i = code[u] >= 0 ? code[u] : -(int64_t)code[u] - 1;
+                    raw[u] = *reinterpret_cast<const V*>(A + i * lda + c0);
+                }
+#pragma unroll
+                for (int u = 0; u < CS_UNROLL; ++u) {
+                    T x[VEC];
+                    VL::get(raw[u], x);
+                    const bool neg = code[u] < 0;
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        ACC xv = to_acc<ACC, T>(x[e]);
+                        acc[e] = neg ? acc[e] - xv : acc[e] + xv;
+                    }
+                }
+            }
+            for (; p < end; ++p) {
+                int32_t code = rows[p];
+                int64_t i = code >= 0 ? code : -(int64_t)code - 1;
+                V raw = *reinterpret_cast<const V*>(A + i * lda + c0);
+                T x[VEC];
+                VL::get(raw, x);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) {
+                    ACC xv = to_acc<ACC, T>(x[e]);
+                    acc[e] = code < 0 ? acc[e] - xv : acc[e] + xv;
+                }
+            }
+        }
+    }
+    if (!done) {
+        for (int p = beg; p < end; ++p) {
+            int32_t code = rows[p];
+            int64_t i = code >= 0 ? code : -(int64_t)code - 1;
+            const T* row = A + i * lda + c0;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) {
+                if (e < nvalid) {
+                    ACC xv = to_acc<ACC, T>(row[e]);
+                    acc[e] = code < 0 ? acc[e] - xv : acc[e] + xv;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+        if (e < nvalid) Y[(int64_t)b * rs + (c0 + e) * cs] = acc[e];
+}
+
+template <typename T, typename ACC, int VEC>
+static void launch_dense(const void* A, int64_t lda, int64_t n, const PlanBufs& pb, int64_t L, void* Y,
+                         int64_t rs, int64_t cs, hipStream_t st) {
+    int64_t nvec = (n + VEC - 1) / VEC;
+    dim3 grid((unsigned)((nvec + CS_THREADS - 1) / CS_THREADS), (unsigned)L);
+    hipLaunchKernelGGL((cs_dense_kernel<T, ACC, VEC>), grid, dim3(CS_THREADS), 0, st, (const T*)A, lda, n,
+                       (const int32_t*)pb.off, (const int32_t*)pb.rows, (ACC*)Y, rs, cs);
+}
+
+ids_status cs_dense(int32_t dtype, int32_t acc, const void* A, int64_t lda, int64_t n, const PlanBufs& pb,
+                    int64_t L, void* Y, int64_t rs, int64_t cs, hipStream_t st) {
+    const uintptr_t base = (uintptr_t)A;
+    auto vec_ok = [&](int esize, int vec) {
+        return (base % 16 == 0) && ((lda * esize) % 16 == 0) && vec * esize == 16;
+    };
+    if (dtype == IDS_F64 && acc == IDS_F64) {
+        if (vec_ok(8, 2)) launch_dense<double, double, 2>(A, lda, n, pb, L, Y, rs, cs, st);
+        else launch_dense<double, double, 1>(A, lda, n, pb, L, Y, rs, cs, st);
+    } else if (dtype == IDS_F32 && acc == IDS_F32) {
+        if (vec_ok(4, 4)) launch_dense<float, float, 4>(A, lda, n, pb, L, Y, rs, cs, st);
+        else launch_dense<float, float, 1>(A, lda, n, pb, L, Y, rs, cs, st);
+    } else if (dtype == IDS_F32 && acc == IDS_F64) {
+        if (vec_ok(4, 4)) launch_dense<float, double, 4>(A, lda, n, pb, L, Y, rs, cs, st);
+        else launch_dense<float, double, 1>(A, lda, n, pb, L, Y, rs, cs, st);
+    } else if (dtype == IDS_BF16 && acc == IDS_F32) {
+        if (vec_ok(2, 8)) launch_dense<uint16_t, float, 8>(A, lda, n, pb, L, Y, rs, cs, st);
+        else launch_dense<uint16_t, float, 1>(A, lda, n, pb, L, Y, rs, cs, st);
+    } else if (dtype == IDS_BF16 && acc == IDS_F64) {
+        if (vec_ok(2, 8)) launch_dense<uint16_t, double, 8>(A, lda, n, pb, L, Y, rs, cs, st);
+        else launch_dense<uint16_t, double, 1>(A, lda, n, pb, L, Y, rs, cs, st);
+    } else {
+        set_error("unsupported (input dtype, accumulation dtype) for dense CountSketch");
+        return IDS_EDTYPE;
+    }
+    return check_launch("countsketch dense");
+}
+
+// ---------------------------------------------------------------------------
+// CSR scatter (FP64)
+// ---------------------------------------------------------------------------
+constexpr int CSR_THREADS = 1024;
+constexpr int CSR_GROUP = 8;  // lanes per row
+
+// LDS-privatised variant: the whole bucket row of Y1 (n <= CSR_LDS_MAX) lives in
+// LDS; a workgroup handles rows [p0, p1) of the bucket's list.
+__global__ __launch_bounds__(CSR_THREADS) void cs_csr_lds_kernel(const int64_t* __restrict__ rowptr,
+                                                                  const int32_t* __restrict__ colind,
+                                                                  const double* __restrict__ val, int64_t n,
+                                                                  const int32_t* __restrict__ off,
+                                                                  const int32_t* __restrict__ rows, int nchunk,
+                                                                  double* __restrict__ Y, int64_t rs, int64_t cs,
+                                                                  int use_atomic) {
+    extern __shared__ double ybuf[];
+    const int b = blockIdx.x / nchunk;
+    const int ch = blockIdx.x % nchunk;
+    for (int64_t j = threadIdx.x; j < n; j += CSR_THREADS) ybuf[j] = 0.0;
+    __syncthreads();
+    const int beg = off[b], end = off[b + 1];
+    const int64_t cnt = end - beg;
+    const int p0 = beg + (int)(cnt * ch / nchunk);
+    const int p1 = beg + (int)(cnt * (ch + 1) / nchunk);
+    const int g = threadIdx.x / CSR_GROUP;
+    const int gl = threadIdx.x % CSR_GROUP;
+    constexpr int NG = CSR_THREADS / CSR_GROUP;
+    for (int p = p0 + g; p < p1; p += NG) {
+        int32_t code = rows[p];
+        int64_t i = code >= 0 ? code : -(int64_t)code - 1;
+        const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
+        for (int64_t e = e0 + gl; e < e1; e += CSR_GROUP) {
+            double v = val[e];
+            atomicAdd(&ybuf[colind[e]], code < 0 ? -v : v);
+        }
+    }
+    __syncthreads();
+    for (int64_t j = threadIdx.x; j < n; j += CSR_THREADS) {
+        double* dst = Y + (int64_t)b * rs + j * cs;
+        if (use_atomic) atomicAdd(dst, ybuf[j]);
+        else *dst = ybuf[j];
+    }
+}
+
+// global-atomic variant for rows wider than LDS
+__global__ __launch_bounds__(256) void cs_csr_global_kernel(const int64_t* __restrict__ rowptr,
+                                                           const int32_t* __restrict__ colind,
+                                                           const double* __restrict__ val,
+                                                           const int32_t* __restrict__ rows, int64_t m,
+                                                           const int32_t* __restrict__ bucket_of_pos,
+                                                           double* __restrict__ Y, int64_t rs, int64_t cs) {
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t p = gid / CSR_GROUP;
+    const int gl = (int)(gid % CSR_GROUP);
+    if (p >= m) return;
+    int32_t code = rows[p];
+    int64_t i = code >= 0 ? code : -(int64_t)code - 1;
+    const int b = bucket_of_pos[p];
+    const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
+    for (int64_t e = e0 + gl; e < e1; e += CSR_GROUP) {
+        double v = val[e];
+        atomicAdd(Y + (int64_t)b * rs + (int64_t)colind[e] * cs, code < 0 ? -v : v);
+    }
+}
+
+// bucket index of every position of the plan's row list
+__global__ void plan_bucket_of_pos_kernel(const int32_t* off, int64_t L, int32_t* bop) {
+    const int b = blockIdx.x;
+    if (b >= L) return;
+    for (int p = off[b] + threadIdx.x; p < off[b + 1]; p += blockDim.x) bop[p] = b;
+}
+
+__global__ void fill_f64_kernel(double* y, int64_t rows, int64_t cols, int64_t rs, int64_t cs) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * cols) return;
+    const int64_t r = t / cols, c = t % cols;
+    y[r * rs + c * cs] = 0.0;
+}
+
+ids_status cs_csr(const int64_t* rowptr, const int32_t* colind, const double* val, int64_t m, int64_t n,
+                  const PlanBufs& pb, int64_t L, double* Y, int64_t rs, int64_t cs, int32_t* scratch_bop,
+                  hipStream_t st) {
+    const size_t lds = sizeof(double) * (size_t)n;
+    if (lds <= CSR_LDS_MAX_BYTES) {
+        // enough workgroups to cover the chip twice, at most one per 256 rows
+        int nchunk = (int)((2 * 256 + L - 1) / L);
+        int64_t rows_per_bucket = (m + L - 1) / L;
+        int64_t maxch = rows_per_bucket / 256;
+        if (nchunk > maxch) nchunk = (int)(maxch > 1 ? maxch : 1);
+        if (nchunk < 1) nchunk = 1;
+        const int use_atomic = nchunk > 1;
+        if (use_atomic) {
+            int64_t tot = L * n;
+            hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Y, L, n,
+                               rs, cs);
+        }
+        hipLaunchKernelGGL(cs_csr_lds_kernel, dim3((unsigned)(L * nchunk)), dim3(CSR_THREADS), lds, st, rowptr,
+                           colind, val, n, (const int32_t*)pb.off, (const int32_t*)pb.rows, nchunk, Y, rs, cs,
+                           use_atomic);
+    } else {
+        int64_t tot = L * n;
+        hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Y, L, n, rs,
+                           cs);
+        hipLaunchKernelGGL(plan_bucket_of_pos_kernel, dim3((unsigned)L), dim3(256), 0, st, (const int32_t*)pb.off,
+                           L, scratch_bop);
+        int64_t thr = m * CSR_GROUP;
+        hipLaunchKernelGGL(cs_csr_global_kernel, dim3((unsigned)((thr + 255) / 256)), dim3(256), 0, st, rowptr,
+                           colind, val, (const int32_t*)pb.rows, m, (const int32_t*)scratch_bop, Y, rs, cs);
+    }
+    return check_launch("countsketch csr");
+}
+
+}  // namespace ids

@@ -1,0 +1,75 @@
+// Internal launch interfaces between the C-ABI layer and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/idsketch.h"
+#include "common.hpp"
+
+namespace ids {
+
+ids_status check_launch(const char* what);
+
+// optional per-stage timing with HIP events on the launch stream
+enum ProfKind { PK_PLAN = 0, PK_CS, PK_PROJ, PK_CPQR, PK_TRSM, PK_TS, PK_LHAT, PK_COUNT };
+struct ProfScope {
+    ProfScope(int kind, hipStream_t st);
+    ~ProfScope();
+    int kind;
+    hipStream_t st;
+    hipEvent_t a;
+    bool on;
+};
+
+// largest dynamic LDS a workgroup may use on the current device
+size_t lds_limit();
+#define CSR_LDS_MAX_BYTES (lds_limit())
+
+// ---- CountSketch plan: rows grouped by bucket -----------------------------
+struct PlanShape {
+    int64_t m, L;
+    int32_t seg_rows, nseg;
+};
+struct PlanBufs {
+    int32_t* seg;
+    int32_t* off;
+    int32_t* rows;
+};
+PlanShape plan_shape(int64_t m, int64_t L);
+size_t plan_bytes(const PlanShape& ps);
+PlanBufs plan_carve(const PlanShape& ps, char*& p);
+ids_status plan_build(const PlanShape& ps, uint64_t key, const int64_t* fr_pi, const int32_t* fr_x,
+                      const PlanBufs& pb, hipStream_t st);
+
+// ---- CountSketch -------------------------------------------------------------
+ids_status cs_dense(int32_t dtype, int32_t acc, const void* A, int64_t lda, int64_t n, const PlanBufs& pb,
+                    int64_t L, void* Y, int64_t rs, int64_t cs, hipStream_t st);
+ids_status cs_csr(const int64_t* rowptr, const int32_t* colind, const double* val, int64_t m, int64_t n,
+                  const PlanBufs& pb, int64_t L, double* Y, int64_t rs, int64_t cs, int32_t* scratch_bop,
+                  hipStream_t st);
+
+// ---- projection GEMM (MFMA): Y(col-major, ldy) = G (l x q) * Y1 (q x n, ld1) --
+ids_status project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void* G, const void* Y1, int64_t ld1,
+                   void* Y, int64_t ldy, hipStream_t st);
+
+// ---- CPQR + interpolation matrix --------------------------------------------
+struct SelectPlan {
+    int64_t l, n, k;
+    int rpl, cpw, nw, nb;  // rows per lane, columns per wave, waves per WG, WGs
+};
+ids_status select_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp);
+size_t select_bytes(const SelectPlan& sp);
+ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t rs, int64_t cs, int64_t* J,
+                      double* P, int64_t* keff, char* ws, hipStream_t st);
+// lambda_hat[t] = lambda[J[t]] * sum_r P[t][r]
+ids_status lambda_hat(int64_t k, int64_t n, const double* P, const int64_t* J, const int64_t* keff,
+                      const double* lambda, double* lhat, hipStream_t st);
+
+// ---- TensorSketch -------------------------------------------------------------
+ids_status tensorsketch(int32_t N, const int64_t* dims, int64_t R, const double* const* factors,
+                        const int64_t* ld, const double* lambda, int64_t Jlen, const PlanBufs* plans,
+                        const double2* twiddle, double* Y, hipStream_t st);
+ids_status twiddles(int64_t Jlen, double2* tw, hipStream_t st);
+size_t ts_lds_bytes(int64_t J);
+
+}  // namespace ids

@@ -1,0 +1,123 @@
+// Second sketch stage Y = G Y1 (Gaussian projection of the CountSketch,
+// Section 1.3.1) on the matrix cores: v_mfma_f64_16x16x4f64 (FP64) and
+// v_mfma_f32_16x16x4f32 (FP32).  64x64 output tile per 256-thread workgroup,
+// each wave a 32x32 quadrant of 2x2 16x16 MFMA blocks; K staged through LDS in
+// slices of 16.  The output is written column-major (column j of Y
+// contiguous), the layout the column-pivoted QR reads.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ids {
+
+typedef double v4f64 __attribute__((ext_vector_type(4)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    using Acc = v4f64;
+    // result r of a lane is row 4 * r + lane / 16
+    __device__ static int row(int lane, int r) { return 4 * r + (lane >> 4); }
+    __device__ static Acc run(double a, double b, Acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma<float> {
+    using Acc = v4f32;
+    // result r of a lane is row 4 * (lane / 16) + r
+    __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+    __device__ static Acc run(float a, float b, Acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+constexpr int PBM = 64, PBN = 64, PBK = 16;
+
+// MFMA 16x16x4 operand layout (lane = 0..63):
+//   A operand: A[lane % 16][lane / 16]      (16 x 4)
+//   B operand: B[lane / 16][lane % 16]      (4 x 16)
+//   result r : C[Mfma<T>::row(lane, r)][lane % 16]; the FP32 and FP64
+//              instructions order the four result rows of a lane differently.
+template <typename T>
+__global__ __launch_bounds__(256) void project_kernel(int64_t l, int64_t q, int64_t n, const T* __restrict__ G,
+                                                      const T* __restrict__ Y1, int64_t ld1, T* __restrict__ Y,
+                                                      int64_t ldy) {
+    __shared__ T Gs[PBM][PBK + 1];
+    __shared__ T Bs[PBK][PBN + 1];
+    using M = Mfma<T>;
+    using Acc = typename M::Acc;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int64_t row0 = (int64_t)blockIdx.y * PBM;
+    const int64_t col0 = (int64_t)blockIdx.x * PBN;
+    Acc acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
+
+    for (int64_t k0 = 0; k0 < q; k0 += PBK) {
+        // G tile: 64 x 16
+#pragma unroll
+        for (int e = 0; e < (PBM * PBK) / 256; ++e) {
+            int idx = tid + e * 256;
+            int r = idx / PBK, c = idx % PBK;
+            int64_t gr = row0 + r, gc = k0 + c;
+            Gs[r][c] = (gr < l && gc < q) ? G[gr * q + gc] : (T)0;
+        }
+        // Y1 tile: 16 x 64
+#pragma unroll
+        for (int e = 0; e < (PBK * PBN) / 256; ++e) {
+            int idx = tid + e * 256;
+            int r = idx / PBN, c = idx % PBN;
+            int64_t gr = k0 + r, gc = col0 + c;
+            Bs[r][c] = (gr < q && gc < n) ? Y1[gr * ld1 + gc] : (T)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < PBK; kk += 4) {
+            T av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = Gs[wm * 32 + a * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + (lane >> 4)][wn * 32 + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = M::run(av[a], bv[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int64_t gr = row0 + wm * 32 + a * 16 + M::row(lane, r);
+                int64_t gc = col0 + wn * 32 + b * 16 + (lane & 15);
+                if (gr < l && gc < n) Y[gc * ldy + gr] = acc[a][b][r];
+            }
+}
+
+ids_status project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void* G, const void* Y1, int64_t ld1,
+                   void* Y, int64_t ldy, hipStream_t st) {
+    dim3 grid((unsigned)((n + PBN - 1) / PBN), (unsigned)((l + PBM - 1) / PBM));
+    if (dtype == IDS_F64) {
+        hipLaunchKernelGGL(project_kernel<double>, grid, dim3(256), 0, st, l, q, n, (const double*)G,
+                           (const double*)Y1, ld1, (double*)Y, ldy);
+    } else if (dtype == IDS_F32) {
+        hipLaunchKernelGGL(project_kernel<float>, grid, dim3(256), 0, st, l, q, n, (const float*)G,
+                           (const float*)Y1, ld1, (float*)Y, ldy);
+    } else {
+        set_error("projection supports IDS_F64 and IDS_F32");
+        return IDS_EDTYPE;
+    }
+    return check_launch("projection");
+}
+
+}  // namespace ids

@@ -1,0 +1,89 @@
+"""Host-side checks of the C-ABI library: it loads, exports every entry point
+declared in include/idsketch.h, and rejects bad arguments before touching the
+GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1901_10559_amd as ids
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "idsketch.h")
+
+
+def declared_functions():
+    text = open(HDR).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_header_parses():
+    names = declared_functions()
+    assert "id_sketch" in names and "id_select" in names and "tensor_id" in names
+    assert set(names) == set(ids.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ids.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = ids.lib()
+    assert L.ids_status_string(0) == b"IDS_OK"
+    assert L.ids_status_string(1) == b"IDS_EINVAL"
+    assert L.ids_status_string(3) == b"IDS_EWORKSPACE"
+    assert L.ids_status_string(99) == b"IDS_UNKNOWN"
+
+
+def test_select_rejects_bad_sizes_without_gpu():
+    L = ids.lib()
+    nb = ctypes.c_size_t(0)
+    assert L.ids_select_workspace_size(10, 5, 5, ctypes.byref(nb)) == 1      # k >= n
+    assert b"k must" in L.ids_last_error()
+    assert L.ids_select_workspace_size(3, 50, 4, ctypes.byref(nb)) == 1      # k > l
+    assert L.ids_select_workspace_size(5000, 50, 4, ctypes.byref(nb)) == 1   # l > 4096
+    assert L.id_select(None, 0, 10, 50, 1, 10, 4, None, None, None, None, 0, None) == 1
+
+
+def test_sketch_rejects_bad_arguments_without_gpu():
+    L = ids.lib()
+    nb = ctypes.c_size_t(0)
+    A = ids.IdsMatrix(ids.DENSE, ids.F64, 100, 20, 20, 0, ctypes.c_void_p(16), None, None)
+    cfg = ids.IdsSketchCfg(30, 40, 0, 0, 0, ids.F64, ids.F64, None, None, None)   # l > l1
+    assert L.ids_sketch_workspace_size(ctypes.byref(A), ctypes.byref(cfg), ctypes.byref(nb)) == 1
+    cfg = ids.IdsSketchCfg(30, 10, 0, 0, 0, ids.F64, ids.F64, None, None, None)   # l < l1 without G
+    assert L.ids_sketch_workspace_size(ctypes.byref(A), ctypes.byref(cfg), ctypes.byref(nb)) == 1
+    assert b"G is required" in L.ids_last_error()
+    cfg = ids.IdsSketchCfg(30, 30, 0, 0, 0, ids.F32, ids.F32, None, None, None)   # FP64 in, FP32 acc
+    assert L.ids_sketch_workspace_size(ctypes.byref(A), ctypes.byref(cfg), ctypes.byref(nb)) == 2
+    A2 = ids.IdsMatrix(ids.DENSE, ids.F64, 100, 20, 10, 0, ctypes.c_void_p(16), None, None)  # ld < n
+    cfg = ids.IdsSketchCfg(30, 30, 0, 0, 0, ids.F64, ids.F64, None, None, None)
+    assert L.ids_sketch_workspace_size(ctypes.byref(A2), ctypes.byref(cfg), ctypes.byref(nb)) == 1
+    cfg = ids.IdsSketchCfg(30, 30, 0, 0, ids.HASH_FULLRANK, ids.F64, ids.F64, None, None, None)
+    assert L.ids_sketch_workspace_size(ctypes.byref(A), ctypes.byref(cfg), ctypes.byref(nb)) == 1
+    A3 = ids.IdsMatrix(ids.CSR, ids.F32, 100, 20, 0, 10, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                       ctypes.c_void_p(16))
+    assert L.ids_sketch_workspace_size(ctypes.byref(A3), ctypes.byref(cfg), ctypes.byref(nb)) == 2
+
+
+def test_tensor_rejects_bad_arguments_without_gpu():
+    L = ids.lib()
+    nb = ctypes.c_size_t(0)
+    dims = (ctypes.c_int64 * 3)(10, 10, 10)
+    p = ctypes.cast(dims, ctypes.c_void_p)
+    assert L.ids_tensor_workspace_size(3, p, 20, 5, 100, ctypes.byref(nb)) == 1   # Jlen not power of 2
+    assert L.ids_tensor_workspace_size(3, p, 20, 20, 64, ctypes.byref(nb)) == 1   # k >= R
+    assert L.ids_tensor_workspace_size(9, p, 20, 5, 64, ctypes.byref(nb)) == 1    # N > 8
+    assert L.ids_tensor_workspace_size(3, p, 20, 5, 8192, ctypes.byref(nb)) == 1  # Jlen > 4096
+
+
+def test_binding_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(ids.IdsError):
+        ids.id_select(torch.zeros(4, 8, dtype=torch.float64), 2)

@@ -1,0 +1,247 @@
+"""GPU parity of the matrix path (Algorithm 2 + projection + Algorithm 1)
+against the FP64 CPU oracle, through the C-ABI library."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ids = pytest.importorskip("paper_1901_10559_amd")
+
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def tie_aware_J(Jg, Jo, nu, rel=1e-12):
+    """J must agree; a first divergence is accepted only at a numerical tie of
+    the oracle's trailing norms (top two within `rel`)."""
+    Jg = np.asarray(Jg)
+    Jo = np.asarray(Jo)
+    if np.array_equal(Jg, Jo):
+        return True
+    t = int(np.argmax(Jg != Jo))
+    row = np.sort(nu[t][nu[t] >= 0])[::-1]
+    return len(row) > 1 and (row[0] - row[1]) <= rel * row[0]
+
+
+# ---------------------------------------------------------------------------
+# CountSketch
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n,L", [(1, 1, 1), (64, 3, 5), (1000, 257, 30), (4097, 130, 128), (3000, 1000, 480),
+                                   (2000, 1001, 37)])
+def test_countsketch_f64_bit_exact(m, n, L):
+    g = np.random.default_rng(m + n + L)
+    A = g.standard_normal((m, n))
+    Y = ids.id_sketch(dev(A), L, seed=3).cpu().numpy()
+    b, s = oracle.hash_maps(3, 0, m, L)
+    Yo = oracle.countsketch_dense(A, b, s, L)
+    # rows of a bucket are added in increasing row order on both sides
+    assert np.array_equal(Y, Yo)
+
+
+def test_countsketch_f64_strided_rows():
+    g = np.random.default_rng(1)
+    A = g.standard_normal((500, 77))
+    Ad = dev(np.zeros((500, 80)))[:, :77]
+    Ad.copy_(dev(A))
+    Y = ids.id_sketch(Ad, 40, seed=9).cpu().numpy()
+    b, s = oracle.hash_maps(9, 0, 500, 40)
+    assert np.array_equal(Y, oracle.countsketch_dense(A, b, s, 40))
+
+
+@pytest.mark.parametrize("n", [2000, 1003, 6])
+def test_countsketch_f32(n):
+    g = np.random.default_rng(n)
+    A = g.standard_normal((5000, n)).astype(np.float32)
+    Y = ids.id_sketch(dev(A), 480, seed=0).cpu().numpy()
+    b, s = oracle.hash_maps(0, 0, 5000, 480)
+    Yo = oracle.countsketch_dense(A.astype(np.float64), b, s, 480)
+    # FP32 accumulation of ~10 terms of size O(1): |error| <= cnt * 2^-24 * max|partial|
+    cnt = np.bincount(b, minlength=480).max()
+    tol = cnt * 2.0 ** -24 * 4 * max(1.0, np.abs(A).max()) * cnt
+    assert np.max(np.abs(Y - Yo)) <= tol
+
+
+def test_countsketch_bf16():
+    g = np.random.default_rng(2)
+    bits = synth.bf16_bits(g.standard_normal((1500, 300)))
+    A64 = synth.bf16_to_f64(bits)
+    At = dev(bits.view(np.int16)).view(torch.bfloat16)
+    Y = ids.id_sketch(At, 100, seed=4).cpu().numpy()
+    b, s = oracle.hash_maps(4, 0, 1500, 100)
+    Yo = oracle.countsketch_dense(A64, b, s, 100)
+    cnt = np.bincount(b, minlength=100).max()
+    assert np.max(np.abs(Y - Yo)) <= cnt * cnt * 2.0 ** -24 * 8
+
+
+def test_countsketch_integer_f32_exact():
+    g = np.random.default_rng(3)
+    A = g.integers(-100, 100, size=(3000, 512)).astype(np.float32)
+    Y = ids.id_sketch(dev(A), 64, seed=1).cpu().numpy()
+    b, s = oracle.hash_maps(1, 0, 3000, 64)
+    assert np.array_equal(Y.astype(np.float64), oracle.countsketch_dense(A, b, s, 64))
+
+
+def test_countsketch_fullrank_hash():
+    m, L = 700, 90
+    pi, x = synth.fullrank_perm(m, L, 2)
+    A = np.random.default_rng(4).standard_normal((m, 33))
+    Y = ids.id_sketch(dev(A), L, seed=2, fullrank=(dev(pi), dev(x))).cpu().numpy()
+    b = oracle.fullrank_buckets(pi, x, L)
+    _, s = oracle.hash_maps(2, 0, m, L)
+    assert np.array_equal(Y, oracle.countsketch_dense(A, b, s, L))
+
+
+@pytest.mark.parametrize("m,n,L", [(2000, 300, 40), (20000, 1500, 240), (777, 21000, 16)])
+def test_countsketch_csr(m, n, L):
+    rp, ci, v = synth.csr_zipf(m=m, n=n, seed=1, kmax=min(681, n), rank=5, nplant_rows=min(200, m),
+                               nplant_cols=min(100, n))
+    A = (dev(rp), dev(ci), dev(v), n)
+    Y = ids.id_sketch(A, L, seed=6).cpu().numpy()
+    b, s = oracle.hash_maps(6, 0, m, L)
+    Yo = oracle.countsketch_csr(rp, ci, v, n, b, s, L)
+    # FP64 atomics: order of additions differs; bound by count * eps * sum|terms|
+    absum = oracle.countsketch_csr(rp, ci, np.abs(v), n, b, np.ones_like(s), L)
+    assert np.all(np.abs(Y - Yo) <= 64 * 2.0 ** -52 * absum + 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# projection
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("l,q,n", [(30, 128, 1000), (120, 480, 2000), (1, 1, 1), (77, 33, 65), (64, 64, 64)])
+def test_projection_f64(l, q, n):
+    g = np.random.default_rng(l * q)
+    G = g.standard_normal((l, q))
+    Y1 = g.standard_normal((q, n))
+    Y = ids.id_project(dev(G), dev(Y1)).cpu().numpy()
+    Yo = oracle.gemm(G, Y1)
+    bound = q * 2.0 ** -52 * (np.abs(G) @ np.abs(Y1)) * 2
+    assert np.all(np.abs(Y - Yo) <= bound)
+
+
+def test_projection_integer_exact():
+    g = np.random.default_rng(8)
+    G = g.integers(-8, 8, size=(45, 200)).astype(np.float64)
+    Y1 = g.integers(-8, 8, size=(200, 333)).astype(np.float64)
+    assert np.array_equal(ids.id_project(dev(G), dev(Y1)).cpu().numpy(), oracle.gemm(G, Y1))
+    G32, Y32 = G.astype(np.float32), Y1.astype(np.float32)
+    assert np.array_equal(ids.id_project(dev(G32), dev(Y32)).cpu().numpy().astype(np.float64),
+                          oracle.gemm(G, Y1))
+
+
+def test_projection_f32():
+    g = np.random.default_rng(9)
+    G = g.standard_normal((120, 480)).astype(np.float32)
+    Y1 = g.standard_normal((480, 2000)).astype(np.float32)
+    Y = ids.id_project(dev(G), dev(Y1)).cpu().numpy()
+    Yo = oracle.gemm(G.astype(np.float64), Y1.astype(np.float64))
+    bound = 480 * 2.0 ** -23 * (np.abs(G.astype(np.float64)) @ np.abs(Y1.astype(np.float64)))
+    assert np.all(np.abs(Y - Yo) <= bound)
+
+
+# ---------------------------------------------------------------------------
+# select (Algorithm 1)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("l,n,k", [(30, 1000, 20), (12, 40, 5), (64, 64, 40), (120, 2000, 100), (60, 20000, 50),
+                                   (130, 700, 130), (300, 900, 64), (1500, 600, 50), (4096, 300, 30)])
+def test_select_f64(l, n, k):
+    g = np.random.default_rng(l + n + k)
+    Y = g.standard_normal((l, n)) * g.uniform(0.1, 10, n)[None, :]
+    J, P, keff = ids.id_select(dev(Y), k)
+    Jo, Po, ko, _, nu = oracle.cpqr_id(Y, k, trace=True)
+    assert int(keff.item()) == ko == k
+    Jg = J.cpu().numpy()
+    assert tie_aware_J(Jg, Jo, nu)
+    if np.array_equal(Jg, Jo):
+        Pg = P.cpu().numpy()
+        assert np.linalg.norm(Pg - Po) <= 1e-10 * np.linalg.norm(Po)
+        assert np.array_equal(Pg[:, Jg], np.eye(k))
+
+
+def test_select_column_major_f32_input():
+    g = np.random.default_rng(5)
+    Y = g.standard_normal((50, 300)).astype(np.float32)
+    Yc = dev(np.asfortranarray(Y).T.copy()).t()   # column-major l x n view
+    assert Yc.stride(0) == 1
+    J, P, keff = ids.id_select(Yc, 20)
+    Jo, Po, _, _, _ = oracle.cpqr_id(Y.astype(np.float64), 20)
+    assert np.array_equal(J.cpu().numpy(), Jo)
+    assert np.linalg.norm(P.cpu().numpy() - Po) <= 1e-10 * np.linalg.norm(Po)
+
+
+def test_select_rank_deficient():
+    g = np.random.default_rng(6)
+    Y = np.zeros((10, 40))
+    Y[:, [3, 17, 29]] = g.standard_normal((10, 3))
+    J, P, keff = ids.id_select(dev(Y), 6)
+    Jo, Po, ko, _, _ = oracle.cpqr_id(Y, 6)
+    assert int(keff.item()) == ko == 3
+    assert np.array_equal(J.cpu().numpy(), Jo)
+    np.testing.assert_allclose(P.cpu().numpy(), Po, rtol=0, atol=1e-12)
+
+
+def test_select_ties_lowest_index():
+    Y = np.zeros((4, 6))
+    Y[0, 1] = 1.0
+    Y[1, 3] = 1.0
+    Y[2, 5] = -1.0
+    J, _, keff = ids.id_select(dev(Y), 3)
+    assert list(J.cpu().numpy()) == [1, 3, 5]
+
+
+# ---------------------------------------------------------------------------
+# full pipeline
+# ---------------------------------------------------------------------------
+def test_matrix_id_config0_parity():
+    A = synth.config0(seed=0)
+    k, p = 20, 10
+    l1 = synth.default_l1(A.shape[0], k, p)
+    G = synth.gaussian(k + p, l1, seed=0)
+    r = ids.matrix_id(dev(A), k, l1, k + p, seed=0, G=dev(G))
+    o = oracle.matrix_id(A, k=k, l1=l1, seed=0, G=G, trace=True)
+    Jg = r["J"].cpu().numpy()
+    Pg = r["P"].cpu().numpy()
+    assert int(r["k_eff"].item()) == k
+    assert np.array_equal(Jg, o["J"])
+    assert np.linalg.norm(Pg - o["P"]) <= 1e-10 * np.linalg.norm(o["P"])
+    res_g = oracle.residual_fro(A, Jg, Pg)
+    res_o = oracle.residual_fro(A, o["J"], o["P"])
+    assert abs(res_g - res_o) <= 1e-10
+    assert np.array_equal(Pg[:, Jg], np.eye(k))
+
+
+def test_matrix_id_exact_rank():
+    A = synth.config0(seed=1, exact=True, m=2000, n=1000, k=20)
+    G = synth.gaussian(30, 128, seed=1)
+    r = ids.matrix_id(dev(A), 20, 128, 30, seed=1, G=dev(G))
+    Jg = r["J"].cpu().numpy()
+    Pg = r["P"].cpu().numpy()
+    assert oracle.residual_fro(A, Jg, Pg) < 1e-13
+    assert np.array_equal(Pg[:, Jg], np.eye(20))
+
+
+def test_matrix_id_no_projection_paper_exact():
+    # the paper's own Algorithm 2: CountSketch straight to L = K + 10 rows
+    A = synth.config0(seed=2, m=1500, n=400, k=15)
+    r = ids.matrix_id(dev(A), 15, 25, seed=2)
+    o = oracle.matrix_id(A, k=15, l1=25, seed=2, trace=True)
+    assert tie_aware_J(r["J"].cpu().numpy(), o["J"], o["nu"])
+    assert np.linalg.norm(r["P"].cpu().numpy() - o["P"]) <= 1e-10 * np.linalg.norm(o["P"])
+
+
+def test_matrix_id_csr_small():
+    rp, ci, v = synth.csr_zipf(m=20000, n=2000, seed=3, rank=20, nplant_rows=2000, nplant_cols=300)
+    k, l1 = 20, 120
+    G = synth.gaussian(k + 10, l1, seed=3)
+    r = ids.matrix_id((dev(rp), dev(ci), dev(v), 2000), k, l1, k + 10, seed=3, G=dev(G))
+    o = oracle.matrix_id(csr=(rp, ci, v), n=2000, k=k, l1=l1, seed=3, G=G, trace=True)
+    Jg = r["J"].cpu().numpy()
+    assert tie_aware_J(Jg, o["J"], o["nu"])
+    if np.array_equal(Jg, o["J"]):
+        assert np.linalg.norm(r["P"].cpu().numpy() - o["P"]) <= 1e-10 * np.linalg.norm(o["P"])

@@ -1,0 +1,77 @@
+"""GPU parity of the tensor path (Algorithm 3: TensorSketch by FFT in LDS,
+Algorithm 1, s-value update) against the FP64 CPU oracle (direct circular
+convolution), through the C-ABI library."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ids = pytest.importorskip("paper_1901_10559_amd")
+
+DEV = "cuda:0"
+
+
+def dev_cols(f):
+    """column-major device copy of an I x R factor"""
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(f).T)).to(DEV).t()
+
+
+@pytest.mark.parametrize("dims,R,Jlen", [((30, 25, 20), 40, 64), ((17, 9), 7, 16), ((40, 30, 20, 10), 33, 32),
+                                         ((100, 80, 60), 21, 128), ((300, 200, 100), 12, 512),
+                                         ((500, 400, 300), 9, 1024), ((600, 500, 400), 10, 2048),
+                                         ((2000, 2000, 2000), 6, 4096), ((64,), 5, 256)])
+def test_tensorsketch_matches_direct_convolution(dims, R, Jlen):
+    g = np.random.default_rng(sum(dims) + R + Jlen)
+    factors = [g.standard_normal((d, R)) for d in dims]
+    lam = g.uniform(0.5, 2.0, R)
+    r = ids.tensor_id([dev_cols(f) for f in factors], torch.from_numpy(lam).to(DEV), 2, Jlen, seed=11,
+                      return_Y=True)
+    Y = r["Y"].cpu().numpy()
+    maps = oracle.tensor_maps(11, dims, Jlen)
+    Yo = oracle.tensorsketch(factors, lam, maps, Jlen)
+    # FFT round-off: a few ulps times log2(J) of the l2 norm of each column
+    scale = np.linalg.norm(Yo, axis=0, keepdims=True)
+    assert np.max(np.abs(Y - Yo) / scale) <= 1e-13
+
+
+def test_tensorsketch_integer_inputs_exact_to_rounding():
+    g = np.random.default_rng(4)
+    dims, R, Jlen = (50, 40, 30), 8, 64
+    factors = [g.integers(-3, 4, size=(d, R)).astype(np.float64) for d in dims]
+    lam = np.ones(R)
+    r = ids.tensor_id([dev_cols(f) for f in factors], torch.from_numpy(lam).to(DEV), 2, Jlen, seed=2,
+                      return_Y=True)
+    Yo = oracle.tensorsketch(factors, lam, oracle.tensor_maps(2, dims, Jlen), Jlen)
+    # integer-valued exact result; the FFT path lands within 1e-9 of it
+    assert np.max(np.abs(r["Y"].cpu().numpy() - Yo)) <= 1e-9
+
+
+@pytest.mark.parametrize("dims,R,nbase,Jlen,k", [((60, 50, 40), 120, 8, 128, 8), ((200, 150, 100), 400, 20, 512, 20),
+                                                 ((300, 300, 300), 301, 30, 1024, 30)])
+def test_tensor_id_parity(dims, R, nbase, Jlen, k):
+    factors, lam, base_of = synth.cp_tensor(dims=dims, R=R, nbase=nbase, pert=1e-8, seed=R)
+    r = ids.tensor_id([dev_cols(f) for f in factors], torch.from_numpy(lam).to(DEV), k, Jlen, seed=3)
+    o = oracle.tensor_id(factors, lam, k=k, Jlen=Jlen, seed=3, trace=True)
+    J = r["J"].cpu().numpy()
+    assert int(r["k_eff"].item()) == o["k_eff"] == k
+    assert np.array_equal(J, o["J"])
+    P = r["P"].cpu().numpy()
+    assert np.linalg.norm(P - o["P"]) <= 1e-10 * np.linalg.norm(o["P"])
+    lh = r["lambda_hat"].cpu().numpy()
+    assert np.max(np.abs(lh - o["lambda_hat"]) / np.abs(o["lambda_hat"])) <= 1e-10
+    assert len(set(base_of[J])) == k   # one kept term per base cluster
+
+
+def test_tensor_id_duplicated_terms_closed_form():
+    factors, lam, base_of = synth.cp_tensor(dims=(40, 30, 20), R=60, nbase=5, pert=0.0, lam_range=(0.5, 2.0),
+                                            seed=7)
+    r = ids.tensor_id([dev_cols(f) for f in factors], torch.from_numpy(lam).to(DEV), 5, 64, seed=7)
+    J = r["J"].cpu().numpy()
+    lh = r["lambda_hat"].cpu().numpy()
+    assert sorted(base_of[J]) == [0, 1, 2, 3, 4]
+    for t, b in enumerate(base_of[J]):
+        np.testing.assert_allclose(lh[t], lam[base_of == b].sum(), rtol=1e-10)
