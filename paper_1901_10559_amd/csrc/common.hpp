@@ -57,6 +57,46 @@ __device__ __forceinline__ int wave_sum(int v) {
     return v;
 }
 
+// DPP-based FP64 wave64 sum (GFX9 DPP controls): pairwise, quad, half-row,
+// row, then row_bcast15 / row_bcast31 fold the four rows into lane 63, whose
+// value is broadcast.  Fixed tree, so the result is deterministic.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane63_f64(double v) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+template <int NV>
+__device__ __forceinline__ void wave_sum_dpp(double (&v)[NV]) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] += dpp_f64<0xB1, 0xf>(v[c]);  // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] += dpp_f64<0x4E, 0xf>(v[c]);  // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] += dpp_f64<0x141, 0xf>(v[c]); // row_half_mirror
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] += dpp_f64<0x140, 0xf>(v[c]); // row_mirror
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] += dpp_f64<0x142, 0xa>(v[c]); // row_bcast15 -> rows 1, 3
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] += dpp_f64<0x143, 0xc>(v[c]); // row_bcast31 -> rows 2, 3
+#pragma unroll
+    for (int c = 0; c < NV; ++c) v[c] = lane63_f64(v[c]);
+}
+
+__device__ __forceinline__ double wave_sum_dpp1(double x) {
+    double v[1] = {x};
+    wave_sum_dpp<1>(v);
+    return v[0];
+}
+
 // bf16 bits -> float
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) {
     return __uint_as_float(((uint32_t)b) << 16);

@@ -4,7 +4,8 @@
 // Design (bucket owner, no atomics for dense input):
 //   1. plan: every row i gets (h(i), D_ii) from the counter-based hash; a
 //      stable counting sort groups the signed row codes by bucket, rows of a
-//      bucket in increasing order (plan_count -> plan_scan -> plan_place).
+//      bucket in increasing order (plan_count -> plan_rowscan -> plan_offsets
+//      -> plan_place).
 //   2. dense gather: workgroup (panel, bucket) walks the rows of its bucket and
 //      accumulates them in registers, 16-byte loads per lane, several rows in
 //      flight, then writes its slice of Y1 once.  Every entry of Y1 is the sum
@@ -63,18 +64,41 @@ __global__ __launch_bounds__(64) void plan_count_kernel(PlanArgs a) {
     for (uint32_t b = lane; b < a.L; b += 64) a.seg[(int64_t)b * a.nseg + s] = hist[b];
 }
 
-// exclusive scan of the L x nseg count matrix in bucket-major order
-__global__ __launch_bounds__(1024) void plan_scan_kernel(PlanArgs a) {
+// Offsets of the bucket-major L x nseg count matrix, in two steps:
+//   plan_rowscan: one wave per bucket b, exclusive scan of row b over the
+//                 segments (in place) and the bucket total tot[b];
+//   plan_offsets: one workgroup, exclusive scan of the L totals -> off[b].
+// plan_place then places row i of segment s at off[b] + seg[b][s] + rank.
+__global__ __launch_bounds__(64) void plan_rowscan_kernel(PlanArgs a, int32_t* tot) {
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x;
+    int32_t* row = a.seg + (int64_t)b * a.nseg;
+    int32_t carry = 0;
+    for (int s0 = 0; s0 < a.nseg; s0 += 64) {
+        const int s = s0 + lane;
+        const int32_t v = s < a.nseg ? row[s] : 0;
+        int32_t x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (s < a.nseg) row[s] = carry + x - v;
+        carry += __shfl(x, 63, 64);
+    }
+    if (lane == 0) tot[b] = carry;
+}
+
+__global__ __launch_bounds__(1024) void plan_offsets_kernel(PlanArgs a, const int32_t* tot) {
     __shared__ int32_t part[1024];
-    const int64_t N = (int64_t)a.L * a.nseg;
     const int t = threadIdx.x;
-    const int64_t per = (N + 1023) / 1024;
-    const int64_t b0 = t * per, b1 = min(N, b0 + per);
-    int32_t s = 0;
-    for (int64_t q = b0; q < b1; ++q) s += a.seg[q];
-    part[t] = s;
+    const int64_t L = a.L;
+    const int64_t per = (L + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = min(L, b0 + per);
+    int32_t sum = 0;
+    for (int64_t q = b0; q < b1; ++q) sum += tot[q];
+    part[t] = sum;
     __syncthreads();
-    // Hillis-Steele inclusive scan over 1024 partials
     for (int o = 1; o < 1024; o <<= 1) {
         int32_t v = (t >= o) ? part[t - o] : 0;
         __syncthreads();
@@ -83,12 +107,10 @@ __global__ __launch_bounds__(1024) void plan_scan_kernel(PlanArgs a) {
     }
     int32_t run = (t == 0) ? 0 : part[t - 1];
     for (int64_t q = b0; q < b1; ++q) {
-        int32_t c = a.seg[q];
-        a.seg[q] = run;
-        if (q % a.nseg == 0) a.off[q / a.nseg] = run;
-        run += c;
+        a.off[q] = run;
+        run += tot[q];
     }
-    if (t == 0) a.off[a.L] = (int32_t)a.m;
+    if (t == 0) a.off[L] = (int32_t)a.m;
 }
 
 // one wave per segment: stable placement (rows of a bucket in increasing order)
@@ -96,7 +118,7 @@ __global__ __launch_bounds__(64) void plan_place_kernel(PlanArgs a) {
     extern __shared__ int32_t run[];
     const int s = blockIdx.x;
     const int lane = threadIdx.x;
-    for (uint32_t b = lane; b < a.L; b += 64) run[b] = a.seg[(int64_t)b * a.nseg + s];
+    for (uint32_t b = lane; b < a.L; b += 64) run[b] = a.off[b] + a.seg[(int64_t)b * a.nseg + s];
     __syncthreads();
     const int64_t r0 = (int64_t)s * a.seg_rows;
     const int64_t r1 = min(a.m, r0 + a.seg_rows);
@@ -140,7 +162,8 @@ ids_status plan_build(const PlanShape& ps, uint64_t key, const int64_t* fr_pi, c
     a.rows = pb.rows;
     size_t lds = sizeof(int32_t) * (size_t)ps.L;
     hipLaunchKernelGGL(plan_count_kernel, dim3(ps.nseg), dim3(64), lds, st, a);
-    hipLaunchKernelGGL(plan_scan_kernel, dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(plan_rowscan_kernel, dim3((unsigned)ps.L), dim3(64), 0, st, a, pb.tot);
+    hipLaunchKernelGGL(plan_offsets_kernel, dim3(1), dim3(1024), 0, st, a, (const int32_t*)pb.tot);
     hipLaunchKernelGGL(plan_place_kernel, dim3(ps.nseg), dim3(64), lds, st, a);
     return check_launch("countsketch plan");
 }
@@ -149,8 +172,9 @@ PlanShape plan_shape(int64_t m, int64_t L) {
     PlanShape ps;
     ps.m = m;
     ps.L = L;
-    // keep the L x nseg count matrix at most ~4M entries
-    int64_t seg = 1024;
+    // segments of 256 rows (4 chunks of 64 per wave); keep the L x nseg count
+    // matrix at most ~4M entries
+    int64_t seg = 256;
     int64_t need = (m * L + (int64_t(1) << 22) - 1) >> 22;
     if (need > seg) seg = need;
     seg = (seg + 63) / 64 * 64;
@@ -162,7 +186,7 @@ PlanShape plan_shape(int64_t m, int64_t L) {
 
 size_t plan_bytes(const PlanShape& ps) {
     return align256(sizeof(int32_t) * (size_t)ps.L * ps.nseg) + align256(sizeof(int32_t) * (ps.L + 1)) +
-           align256(sizeof(int32_t) * (size_t)ps.m);
+           align256(sizeof(int32_t) * (size_t)ps.m) + align256(sizeof(int32_t) * (size_t)ps.L);
 }
 
 PlanBufs plan_carve(const PlanShape& ps, char*& p) {
@@ -173,6 +197,8 @@ PlanBufs plan_carve(const PlanShape& ps, char*& p) {
     p += align256(sizeof(int32_t) * (ps.L + 1));
     pb.rows = (int32_t*)p;
     p += align256(sizeof(int32_t) * (size_t)ps.m);
+    pb.tot = (int32_t*)p;
+    p += align256(sizeof(int32_t) * (size_t)ps.L);
     return pb;
 }
 

@@ -31,9 +31,10 @@ struct PlanShape {
     int32_t seg_rows, nseg;
 };
 struct PlanBufs {
-    int32_t* seg;
-    int32_t* off;
-    int32_t* rows;
+    int32_t* seg;   // L x nseg counts, then per-bucket exclusive scans
+    int32_t* off;   // L + 1 bucket offsets into rows
+    int32_t* rows;  // m signed row codes grouped by bucket
+    int32_t* tot;   // L bucket totals
 };
 PlanShape plan_shape(int64_t m, int64_t L);
 size_t plan_bytes(const PlanShape& ps);
