@@ -156,6 +156,38 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
                      int64_t* k_eff, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Batched mixed-precision matrix ID (hierarchical-matrix style block
+ * compression): nprob independent dense problems A_p (m_p x n_p, BF16,
+ * row-major, stored back to back in A: A_p starts at element
+ * sum_{q<p} m_q n_q), each through Algorithm 2 with a Gaussian second stage and
+ * Algorithm 1 with target rank k:
+ *   CountSketch of A_p to l1_p = min(m_p, l1max) rows, stream (seed, tag = p),
+ *   FP32 accumulation; the sketch is split into BF16 hi + lo parts and
+ *   projected by G[:, 0:l1_p] (G: l x l1max row-major BF16, shared by all
+ *   problems) on the BF16 matrix cores with FP32 accumulation; column-pivoted
+ *   QR of the l x n_p projection with FP32 data and FP64 norms recomputed
+ *   every step; FP64 back-substitution for P_p.
+ * Limits: 1 <= k <= l <= 122, l <= l1max <= 512, l <= m_p <= 4096,
+ * k < n_p <= 1024.
+ *   ids_batched_plan  uploads per-problem descriptors (offsets, largest-first
+ *                     schedule) into a caller-owned device buffer of
+ *                     ids_batched_plan_size() bytes; synchronises `stream`
+ *                     once; returns the workspace size id_batched needs.
+ *                     m, n are HOST arrays.
+ *   id_batched        asynchronous; J int64[nprob*k] (J_p at p*k, -1 past
+ *                     k_eff_p), P double[k * sum n_p] (P_p, k x n_p row-major,
+ *                     at k * sum_{q<p} n_q), k_eff int64[nprob].  The plan, m
+ *                     and n must be the ones the plan was built from.
+ */
+ids_status ids_batched_plan_size(int64_t nprob, size_t* bytes);
+ids_status ids_batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, int64_t k, int64_t l,
+                            int64_t l1max, void* plan, size_t plan_bytes, size_t* ws_bytes,
+                            void* stream);
+ids_status id_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* plan, int64_t k,
+                      int64_t l, int64_t l1max, uint64_t seed, const void* A, const void* G,
+                      int64_t* J, double* P, int64_t* k_eff, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Stage timing.  While enabled, every call records a pair of HIP events on its
  * stream around each stage ("plan", "countsketch", "project", "cpqr", "trsm",
  * "tensorsketch", "lambda_hat").  ids_profile_read waits for the recorded

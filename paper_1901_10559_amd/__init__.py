@@ -21,7 +21,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["lib", "lib_path", "profile_enable", "profile_read", "profile_reset", "id_sketch", "id_project", "id_select", "matrix_id", "tensor_id",
+__all__ = ["lib", "lib_path", "BatchedPlan", "batched_plan", "id_batched", "profile_enable", "profile_read", "profile_reset", "id_sketch", "id_project", "id_select", "matrix_id", "tensor_id",
            "IdsError", "F64", "F32", "BF16", "HASH_FULLRANK", "EXPORTED"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -32,7 +32,8 @@ DENSE, CSR = 0, 1
 HASH_FULLRANK = 1
 
 EXPORTED = ["ids_sketch_workspace_size", "id_sketch", "id_project", "ids_select_workspace_size",
-            "id_select", "ids_tensor_workspace_size", "tensor_id", "ids_profile_enable", "ids_profile_read",
+            "id_select", "ids_tensor_workspace_size", "tensor_id", "ids_batched_plan_size", "ids_batched_plan",
+            "id_batched", "ids_profile_enable", "ids_profile_read",
             "ids_profile_reset", "ids_status_string", "ids_last_error"]
 
 c_i64 = ctypes.c_int64
@@ -76,6 +77,12 @@ def lib():
         L.ids_tensor_workspace_size.argtypes = [c_i32, c_vp, c_i64, c_i64, c_i64, P(c_sz)]
         L.tensor_id.argtypes = [c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_u64, c_vp, c_vp, c_vp,
                                 c_vp, c_vp, c_vp, c_sz, c_vp]
+        L.ids_batched_plan_size.argtypes = [c_i64, P(c_sz)]
+        L.ids_batched_plan.argtypes = [c_i64, c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_sz, P(c_sz), c_vp]
+        L.id_batched.argtypes = [c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_u64, c_vp, c_vp, c_vp, c_vp, c_vp,
+                                 c_vp, c_sz, c_vp]
+        for fn in ("ids_batched_plan_size", "ids_batched_plan", "id_batched"):
+            getattr(L, fn).restype = c_i32
         L.ids_profile_enable.argtypes = [c_i32]
         L.ids_profile_enable.restype = None
         L.ids_profile_read.argtypes = [ctypes.c_char_p, P(ctypes.c_double), P(c_i64)]
@@ -266,4 +273,66 @@ def tensor_id(factors, lam, k: int, Jlen: int, *, seed: int = 0, return_Y: bool 
     out = dict(J=J, P=P, lambda_hat=lh, k_eff=keff)
     if Y is not None:
         out["Y"] = Y.t()
+    return out
+
+
+class BatchedPlan:
+    """Device-resident descriptors of a batch of problems (see ids_batched_plan)."""
+
+    def __init__(self, m, n, k, l, l1max, buf, ws_bytes):
+        import numpy as np
+        self.m = np.ascontiguousarray(m, dtype=np.int64)
+        self.n = np.ascontiguousarray(n, dtype=np.int64)
+        self.k, self.l, self.l1max = int(k), int(l), int(l1max)
+        self.buf = buf
+        self.ws_bytes = int(ws_bytes)
+        self.nprob = int(self.m.shape[0])
+        self.a_off = np.concatenate([[0], np.cumsum(self.m * self.n)])
+        self.p_off = np.concatenate([[0], np.cumsum(self.k * self.n)])
+        self.y_off = np.concatenate([[0], np.cumsum(self.l * self.n)])
+
+
+def batched_plan(m, n, k: int, l: int, l1max: int, device="cuda:0", stream=None) -> BatchedPlan:
+    import numpy as np
+    torch = _torch()
+    m = np.ascontiguousarray(m, dtype=np.int64)
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    nprob = m.shape[0]
+    nb = c_sz(0)
+    _check(lib().ids_batched_plan_size(nprob, ctypes.byref(nb)), "ids_batched_plan_size")
+    buf = torch.empty(nb.value, dtype=torch.uint8, device=device)
+    wsb = c_sz(0)
+    _check(lib().ids_batched_plan(nprob, c_vp(m.ctypes.data), c_vp(n.ctypes.data), k, l, l1max,
+                                  c_vp(buf.data_ptr()), nb.value, ctypes.byref(wsb), _stream(torch, stream)),
+           "ids_batched_plan")
+    return BatchedPlan(m, n, k, l, l1max, buf, wsb.value)
+
+
+def id_batched(plan: BatchedPlan, A, G, seed: int = 0, stream=None, return_Y: bool = False):
+    """Batched mixed-precision ID.  A: flat bfloat16 device tensor of all A_p
+    (row-major, back to back); G: l x l1max bfloat16.  Returns dict with J
+    (nprob x k), P (flat float64, P_p = P[p_off[p]:p_off[p+1]].view(k, n_p)),
+    k_eff (nprob) and, if asked, Y (flat float32, Y_p column-major l x n_p)."""
+    torch = _torch()
+    if A.dtype != torch.bfloat16 or G.dtype != torch.bfloat16:
+        raise IdsError("A and G must be bfloat16")
+    if tuple(G.shape) != (plan.l, plan.l1max) or not G.is_contiguous():
+        raise IdsError("G must be a contiguous l x l1max tensor")
+    if A.numel() < int(plan.a_off[-1]):
+        raise IdsError("A is smaller than the batch")
+    dev = A.device
+    ws, wsb = _workspace(torch, plan.ws_bytes, dev, stream)
+    J = torch.empty((plan.nprob, plan.k), dtype=torch.int64, device=dev)
+    P = torch.empty(int(plan.p_off[-1]), dtype=torch.float64, device=dev)
+    keff = torch.empty(plan.nprob, dtype=torch.int64, device=dev)
+    _check(lib().id_batched(plan.nprob, c_vp(plan.m.ctypes.data), c_vp(plan.n.ctypes.data),
+                            c_vp(plan.buf.data_ptr()), plan.k, plan.l, plan.l1max, seed, c_vp(A.data_ptr()),
+                            c_vp(G.data_ptr()), c_vp(J.data_ptr()), c_vp(P.data_ptr()), c_vp(keff.data_ptr()),
+                            c_vp(ws[1]), wsb, _stream(torch, stream)), "id_batched")
+    out = dict(J=J, P=P, k_eff=keff)
+    if return_Y:
+        # Y is the first region of the workspace (FP32, Y_p column-major l x n_p)
+        ny = int(plan.y_off[-1])
+        start = ws[1] - ws[0].data_ptr()
+        out["Y"] = ws[0][start:start + 4 * ny].view(torch.float32).clone()
     return out

@@ -394,4 +394,58 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
     return ids::lambda_hat(k, R, P, J, k_eff, lambda, lambda_hat, st);
 }
 
+// ---------------------------------------------------------------------------
+// batched
+// ---------------------------------------------------------------------------
+static ids_status validate_batched(int64_t nprob, const int64_t* m, const int64_t* n, int64_t k, int64_t l,
+                                   int64_t l1max) {
+    if (nprob < 1 || nprob >= (int64_t(1) << 31)) return fail(IDS_EINVAL, "nprob must be in [1, 2^31)");
+    if (!m || !n) return fail(IDS_EINVAL, "m and n must be non-NULL host arrays");
+    if (l < 1 || l > 122) return fail(IDS_EINVAL, "batched: l must be in [1, 122]");
+    if (k < 1 || k > l) return fail(IDS_EINVAL, "batched: k must be in [1, l]");
+    if (l1max < l || l1max > 512) return fail(IDS_EINVAL, "batched: l1max must be in [l, 512]");
+    for (int64_t q = 0; q < nprob; ++q) {
+        if (m[q] < l || m[q] > 4096)
+            return fail(IDS_EINVAL, "batched: problem " + std::to_string(q) + ": m must be in [l, 4096]");
+        if (n[q] <= k || n[q] >= (int64_t(1) << 31))
+            return fail(IDS_EINVAL, "batched: problem " + std::to_string(q) + ": n must exceed k");
+        if (n[q] > 1024) return fail(IDS_EINVAL, "batched: problem " + std::to_string(q) + ": n must be <= 1024");
+    }
+    return IDS_OK;
+}
+
+ids_status ids_batched_plan_size(int64_t nprob, size_t* bytes) {
+    g_err.clear();
+    if (!bytes || nprob < 1) return fail(IDS_EINVAL, "bytes must be non-NULL and nprob >= 1");
+    return batched_plan_bytes(nprob, bytes);
+}
+
+ids_status ids_batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, int64_t k, int64_t l, int64_t l1max,
+                            void* plan, size_t plan_bytes, size_t* ws_bytes, void* stream) {
+    g_err.clear();
+    ids_status s = validate_batched(nprob, m, n, k, l, l1max);
+    if (s) return s;
+    if (!plan || !ws_bytes) return fail(IDS_EINVAL, "plan and ws_bytes must be non-NULL");
+    return batched_plan(nprob, m, n, k, l, l1max, plan, plan_bytes, ws_bytes, (hipStream_t)stream);
+}
+
+ids_status id_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* plan, int64_t k, int64_t l,
+                      int64_t l1max, uint64_t seed, const void* A, const void* G, int64_t* J, double* P,
+                      int64_t* k_eff, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    ids_status s = validate_batched(nprob, m, n, k, l, l1max);
+    if (s) return s;
+    if (!plan || !A || !G || !J || !P || !k_eff) return fail(IDS_EINVAL, "plan, A, G, J, P and k_eff required");
+    int64_t y_elems = 0, r_elems = 0;
+    for (int64_t q = 0; q < nprob; ++q) {
+        y_elems += l * n[q];
+        r_elems += n[q];
+    }
+    const size_t need = align256(sizeof(float) * (size_t)y_elems) + align256(sizeof(double) * (size_t)r_elems * k) +
+                        align256(sizeof(int32_t) * (size_t)r_elems) + align256(sizeof(double) * (size_t)nprob * k);
+    if ((s = check_ws(ws, ws_bytes, need))) return s;
+    return batched_run(nprob, plan, k, l, l1max, seed, A, G, J, P, k_eff, ws, ws_bytes, y_elems, r_elems,
+                       (hipStream_t)stream);
+}
+
 }  // extern "C"

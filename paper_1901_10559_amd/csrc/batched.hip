@@ -1,0 +1,614 @@
+// Batched mixed-precision matrix ID: thousands of independent dense problems
+// A_p (m_p x n_p, BF16, row-major), each through Algorithm 2 with a Gaussian
+// second stage and Algorithm 1:
+//   batched_sketch_kernel  one workgroup per problem (largest first): the
+//       CountSketch plan in LDS, then per 256-column panel and per group of 32
+//       buckets, Y1 rows summed in FP32 from 16-byte BF16 loads, split into
+//       BF16 hi + lo, and multiplied by the BF16 Gaussian G on the matrix cores
+//       (v_mfma_f32_16x16x32_bf16, FP32 accumulation): Y_p = G (S A_p) stays in
+//       registers per panel and is written once (FP32, column-major).
+//   batched_cpqr_kernel    one workgroup per problem: column j of Y_p in lane
+//       j (rows 0..RL-1 in LDS, rows RL.. in registers), FP32 data and
+//       Householder updates, trailing norms recomputed in FP64 each step.
+//   batched_trsm_kernel    one workgroup per problem: R11 in LDS, FP64
+//       back-substitution, 16 lanes per column; writes P_p.
+// Problem p draws its CountSketch from the stream (seed, tag = p) and uses
+// the first l1_p = min(m_p, l1max) columns of the shared l x l1max G.
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ids {
+
+typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+struct BProb {
+    int32_t m, n, l1, pad;
+    int64_t a_off;  // element offset of A_p
+    int64_t y_off;  // element offset of Y_p (l x n FP32, column-major)
+    int64_t p_off;  // element offset of P_p (k x n FP64, row-major)
+    int64_t r_off;  // element offset of Rt_p (n x k FP64) and pos_p (n int32)
+};
+
+struct BatchHdr {
+    int64_t nprob, k, l, l1max;
+    int64_t y_elems, r_elems;
+    int32_t max_n, max_m;
+};
+
+// plan buffer layout (device): BatchHdr | BProb[nprob] | order_sketch[nprob] | order_cpqr[nprob]
+static size_t plan_layout(int64_t nprob, size_t* off_prob, size_t* off_o1, size_t* off_o2) {
+    size_t o = align256(sizeof(BatchHdr));
+    *off_prob = o;
+    o += align256(sizeof(BProb) * (size_t)nprob);
+    *off_o1 = o;
+    o += align256(sizeof(int32_t) * (size_t)nprob);
+    *off_o2 = o;
+    o += align256(sizeof(int32_t) * (size_t)nprob);
+    return o;
+}
+
+struct BatchArgs {
+    const BProb* prob;
+    const int32_t* order;
+    int64_t nprob, k, l, l1max;
+    uint64_t seed;
+    const uint16_t* A;
+    const uint16_t* G;  // l x l1max BF16
+    float* Y;
+    double* Rt;
+    int32_t* pos;
+    double* beta;       // nprob x k: R[t][J[t]] in FP64
+    int64_t* J;
+    double* P;
+    int64_t* keff;
+};
+
+// ---------------------------------------------------------------------------
+// K1: CountSketch + projection
+// ---------------------------------------------------------------------------
+constexpr int BS_THREADS = 1024;
+constexpr int BS_PANEL = 256;   // columns per panel
+constexpr int BS_BG = 32;       // buckets per group (= MFMA K)
+constexpr int BS_LMAX = 128;    // padded sketch height (l <= 128)
+constexpr int BS_MMAX = 4096;   // rows per problem
+constexpr int BS_L1MAX = 512;   // buckets per problem
+
+__device__ __forceinline__ uint16_t f2bf_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a) {
+    __shared__ int32_t cnt[BS_L1MAX + 1];
+    __shared__ int32_t off[BS_L1MAX + 1];
+    __shared__ int32_t rows[BS_MMAX];
+    __shared__ uint16_t Y1h[BS_PANEL][BS_BG + 8];  // transposed: [column][bucket]
+    __shared__ uint16_t Y1l[BS_PANEL][BS_BG + 8];
+    __shared__ uint16_t Gs[BS_LMAX][BS_BG + 8];
+
+    const int p = a.order[blockIdx.x];
+    const BProb pr = a.prob[p];
+    const int m = pr.m, n = pr.n, L1 = pr.l1;
+    const int l = (int)a.l;
+    const int tid = threadIdx.x;
+    const uint64_t key = stream_key(a.seed, (uint64_t)p);
+
+    // ---- plan: bucket counts, offsets, rows grouped by bucket (ascending)
+    for (int b = tid; b <= L1; b += BS_THREADS) cnt[b] = 0;
+    __syncthreads();
+    for (int i = tid; i < m; i += BS_THREADS) {
+        uint32_t b;
+        bool neg;
+        hash_row(key, i, (uint32_t)L1, b, neg);
+        atomicAdd(&cnt[b], 1);
+    }
+    __syncthreads();
+    if (tid < 64) {
+        // exclusive scan of L1 counts by one wave
+        int carry = 0;
+        for (int b0 = 0; b0 < L1; b0 += 64) {
+            const int b = b0 + tid;
+            const int v = b < L1 ? cnt[b] : 0;
+            int x = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o, 64);
+                if (tid >= o) x += y;
+            }
+            if (b < L1) off[b] = carry + x - v;
+            carry += __shfl(x, 63, 64);
+        }
+        if (tid == 0) off[L1] = carry;
+    }
+    __syncthreads();
+    for (int b = tid; b < L1; b += BS_THREADS) cnt[b] = off[b];
+    __syncthreads();
+    for (int i = tid; i < m; i += BS_THREADS) {
+        uint32_t b;
+        bool neg;
+        hash_row(key, i, (uint32_t)L1, b, neg);
+        const int q = atomicAdd(&cnt[b], 1);
+        rows[q] = encode_row(i, neg);
+    }
+    __syncthreads();
+    // rows of a bucket in increasing row order (insertion sort, buckets are short)
+    for (int b = tid; b < L1; b += BS_THREADS) {
+        for (int q = off[b] + 1; q < off[b + 1]; ++q) {
+            const int32_t c = rows[q];
+            const int32_t ci = c >= 0 ? c : -c - 1;
+            int r = q - 1;
+            while (r >= off[b]) {
+                const int32_t d = rows[r];
+                const int32_t di = d >= 0 ? d : -d - 1;
+                if (di <= ci) break;
+                rows[r + 1] = d;
+                --r;
+            }
+            rows[r + 1] = c;
+        }
+    }
+    __syncthreads();
+
+    const int w = tid >> 6, lane = tid & 63;
+    const int rt = w & 7;           // row tile (16 rows of Y)
+    const int ct0 = (w >> 3) * 8;   // first of 8 column tiles
+    const int bl = tid >> 5;        // bucket within group (gather phase)
+    const int ch = tid & 31;        // 8-column chunk within panel (gather phase)
+    const uint16_t* Ap = a.A + pr.a_off;
+    float* Yp = a.Y + pr.y_off;
+
+    for (int c0 = 0; c0 < n; c0 += BS_PANEL) {
+        v4f32 acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = v4f32{0.f, 0.f, 0.f, 0.f};
+        for (int g0 = 0; g0 < L1; g0 += BS_BG) {
+            // gather: Y1[b][c0 + 8ch .. +8] for b = g0 + bl
+            {
+                const int b = g0 + bl;
+                const int cc = c0 + 8 * ch;
+                float s[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) s[e] = 0.f;
+                if (b < L1 && cc < n) {
+                    const bool full = cc + 8 <= n && (n % 8) == 0 && (pr.a_off % 8) == 0;
+                    for (int q = off[b]; q < off[b + 1]; ++q) {
+                        const int32_t code = rows[q];
+                        const int64_t i = code >= 0 ? code : -(int64_t)code - 1;
+                        const uint16_t* rowp = Ap + i * n + cc;
+                        float x[8];
+                        if (full) {
+                            const uint4 raw = *reinterpret_cast<const uint4*>(rowp);
+                            x[0] = bf16_to_f32(raw.x & 0xffff); x[1] = bf16_to_f32(raw.x >> 16);
+                            x[2] = bf16_to_f32(raw.y & 0xffff); x[3] = bf16_to_f32(raw.y >> 16);
+                            x[4] = bf16_to_f32(raw.z & 0xffff); x[5] = bf16_to_f32(raw.z >> 16);
+                            x[6] = bf16_to_f32(raw.w & 0xffff); x[7] = bf16_to_f32(raw.w >> 16);
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) x[e] = (cc + e < n) ? bf16_to_f32(rowp[e]) : 0.f;
+                        }
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) s[e] = code < 0 ? s[e] - x[e] : s[e] + x[e];
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint16_t h = f2bf_rne(s[e]);
+                    const float hf = bf16_to_f32(h);
+                    Y1h[8 * ch + e][bl] = h;
+                    Y1l[8 * ch + e][bl] = f2bf_rne(s[e] - hf);
+                }
+            }
+            // G[:, g0 .. g0 + 32] -> LDS (rows >= l and columns >= L1 are zero)
+            for (int e = tid; e < BS_LMAX * BS_BG; e += BS_THREADS) {
+                const int r = e / BS_BG, c = e % BS_BG;
+                Gs[r][c] = (r < l && g0 + c < L1) ? a.G[(int64_t)r * a.l1max + g0 + c] : (uint16_t)0;
+            }
+            __syncthreads();
+            // Y(rows rt*16.., cols ct*16..) += G tile (16 x 32) * Y1 (32 x 16), hi and lo
+            {
+                v8bf16 av;
+                const uint16_t* gsrc = &Gs[rt * 16 + (lane & 15)][8 * (lane >> 4)];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) av[e] = __builtin_bit_cast(__bf16, gsrc[e]);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int col = (ct0 + q) * 16 + (lane & 15);
+                    v8bf16 bh, blo;
+                    const uint16_t* hs = &Y1h[col][8 * (lane >> 4)];
+                    const uint16_t* ls = &Y1l[col][8 * (lane >> 4)];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        bh[e] = __builtin_bit_cast(__bf16, hs[e]);
+                        blo[e] = __builtin_bit_cast(__bf16, ls[e]);
+                    }
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bh, acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, blo, acc[q], 0, 0, 0);
+                }
+            }
+            __syncthreads();
+        }
+        // write the panel of Y_p (column-major, leading dimension l)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int col = c0 + (ct0 + q) * 16 + (lane & 15);
+            if (col >= n) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rt * 16 + 4 * (lane >> 4) + r;
+                if (row < l) Yp[(int64_t)col * l + row] = acc[q][r];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K2: CPQR, FP32 data, FP64 norms
+// ---------------------------------------------------------------------------
+constexpr int BC_THREADS = 1024;
+constexpr int BC_RL = 38;   // rows held in LDS (the first ones: frozen after step RL)
+constexpr int BC_RR = 84;   // rows held in registers (RL + RR >= l)
+static_assert(BC_RL + BC_RR >= 122 && BC_RL + BC_RR <= BS_LMAX, "batched CPQR row split");
+
+template <int N>
+__device__ __forceinline__ double tree_sum_d(double (&s)[N]) {
+#pragma unroll
+    for (int h = N / 2; h > 0; h >>= 1)
+#pragma unroll
+        for (int q = 0; q < h; ++q) s[q] += s[q + h];
+    return s[0];
+}
+
+__global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
+    extern __shared__ float ylds[];           // BC_RL x BC_THREADS
+    __shared__ double xb[BS_LMAX];            // pivot column (FP64 copy)
+    __shared__ float vb[BS_LMAX];             // reflector (FP32)
+    __shared__ double s_nu[16];
+    __shared__ int s_j[16];
+    __shared__ int s_wj;
+    __shared__ double s_wnu;
+
+    const int p = a.order[blockIdx.x];
+    const BProb pr = a.prob[p];
+    const int n = pr.n;
+    const int l = (int)a.l, k = (int)a.k;
+    const int j = threadIdx.x;
+    const int lane = j & 63, w = j >> 6;
+    bool alive = j < n;
+    const float* Yp = a.Y + pr.y_off;
+
+    float y[BC_RR];
+    {
+        const int jc = min(j, n - 1);
+#pragma unroll
+        for (int r = 0; r < BC_RL; ++r) {
+            const float v = Yp[(int64_t)jc * l + min(r, l - 1)];
+            ylds[r * BC_THREADS + j] = (alive && r < l) ? v : 0.f;
+        }
+#pragma unroll
+        for (int r = 0; r < BC_RR; ++r) {
+            const int i = BC_RL + r;
+            const float v = Yp[(int64_t)jc * l + min(i, l - 1)];
+            y[r] = (alive && i < l) ? v : 0.f;
+        }
+    }
+    auto norm_from = [&](int t0) -> double {  // FP64 sum of squares over rows i >= t0
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        if (t0 < BC_RL) {
+            for (int r = t0; r < BC_RL; ++r) {
+                const double v = (double)ylds[r * BC_THREADS + j];
+                s[r & 3] = fma(v, v, s[r & 3]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < BC_RR; c += 8) {
+            if (BC_RL + c + 8 > t0) {
+#pragma unroll
+                for (int r = c; r < c + 8 && r < BC_RR; ++r) {
+                    const double v = (BC_RL + r >= t0) ? (double)y[r] : 0.0;
+                    s[r & 3] = fma(v, v, s[r & 3]);
+                }
+            }
+        }
+        return tree_sum_d<4>(s);
+    };
+    double nu = norm_from(0);
+    int keff = k;
+    const int64_t roff = pr.r_off;
+    if (alive) a.pos[roff + j] = -1;
+
+    for (int t = 0; t < k; ++t) {
+        // ---- argmax of (nu, j) over the workgroup
+        double wn = alive ? nu : -1.0;
+        int wjj = alive ? j : INT32_MAX;
+        {
+            double m2 = wn;
+            int q2 = wjj;
+            // wave argmax (largest nu, smallest j)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const double on = __shfl_xor(m2, o, 64);
+                const int oj = __shfl_xor(q2, o, 64);
+                if (on > m2 || (on == m2 && oj < q2)) {
+                    m2 = on;
+                    q2 = oj;
+                }
+            }
+            if (lane == 0) {
+                s_nu[w] = m2;
+                s_j[w] = q2;
+            }
+        }
+        __syncthreads();
+        if (j == 0) {
+            double bn = s_nu[0];
+            int bj = s_j[0];
+            for (int q = 1; q < BC_THREADS / 64; ++q)
+                if (s_nu[q] > bn || (s_nu[q] == bn && s_j[q] < bj)) {
+                    bn = s_nu[q];
+                    bj = s_j[q];
+                }
+            s_wnu = bn;
+            s_wj = bj;
+        }
+        __syncthreads();
+        const double wnu = s_wnu;
+        const int wj = s_wj;
+        if (wj == INT32_MAX || !(wnu > 0.0)) {
+            keff = t;
+            break;
+        }
+        // ---- the pivot column to LDS (FP64), by its owner lane
+        if (j == wj) {
+            for (int i = 0; i < BC_RL; ++i) xb[i] = (double)ylds[i * BC_THREADS + j];
+#pragma unroll
+            for (int r = 0; r < BC_RR; ++r)
+                if (BC_RL + r < BS_LMAX) xb[BC_RL + r] = (double)y[r];
+        }
+        __syncthreads();
+        // ---- Householder reflector in FP64 (every wave, same bits)
+        double sig2 = 0.0;
+        for (int i = t + 1 + lane; i < l; i += 64) sig2 = fma(xb[i], xb[i], sig2);
+        sig2 = wave_sum_dpp1(sig2);
+        const double alpha = xb[t];
+        double tau, beta, scal;
+        if (sig2 == 0.0) {
+            tau = 0.0;
+            beta = alpha;
+            scal = 0.0;
+        } else {
+            const double nrm = sqrt(alpha * alpha + sig2);
+            beta = (alpha >= 0.0) ? -nrm : nrm;
+            tau = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        if (j < BS_LMAX) vb[j] = (j < t || j >= l) ? 0.f : (j == t ? 1.f : (float)(xb[j] * scal));
+        __syncthreads();
+        // ---- apply H to the live columns (FP32 dot and update)
+        if (alive) {
+            float d[4] = {0.f, 0.f, 0.f, 0.f};
+            if (t < BC_RL)
+                for (int r = t; r < BC_RL; ++r) d[r & 3] = fmaf(vb[r], ylds[r * BC_THREADS + j], d[r & 3]);
+#pragma unroll
+            for (int c = 0; c < BC_RR; c += 8)
+                if (BC_RL + c + 8 > t) {
+#pragma unroll
+                    for (int r = c; r < c + 8 && r < BC_RR; ++r)
+                        if (BC_RL + r < BS_LMAX) d[r & 3] = fmaf(vb[BC_RL + r], y[r], d[r & 3]);
+                }
+            const float dt = ((d[0] + d[1]) + (d[2] + d[3])) * (float)tau;
+            if (t < BC_RL)
+                for (int r = t; r < BC_RL; ++r) ylds[r * BC_THREADS + j] = fmaf(-dt, vb[r], ylds[r * BC_THREADS + j]);
+#pragma unroll
+            for (int c = 0; c < BC_RR; c += 8)
+                if (BC_RL + c + 8 > t) {
+#pragma unroll
+                    for (int r = c; r < c + 8 && r < BC_RR; ++r)
+                        if (BC_RL + r < BS_LMAX) y[r] = fmaf(-dt, vb[BC_RL + r], y[r]);
+                }
+            if (j == wj) {
+                alive = false;
+                a.pos[roff + j] = t;
+            }
+        }
+        if (j == 0) {
+            a.J[(int64_t)p * k + t] = wj;
+            a.beta[(int64_t)p * k + t] = beta;
+        }
+        nu = norm_from(t + 1);
+        __syncthreads();
+    }
+    // top keff rows of every column -> Rt (FP64); the pivots' diagonal is beta
+    if (j < n) {
+        double* Rj = a.Rt + roff * (int64_t)k + (int64_t)j * k;
+        for (int i = 0; i < min(keff, BC_RL); ++i) Rj[i] = (double)ylds[i * BC_THREADS + j];
+#pragma unroll
+        for (int r = 0; r < BC_RR; ++r)
+            if (BC_RL + r < keff) Rj[BC_RL + r] = (double)y[r];
+    }
+    if (j == 0) {
+        a.keff[p] = keff;
+        for (int t = keff; t < k; ++t) a.J[(int64_t)p * k + t] = -1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K3: interpolation matrix per problem (FP64)
+// ---------------------------------------------------------------------------
+template <int KS>
+__global__ __launch_bounds__(1024) void batched_trsm_kernel(BatchArgs a) {
+    extern __shared__ double R11s[];  // keff x keff
+    const int p = blockIdx.x;
+    const BProb pr = a.prob[p];
+    const int n = pr.n;
+    const int k = (int)a.k;
+    const int keff = (int)a.keff[p];
+    const int64_t* J = a.J + (int64_t)p * k;
+    const double* bt = a.beta + (int64_t)p * k;
+    const double* Rt = a.Rt + pr.r_off * (int64_t)k;
+    const int32_t* pos = a.pos + pr.r_off;
+    double* P = a.P + pr.p_off;
+    for (int e = threadIdx.x; e < keff * keff; e += 1024) {
+        const int r = e / keff, c = e % keff;
+        R11s[e] = (r < c) ? Rt[J[c] * k + r] : (r == c ? bt[r] : 0.0);
+    }
+    __syncthreads();
+    const int q = threadIdx.x & 15;
+    for (int j = threadIdx.x >> 4; j < n; j += 64) {
+        const int pj = pos[j];
+        if (pj >= 0) {
+            for (int r = q; r < k; r += 16) P[(int64_t)r * n + j] = (r == pj) ? 1.0 : 0.0;
+            continue;
+        }
+        double b[KS], x[KS];
+#pragma unroll
+        for (int sl = 0; sl < KS; ++sl) {
+            const int c = 16 * sl + q;
+            b[sl] = (c < keff) ? Rt[(int64_t)j * k + c] : 0.0;
+            x[sl] = 0.0;
+        }
+        for (int r = keff - 1; r >= 0; --r) {
+            double part = 0.0;
+#pragma unroll
+            for (int sl = 0; sl < KS; ++sl) {
+                const int c = 16 * sl + q;
+                if (c == r) part = b[sl];
+                if (c > r && c < keff) part = fma(-R11s[r * keff + c], x[sl], part);
+            }
+            part += dpp_f64<0xB1, 0xf>(part);
+            part += dpp_f64<0x4E, 0xf>(part);
+            part += dpp_f64<0x141, 0xf>(part);
+            part += dpp_f64<0x140, 0xf>(part);
+            const double xr = part / R11s[r * keff + r];
+            if (q == (r & 15)) {
+#pragma unroll
+                for (int sl = 0; sl < KS; ++sl)
+                    if (sl == (r >> 4)) x[sl] = xr;
+            }
+            if (q == 0) P[(int64_t)r * n + j] = xr;
+        }
+        for (int r = keff + q; r < k; r += 16) P[(int64_t)r * n + j] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+ids_status batched_plan_bytes(int64_t nprob, size_t* bytes) {
+    size_t a, b, c;
+    *bytes = plan_layout(nprob, &a, &b, &c);
+    return IDS_OK;
+}
+
+ids_status batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, int64_t k, int64_t l, int64_t l1max,
+                        void* plan, size_t plan_bytes, size_t* ws_bytes, hipStream_t st) {
+    size_t op, o1, o2;
+    const size_t need = plan_layout(nprob, &op, &o1, &o2);
+    if (plan_bytes < need) {
+        set_error("plan buffer too small: need " + std::to_string(need) + " bytes");
+        return IDS_EWORKSPACE;
+    }
+    std::vector<char> host(need, 0);
+    BatchHdr* h = (BatchHdr*)host.data();
+    BProb* pr = (BProb*)(host.data() + op);
+    int32_t* ord1 = (int32_t*)(host.data() + o1);
+    int32_t* ord2 = (int32_t*)(host.data() + o2);
+    int64_t a_off = 0, y_off = 0, p_off = 0, r_off = 0;
+    int32_t max_n = 0, max_m = 0;
+    for (int64_t q = 0; q < nprob; ++q) {
+        pr[q].m = (int32_t)m[q];
+        pr[q].n = (int32_t)n[q];
+        pr[q].l1 = (int32_t)std::min<int64_t>(m[q], l1max);
+        pr[q].pad = 0;
+        pr[q].a_off = a_off;
+        pr[q].y_off = y_off;
+        pr[q].p_off = p_off;
+        pr[q].r_off = r_off;
+        a_off += m[q] * n[q];
+        y_off += l * n[q];
+        p_off += k * n[q];
+        r_off += n[q];
+        max_n = std::max<int32_t>(max_n, (int32_t)n[q]);
+        max_m = std::max<int32_t>(max_m, (int32_t)m[q]);
+    }
+    h->nprob = nprob;
+    h->k = k;
+    h->l = l;
+    h->l1max = l1max;
+    h->y_elems = y_off;
+    h->r_elems = r_off;
+    h->max_n = max_n;
+    h->max_m = max_m;
+    // largest problems first (longest-processing-time order for the dispatcher)
+    std::vector<int32_t> idx(nprob);
+    for (int64_t q = 0; q < nprob; ++q) idx[q] = (int32_t)q;
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return m[x] * n[x] > m[y] * n[y]; });
+    std::copy(idx.begin(), idx.end(), ord1);
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return n[x] > n[y]; });
+    std::copy(idx.begin(), idx.end(), ord2);
+    if (hipMemcpyAsync(plan, host.data(), need, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("batched plan upload failed");
+        return IDS_EHIP;
+    }
+    // workspace: Y (FP32), Rt (FP64 n x k per problem), pos (int32), beta (FP64)
+    *ws_bytes = align256(sizeof(float) * (size_t)y_off) + align256(sizeof(double) * (size_t)r_off * k) +
+                align256(sizeof(int32_t) * (size_t)r_off) + align256(sizeof(double) * (size_t)nprob * k);
+    return IDS_OK;
+}
+
+ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, int64_t l1max, uint64_t seed,
+                       const void* A, const void* G, int64_t* J, double* P, int64_t* keff, void* ws,
+                       size_t ws_bytes, int64_t y_elems, int64_t r_elems, hipStream_t st) {
+    size_t op, o1, o2;
+    plan_layout(nprob, &op, &o1, &o2);
+    BatchArgs a;
+    a.prob = (const BProb*)((const char*)plan + op);
+    a.nprob = nprob;
+    a.k = k;
+    a.l = l;
+    a.l1max = l1max;
+    a.seed = seed;
+    a.A = (const uint16_t*)A;
+    a.G = (const uint16_t*)G;
+    char* p = (char*)ws;
+    a.Y = (float*)p;
+    p += align256(sizeof(float) * (size_t)y_elems);
+    a.Rt = (double*)p;
+    p += align256(sizeof(double) * (size_t)r_elems * k);
+    a.pos = (int32_t*)p;
+    p += align256(sizeof(int32_t) * (size_t)r_elems);
+    a.beta = (double*)p;
+    a.J = J;
+    a.P = P;
+    a.keff = keff;
+    (void)ws_bytes;
+    {
+        ProfScope ps(PK_CS, st);
+        a.order = (const int32_t*)((const char*)plan + o1);
+        hipLaunchKernelGGL(batched_sketch_kernel, dim3((unsigned)nprob), dim3(BS_THREADS), 0, st, a);
+    }
+    {
+        ProfScope ps(PK_CPQR, st);
+        a.order = (const int32_t*)((const char*)plan + o2);
+        hipLaunchKernelGGL(batched_cpqr_kernel, dim3((unsigned)nprob), dim3(BC_THREADS),
+                           sizeof(float) * BC_RL * BC_THREADS, st, a);
+    }
+    {
+        ProfScope ps(PK_TRSM, st);
+        const size_t lds = sizeof(double) * (size_t)k * k;
+        if (k <= 32)
+            hipLaunchKernelGGL(batched_trsm_kernel<2>, dim3((unsigned)nprob), dim3(1024), lds, st, a);
+        else if (k <= 64)
+            hipLaunchKernelGGL(batched_trsm_kernel<4>, dim3((unsigned)nprob), dim3(1024), lds, st, a);
+        else
+            hipLaunchKernelGGL(batched_trsm_kernel<8>, dim3((unsigned)nprob), dim3(1024), lds, st, a);
+    }
+    return check_launch("batched ID");
+}
+
+}  // namespace ids

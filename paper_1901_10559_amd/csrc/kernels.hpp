@@ -66,6 +66,14 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
 ids_status lambda_hat(int64_t k, int64_t n, const double* P, const int64_t* J, const int64_t* keff,
                       const double* lambda, double* lhat, hipStream_t st);
 
+// ---- batched mixed-precision ID --------------------------------------------
+ids_status batched_plan_bytes(int64_t nprob, size_t* bytes);
+ids_status batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, int64_t k, int64_t l, int64_t l1max,
+                        void* plan, size_t plan_bytes, size_t* ws_bytes, hipStream_t st);
+ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, int64_t l1max, uint64_t seed,
+                       const void* A, const void* G, int64_t* J, double* P, int64_t* keff, void* ws,
+                       size_t ws_bytes, int64_t y_elems, int64_t r_elems, hipStream_t st);
+
 // ---- TensorSketch -------------------------------------------------------------
 ids_status tensorsketch(int32_t N, const int64_t* dims, int64_t R, const double* const* factors,
                         const int64_t* ld, const double* lambda, int64_t Jlen, const PlanBufs* plans,
