@@ -9,6 +9,12 @@ to k = 100 skeleton columns and the FP64 interpolation matrix.
 Prints one JSON line.  `value` is IDs per second; the roofline object is for
 the dominant kernel (the CountSketch pass over A, HBM-bound); cpu_baseline is
 the FP64 CPU oracle timed on this host.
+
+The same line carries a "batched" object: 4096 independent BF16 problems
+(m ~ logU[256, 4096], n ~ logU[128, 1024], sigma_i = exp(-i/8), k = 111,
+l = 121, l1 = min(m, 496)) through the batched mixed-precision path, in IDs/s,
+beside plain per-problem FP64 IDs on the same GPU and the residual ratio to the
+FP64 oracle on the same BF16 inputs.
 """
 from __future__ import annotations
 
@@ -49,6 +55,103 @@ def workload(seed: int = 0):
     l1 = synth.default_l1(M, K, P)
     G = synth.gaussian(K + P, l1, seed=seed).astype(np.float32)
     return np.asarray(A), G, l1
+
+
+NB, KB, LB, L1B = 4096, 111, 121, 496
+
+
+def batched_workload(seed: int = 0):
+    import numpy as np
+
+    import synth
+    base = os.path.join(cache_dir(), f"batched_{NB}_seed{seed}_v2")
+    if os.path.exists(base + "_A.npy"):
+        A = np.load(base + "_A.npy", mmap_mode="r")
+        m = np.load(base + "_m.npy")
+        n = np.load(base + "_n.npy")
+    else:
+        workers = max(1, min(16, os.cpu_count() or 1))
+        print(f"[bench] generating {NB} BF16 problems ({workers} processes)", flush=True)
+        m, n, A = synth.batched_inputs(NB, seed, workers=workers)
+        for suffix, arr in (("_m", m), ("_n", n), ("_A", A)):
+            np.save(base + suffix + ".tmp.npy", arr)
+            os.replace(base + suffix + ".tmp.npy", base + suffix + ".npy")
+    Gb = synth.bf16_bits(synth.gaussian(LB, L1B, seed=seed))
+    return m, n, np.asarray(A), Gb
+
+
+def run_batched(ids, torch, np, m, n, Abits, Gb, steps: int, check: bool):
+    """Batched BF16/FP32 IDs/s, plain per-problem FP64 IDs/s, residual ratios."""
+    import oracle
+    import synth
+    dev = torch.device("cuda:0")
+    At = torch.from_numpy(Abits.view(np.int16)).to(dev).view(torch.bfloat16)
+    Gt = torch.from_numpy(Gb.view(np.int16)).to(dev).view(torch.bfloat16)
+    plan = ids.batched_plan(m, n, KB, LB, L1B)
+    for _ in range(2):
+        out = ids.id_batched(plan, At, Gt, seed=0)
+    torch.cuda.synchronize()
+    ids.profile_reset()
+    ids.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        out = ids.id_batched(plan, At, Gt, seed=0)
+    e1.record()
+    torch.cuda.synchronize()
+    ids.profile_enable(False)
+    ms = e0.elapsed_time(e1) / steps
+    st = {}
+    for sname, key in (("countsketch", "sketch_project"), ("cpqr", "cpqr"), ("trsm", "trsm")):
+        t, c = ids.profile_read(sname)
+        st[key] = t / max(c, 1)
+    ids.profile_reset()
+    sk_bytes = int((m * n).sum()) * 2 + int(n.sum()) * LB * 4      # read A (BF16), write Y (FP32)
+    res = {"value": NB / (ms / 1e3), "unit": "IDs/s", "ms_per_batch": ms, "problems": NB,
+           "workload": f"{NB} problems, m~logU[256,4096], n~logU[128,1024], sigma_i=exp(-i/8), "
+                       f"k={KB}, l={LB}, l1=min(m,{L1B}), A in bf16",
+           "precision": {"countsketch": "bf16 in, f32 accumulate", "projection": "bf16 hi+lo MFMA, f32 acc",
+                         "cpqr": "f32 data, f64 norms", "solve": "f64"},
+           "stages_ms": st,
+           "sketch_roofline": {"bound": "hbm", "achieved": sk_bytes / (st["sketch_project"] / 1e3) / 1e9,
+                               "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                               "frac": sk_bytes / (st["sketch_project"] / 1e3) / 1e9 / HBM_PEAK_GBPS,
+                               "algorithmic_bytes": sk_bytes}}
+    # plain per-problem FP64 on the same GPU: the single-problem FP64 path, one
+    # problem after another, on the first 128 problems (inputs resident)
+    nfp = 128
+    a_off = np.concatenate([[0], np.cumsum(m * n)])
+    G64 = torch.from_numpy(synth.bf16_to_f64(Gb)).to(dev)
+    A64 = [torch.from_numpy(synth.bf16_to_f64(Abits[a_off[p]:a_off[p + 1]]).reshape(m[p], n[p])).to(dev)
+           for p in range(nfp)]
+    Gs = [G64[:, :min(int(m[p]), L1B)].contiguous() for p in range(nfp)]
+    for p in range(4):
+        ids.matrix_id(A64[p], KB, min(int(m[p]), L1B), LB, seed=0, tag=p, G=Gs[p])
+    torch.cuda.synchronize()
+    e0.record()
+    for p in range(nfp):
+        ids.matrix_id(A64[p], KB, min(int(m[p]), L1B), LB, seed=0, tag=p, G=Gs[p])
+    e1.record()
+    torch.cuda.synchronize()
+    fp_ms = e0.elapsed_time(e1)
+    res["fp64_per_problem"] = {"value": nfp / (fp_ms / 1e3), "unit": "IDs/s",
+                               "sample": f"first {nfp} problems, one FP64 ID call each (id_sketch + id_select)"}
+    res["speedup_vs_fp64"] = res["value"] / res["fp64_per_problem"]["value"]
+    if check:
+        J = out["J"].cpu().numpy()
+        P = out["P"].cpu().numpy()
+        ratios = []
+        for p in range(0, NB, NB // 24):
+            A64n = synth.bf16_to_f64(Abits[a_off[p]:a_off[p + 1]]).reshape(m[p], n[p])
+            l1 = min(int(m[p]), L1B)
+            o = oracle.matrix_id(A64n, k=KB, l1=l1, seed=0, tag=p, G=synth.bf16_to_f64(Gb)[:, :l1])
+            Pp = P[plan.p_off[p]:plan.p_off[p + 1]].reshape(KB, n[p])
+            ratios.append(oracle.residual_fro(A64n, J[p], Pp) / oracle.residual_fro(A64n, o["J"], o["P"]))
+        res["residual_ratio_vs_oracle"] = {"median": float(np.median(ratios)), "max": float(np.max(ratios)),
+                                           "sample": len(ratios),
+                                           "note": "FP64 oracle on the same BF16 inputs and BF16 G"}
+    return res
 
 
 def source_hash(path: str) -> str:
@@ -95,6 +198,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the residual comparison with the oracle")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-precision workload")
+    ap.add_argument("--batched-steps", type=int, default=10)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -104,11 +209,15 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    # all inputs are generated before the GPU is touched
+    A, G, l1 = workload()
+    batch = None if args.no_batched else batched_workload()
+
     import torch
 
     import paper_1901_10559_amd as ids
 
-    A, G, l1 = workload()
     dev = torch.device("cuda:0")
     At = torch.from_numpy(np.ascontiguousarray(A)).to(dev)
     Gt = torch.from_numpy(G).to(dev)
@@ -192,6 +301,9 @@ def main():
         res_o = oracle.residual_fro(A64, oracle_out["J"], oracle_out["P"])
         out["residual"] = {"gpu": res_g, "oracle_f64": res_o, "ratio": res_g / res_o,
                            "J_overlap": int(len(set(Jg.tolist()) & set(oracle_out["J"].tolist())))}
+    if batch is not None:
+        print("[bench] batched workload", flush=True)
+        out["batched"] = run_batched(ids, torch, np, *batch, steps=args.batched_steps, check=not args.no_check)
     print(json.dumps(out), flush=True)
 
 

@@ -402,7 +402,7 @@ static ids_status validate_batched(int64_t nprob, const int64_t* m, const int64_
     if (nprob < 1 || nprob >= (int64_t(1) << 31)) return fail(IDS_EINVAL, "nprob must be in [1, 2^31)");
     if (!m || !n) return fail(IDS_EINVAL, "m and n must be non-NULL host arrays");
     if (l < 1 || l > 122) return fail(IDS_EINVAL, "batched: l must be in [1, 122]");
-    if (k < 1 || k > l) return fail(IDS_EINVAL, "batched: k must be in [1, l]");
+    if (k < 1 || k > l) return fail(IDS_EINVAL, "batched: k must be in [1, l]");  // l <= 122 < 128
     if (l1max < l || l1max > 512) return fail(IDS_EINVAL, "batched: l1max must be in [l, 512]");
     for (int64_t q = 0; q < nprob; ++q) {
         if (m[q] < l || m[q] > 4096)

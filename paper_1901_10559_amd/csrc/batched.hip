@@ -70,8 +70,8 @@ struct BatchArgs {
 // ---------------------------------------------------------------------------
 // K1: CountSketch + projection
 // ---------------------------------------------------------------------------
-constexpr int BS_THREADS = 1024;
-constexpr int BS_PANEL = 256;   // columns per panel
+constexpr int BS_THREADS = 512;  // two problems per CU (LDS and registers allow it)
+constexpr int BS_PANEL = 128;   // columns per panel
 constexpr int BS_BG = 32;       // buckets per group (= MFMA K)
 constexpr int BS_LMAX = 128;    // padded sketch height (l <= 128)
 constexpr int BS_MMAX = 4096;   // rows per problem
@@ -87,9 +87,11 @@ __global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a)
     __shared__ int32_t cnt[BS_L1MAX + 1];
     __shared__ int32_t off[BS_L1MAX + 1];
     __shared__ int32_t rows[BS_MMAX];
-    __shared__ uint16_t Y1h[BS_PANEL][BS_BG + 8];  // transposed: [column][bucket]
-    __shared__ uint16_t Y1l[BS_PANEL][BS_BG + 8];
-    __shared__ uint16_t Gs[BS_LMAX][BS_BG + 8];
+    // transposed sketch tile [column][bucket]; rows of 40 entries (80 bytes,
+    // a multiple of 16) so each MFMA operand is one 16-byte LDS read
+    __shared__ __attribute__((aligned(16))) uint16_t Y1h[BS_PANEL][BS_BG + 8];
+    __shared__ __attribute__((aligned(16))) uint16_t Y1l[BS_PANEL][BS_BG + 8];
+    __shared__ __attribute__((aligned(16))) uint16_t Gs[BS_LMAX][BS_BG + 8];
 
     const int p = a.order[blockIdx.x];
     const BProb pr = a.prob[p];
@@ -155,10 +157,10 @@ __global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a)
     __syncthreads();
 
     const int w = tid >> 6, lane = tid & 63;
-    const int rt = w & 7;           // row tile (16 rows of Y)
-    const int ct0 = (w >> 3) * 8;   // first of 8 column tiles
-    const int bl = tid >> 5;        // bucket within group (gather phase)
-    const int ch = tid & 31;        // 8-column chunk within panel (gather phase)
+    const int rt = w;               // row tile (16 rows of Y), 8 waves = 128 rows
+    const int ct0 = 0;              // 8 column tiles = the 128-column panel
+    const int bl = tid >> 4;        // bucket within group (gather phase)
+    const int ch = tid & 15;        // 8-column chunk within panel (gather phase)
     const uint16_t* Ap = a.A + pr.a_off;
     float* Yp = a.Y + pr.y_off;
 
@@ -176,7 +178,31 @@ __global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a)
                 for (int e = 0; e < 8; ++e) s[e] = 0.f;
                 if (b < L1 && cc < n) {
                     const bool full = cc + 8 <= n && (n % 8) == 0 && (pr.a_off % 8) == 0;
-                    for (int q = off[b]; q < off[b + 1]; ++q) {
+                    int q = off[b];
+                    const int qe = off[b + 1];
+                    if (full) {
+                        // four rows in flight, then added in increasing row order
+                        for (; q + 4 <= qe; q += 4) {
+                            uint4 raw[4];
+                            int32_t code[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                code[u] = rows[q + u];
+                                const int64_t i = code[u] >= 0 ? code[u] : -(int64_t)code[u] - 1;
+                                raw[u] = *reinterpret_cast<const uint4*>(Ap + i * n + cc);
+                            }
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const uint32_t wv[4] = {raw[u].x, raw[u].y, raw[u].z, raw[u].w};
+#pragma unroll
+                                for (int e = 0; e < 8; ++e) {
+                                    const float xe = bf16_to_f32((uint16_t)(wv[e >> 1] >> (16 * (e & 1))));
+                                    s[e] = code[u] < 0 ? s[e] - xe : s[e] + xe;
+                                }
+                            }
+                        }
+                    }
+                    for (; q < qe; ++q) {
                         const int32_t code = rows[q];
                         const int64_t i = code >= 0 ? code : -(int64_t)code - 1;
                         const uint16_t* rowp = Ap + i * n + cc;
@@ -211,21 +237,15 @@ __global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a)
             __syncthreads();
             // Y(rows rt*16.., cols ct*16..) += G tile (16 x 32) * Y1 (32 x 16), hi and lo
             {
-                v8bf16 av;
-                const uint16_t* gsrc = &Gs[rt * 16 + (lane & 15)][8 * (lane >> 4)];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) av[e] = __builtin_bit_cast(__bf16, gsrc[e]);
+                const v8bf16 av =
+                    __builtin_bit_cast(v8bf16, *reinterpret_cast<const uint4*>(&Gs[rt * 16 + (lane & 15)][8 * (lane >> 4)]));
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const int col = (ct0 + q) * 16 + (lane & 15);
-                    v8bf16 bh, blo;
-                    const uint16_t* hs = &Y1h[col][8 * (lane >> 4)];
-                    const uint16_t* ls = &Y1l[col][8 * (lane >> 4)];
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        bh[e] = __builtin_bit_cast(__bf16, hs[e]);
-                        blo[e] = __builtin_bit_cast(__bf16, ls[e]);
-                    }
+                    const v8bf16 bh =
+                        __builtin_bit_cast(v8bf16, *reinterpret_cast<const uint4*>(&Y1h[col][8 * (lane >> 4)]));
+                    const v8bf16 blo =
+                        __builtin_bit_cast(v8bf16, *reinterpret_cast<const uint4*>(&Y1l[col][8 * (lane >> 4)]));
                     acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bh, acc[q], 0, 0, 0);
                     acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, blo, acc[q], 0, 0, 0);
                 }
@@ -254,6 +274,38 @@ constexpr int BC_RL = 38;   // rows held in LDS (the first ones: frozen after st
 constexpr int BC_RR = 84;   // rows held in registers (RL + RR >= l)
 static_assert(BC_RL + BC_RR >= 122 && BC_RL + BC_RR <= BS_LMAX, "batched CPQR row split");
 
+// wave argmax of (nu, j): DPP max tree for nu, then DPP min tree over the j
+// of the lanes holding the maximum; both fold into lane 63 and are broadcast.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dppk_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(v), __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dppk_i32(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, ROW_MASK, 0xf, false);
+}
+__device__ __forceinline__ void wave_argmax_dpp(double& nu, int& j) {
+    double m = nu;
+    m = fmax(m, dppk_f64<0xB1, 0xf>(m));
+    m = fmax(m, dppk_f64<0x4E, 0xf>(m));
+    m = fmax(m, dppk_f64<0x141, 0xf>(m));
+    m = fmax(m, dppk_f64<0x140, 0xf>(m));
+    m = fmax(m, dppk_f64<0x142, 0xa>(m));
+    m = fmax(m, dppk_f64<0x143, 0xc>(m));
+    m = lane63_f64(m);
+    int q = (nu == m) ? j : INT32_MAX;
+    q = min(q, dppk_i32<0xB1, 0xf>(q));
+    q = min(q, dppk_i32<0x4E, 0xf>(q));
+    q = min(q, dppk_i32<0x141, 0xf>(q));
+    q = min(q, dppk_i32<0x140, 0xf>(q));
+    q = min(q, dppk_i32<0x142, 0xa>(q));
+    q = min(q, dppk_i32<0x143, 0xc>(q));
+    nu = m;
+    j = __builtin_amdgcn_readlane(q, 63);
+}
+
 template <int N>
 __device__ __forceinline__ double tree_sum_d(double (&s)[N]) {
 #pragma unroll
@@ -265,12 +317,10 @@ __device__ __forceinline__ double tree_sum_d(double (&s)[N]) {
 
 __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
     extern __shared__ float ylds[];           // BC_RL x BC_THREADS
-    __shared__ double xb[BS_LMAX];            // pivot column (FP64 copy)
+    __shared__ __attribute__((aligned(16))) float xf[BS_LMAX];  // pivot column (FP32)
     __shared__ float vb[BS_LMAX];             // reflector (FP32)
     __shared__ double s_nu[16];
     __shared__ int s_j[16];
-    __shared__ int s_wj;
-    __shared__ double s_wnu;
 
     const int p = a.order[blockIdx.x];
     const BProb pr = a.prob[p];
@@ -278,6 +328,7 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
     const int l = (int)a.l, k = (int)a.k;
     const int j = threadIdx.x;
     const int lane = j & 63, w = j >> 6;
+    const bool wave_live = w * 64 < n;        // waves past the last column skip column work
     bool alive = j < n;
     const float* Yp = a.Y + pr.y_off;
 
@@ -316,65 +367,52 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
         }
         return tree_sum_d<4>(s);
     };
-    double nu = norm_from(0);
+    double nu = wave_live ? norm_from(0) : 0.0;
     int keff = k;
     const int64_t roff = pr.r_off;
     if (alive) a.pos[roff + j] = -1;
 
     for (int t = 0; t < k; ++t) {
-        // ---- argmax of (nu, j) over the workgroup
-        double wn = alive ? nu : -1.0;
-        int wjj = alive ? j : INT32_MAX;
+        // ---- argmax of (nu, j): per wave, then across waves by every wave
         {
-            double m2 = wn;
-            int q2 = wjj;
-            // wave argmax (largest nu, smallest j)
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const double on = __shfl_xor(m2, o, 64);
-                const int oj = __shfl_xor(q2, o, 64);
-                if (on > m2 || (on == m2 && oj < q2)) {
-                    m2 = on;
-                    q2 = oj;
-                }
-            }
+            double m2 = alive ? nu : -1.0;
+            int q2 = alive ? j : INT32_MAX;
+            wave_argmax_dpp(m2, q2);
             if (lane == 0) {
                 s_nu[w] = m2;
                 s_j[w] = q2;
             }
         }
         __syncthreads();
-        if (j == 0) {
-            double bn = s_nu[0];
-            int bj = s_j[0];
-            for (int q = 1; q < BC_THREADS / 64; ++q)
-                if (s_nu[q] > bn || (s_nu[q] == bn && s_j[q] < bj)) {
-                    bn = s_nu[q];
-                    bj = s_j[q];
-                }
-            s_wnu = bn;
-            s_wj = bj;
+        double wnu;
+        int wj;
+        {
+            double m2 = (lane < BC_THREADS / 64) ? s_nu[lane] : -1.0;
+            int q2 = (lane < BC_THREADS / 64) ? s_j[lane] : INT32_MAX;
+            wave_argmax_dpp(m2, q2);
+            wnu = m2;
+            wj = q2;
         }
-        __syncthreads();
-        const double wnu = s_wnu;
-        const int wj = s_wj;
         if (wj == INT32_MAX || !(wnu > 0.0)) {
             keff = t;
             break;
         }
-        // ---- the pivot column to LDS (FP64), by its owner lane
+        // ---- pivot column to LDS: rows in registers by the owner lane, rows in
+        //      LDS copied by BC_RL threads
         if (j == wj) {
-            for (int i = 0; i < BC_RL; ++i) xb[i] = (double)ylds[i * BC_THREADS + j];
 #pragma unroll
-            for (int r = 0; r < BC_RR; ++r)
-                if (BC_RL + r < BS_LMAX) xb[BC_RL + r] = (double)y[r];
+            for (int r = 0; r < BC_RR; ++r) xf[BC_RL + r] = y[r];
         }
+        if (j < BC_RL) xf[j] = ylds[j * BC_THREADS + wj];
         __syncthreads();
         // ---- Householder reflector in FP64 (every wave, same bits)
         double sig2 = 0.0;
-        for (int i = t + 1 + lane; i < l; i += 64) sig2 = fma(xb[i], xb[i], sig2);
+        for (int i = t + 1 + lane; i < l; i += 64) {
+            const double xi = (double)xf[i];
+            sig2 = fma(xi, xi, sig2);
+        }
         sig2 = wave_sum_dpp1(sig2);
-        const double alpha = xb[t];
+        const double alpha = (double)xf[t];
         double tau, beta, scal;
         if (sig2 == 0.0) {
             tau = 0.0;
@@ -386,40 +424,43 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
             tau = (beta - alpha) / beta;
             scal = 1.0 / (alpha - beta);
         }
-        if (j < BS_LMAX) vb[j] = (j < t || j >= l) ? 0.f : (j == t ? 1.f : (float)(xb[j] * scal));
+        if (j < BS_LMAX) vb[j] = (j < t || j >= l) ? 0.f : (j == t ? 1.f : (float)((double)xf[j] * scal));
         __syncthreads();
-        // ---- apply H to the live columns (FP32 dot and update)
-        if (alive) {
-            float d[4] = {0.f, 0.f, 0.f, 0.f};
-            if (t < BC_RL)
-                for (int r = t; r < BC_RL; ++r) d[r & 3] = fmaf(vb[r], ylds[r * BC_THREADS + j], d[r & 3]);
+        // ---- apply H to the live columns (FP32 dot and update), new norms
+        if (wave_live) {
+            if (alive) {
+                float d[4] = {0.f, 0.f, 0.f, 0.f};
+                if (t < BC_RL)
+                    for (int r = t; r < BC_RL; ++r) d[r & 3] = fmaf(vb[r], ylds[r * BC_THREADS + j], d[r & 3]);
 #pragma unroll
-            for (int c = 0; c < BC_RR; c += 8)
-                if (BC_RL + c + 8 > t) {
+                for (int c = 0; c < BC_RR; c += 8)
+                    if (BC_RL + c + 8 > t) {
 #pragma unroll
-                    for (int r = c; r < c + 8 && r < BC_RR; ++r)
-                        if (BC_RL + r < BS_LMAX) d[r & 3] = fmaf(vb[BC_RL + r], y[r], d[r & 3]);
+                        for (int r = c; r < c + 8 && r < BC_RR; ++r)
+                            if (BC_RL + r < BS_LMAX) d[r & 3] = fmaf(vb[BC_RL + r], y[r], d[r & 3]);
+                    }
+                const float dt = ((d[0] + d[1]) + (d[2] + d[3])) * (float)tau;
+                if (t < BC_RL)
+                    for (int r = t; r < BC_RL; ++r)
+                        ylds[r * BC_THREADS + j] = fmaf(-dt, vb[r], ylds[r * BC_THREADS + j]);
+#pragma unroll
+                for (int c = 0; c < BC_RR; c += 8)
+                    if (BC_RL + c + 8 > t) {
+#pragma unroll
+                        for (int r = c; r < c + 8 && r < BC_RR; ++r)
+                            if (BC_RL + r < BS_LMAX) y[r] = fmaf(-dt, vb[BC_RL + r], y[r]);
+                    }
+                if (j == wj) {
+                    alive = false;
+                    a.pos[roff + j] = t;
                 }
-            const float dt = ((d[0] + d[1]) + (d[2] + d[3])) * (float)tau;
-            if (t < BC_RL)
-                for (int r = t; r < BC_RL; ++r) ylds[r * BC_THREADS + j] = fmaf(-dt, vb[r], ylds[r * BC_THREADS + j]);
-#pragma unroll
-            for (int c = 0; c < BC_RR; c += 8)
-                if (BC_RL + c + 8 > t) {
-#pragma unroll
-                    for (int r = c; r < c + 8 && r < BC_RR; ++r)
-                        if (BC_RL + r < BS_LMAX) y[r] = fmaf(-dt, vb[BC_RL + r], y[r]);
-                }
-            if (j == wj) {
-                alive = false;
-                a.pos[roff + j] = t;
             }
+            nu = norm_from(t + 1);
         }
         if (j == 0) {
             a.J[(int64_t)p * k + t] = wj;
             a.beta[(int64_t)p * k + t] = beta;
         }
-        nu = norm_from(t + 1);
         __syncthreads();
     }
     // top keff rows of every column -> Rt (FP64); the pivots' diagonal is beta
@@ -439,9 +480,12 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
 // ---------------------------------------------------------------------------
 // K3: interpolation matrix per problem (FP64)
 // ---------------------------------------------------------------------------
-template <int KS>
+constexpr int BT_COLS = 64;
+// Column-block back-substitution: X (keff x 64 columns) starts as R12's block;
+// for r = keff-1 .. 0 every thread recomputes x_r = X[r][c] / R11[r][r] for its
+// column and removes R11[i][r] x_r from its rows i < r; one barrier per r.
 __global__ __launch_bounds__(1024) void batched_trsm_kernel(BatchArgs a) {
-    extern __shared__ double R11s[];  // keff x keff
+    extern __shared__ double sm3[];
     const int p = blockIdx.x;
     const BProb pr = a.prob[p];
     const int n = pr.n;
@@ -452,46 +496,56 @@ __global__ __launch_bounds__(1024) void batched_trsm_kernel(BatchArgs a) {
     const double* Rt = a.Rt + pr.r_off * (int64_t)k;
     const int32_t* pos = a.pos + pr.r_off;
     double* P = a.P + pr.p_off;
+    double* R11s = sm3;                  // keff x keff, diagonal holds 1 / R11[r][r]
+    double* X = sm3 + (size_t)k * k;     // keff x BT_COLS
+    __shared__ int cols[BT_COLS];
+    __shared__ int ncols_s;
     for (int e = threadIdx.x; e < keff * keff; e += 1024) {
         const int r = e / keff, c = e % keff;
-        R11s[e] = (r < c) ? Rt[J[c] * k + r] : (r == c ? bt[r] : 0.0);
+        R11s[e] = (r < c) ? Rt[J[c] * k + r] : (r == c ? 1.0 / bt[r] : 0.0);
     }
-    __syncthreads();
-    const int q = threadIdx.x & 15;
-    for (int j = threadIdx.x >> 4; j < n; j += 64) {
+    // chosen columns: P[:, j] = e_pos
+    for (int e = threadIdx.x; e < n * 16; e += 1024) {
+        const int j = e >> 4, q = e & 15;
         const int pj = pos[j];
-        if (pj >= 0) {
+        if (pj >= 0)
             for (int r = q; r < k; r += 16) P[(int64_t)r * n + j] = (r == pj) ? 1.0 : 0.0;
-            continue;
+    }
+    const int c = threadIdx.x & (BT_COLS - 1);   // column within block
+    const int rg = threadIdx.x / BT_COLS;        // row group (16 groups)
+    for (int j0 = 0; j0 < n; j0 += BT_COLS) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int cnt = 0;
+            for (int j = j0; j < min(n, j0 + BT_COLS); ++j)
+                if (pos[j] < 0) cols[cnt++] = j;
+            ncols_s = cnt;
         }
-        double b[KS], x[KS];
-#pragma unroll
-        for (int sl = 0; sl < KS; ++sl) {
-            const int c = 16 * sl + q;
-            b[sl] = (c < keff) ? Rt[(int64_t)j * k + c] : 0.0;
-            x[sl] = 0.0;
-        }
+        __syncthreads();
+        const int nc = ncols_s;
+        const int jj = (c < nc) ? cols[c] : -1;
+        for (int r = rg; r < keff; r += 16) X[r * BT_COLS + c] = (jj >= 0) ? Rt[(int64_t)jj * k + r] : 0.0;
+        __syncthreads();
         for (int r = keff - 1; r >= 0; --r) {
-            double part = 0.0;
+            const double x = X[r * BT_COLS + c] * R11s[r * keff + r];
+            // rows i = rg + 16 q < r (q < 8 since keff <= 128): loads issued together
+            double xi[8], ri[8];
 #pragma unroll
-            for (int sl = 0; sl < KS; ++sl) {
-                const int c = 16 * sl + q;
-                if (c == r) part = b[sl];
-                if (c > r && c < keff) part = fma(-R11s[r * keff + c], x[sl], part);
+            for (int q = 0; q < 8; ++q) {
+                const int i = rg + 16 * q;
+                xi[q] = (i < r) ? X[i * BT_COLS + c] : 0.0;
+                ri[q] = (i < r) ? R11s[i * keff + r] : 0.0;
             }
-            part += dpp_f64<0xB1, 0xf>(part);
-            part += dpp_f64<0x4E, 0xf>(part);
-            part += dpp_f64<0x141, 0xf>(part);
-            part += dpp_f64<0x140, 0xf>(part);
-            const double xr = part / R11s[r * keff + r];
-            if (q == (r & 15)) {
 #pragma unroll
-                for (int sl = 0; sl < KS; ++sl)
-                    if (sl == (r >> 4)) x[sl] = xr;
+            for (int q = 0; q < 8; ++q) {
+                const int i = rg + 16 * q;
+                if (i < r) X[i * BT_COLS + c] = fma(-ri[q], x, xi[q]);
             }
-            if (q == 0) P[(int64_t)r * n + j] = xr;
+            if (rg == 0 && jj >= 0) P[(int64_t)r * n + jj] = x;
+            __syncthreads();
         }
-        for (int r = keff + q; r < k; r += 16) P[(int64_t)r * n + j] = 0.0;
+        if (jj >= 0)
+            for (int r = keff + rg; r < k; r += 16) P[(int64_t)r * n + jj] = 0.0;
     }
 }
 
@@ -600,13 +654,8 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
     }
     {
         ProfScope ps(PK_TRSM, st);
-        const size_t lds = sizeof(double) * (size_t)k * k;
-        if (k <= 32)
-            hipLaunchKernelGGL(batched_trsm_kernel<2>, dim3((unsigned)nprob), dim3(1024), lds, st, a);
-        else if (k <= 64)
-            hipLaunchKernelGGL(batched_trsm_kernel<4>, dim3((unsigned)nprob), dim3(1024), lds, st, a);
-        else
-            hipLaunchKernelGGL(batched_trsm_kernel<8>, dim3((unsigned)nprob), dim3(1024), lds, st, a);
+        const size_t lds = sizeof(double) * ((size_t)k * k + (size_t)k * BT_COLS);
+        hipLaunchKernelGGL(batched_trsm_kernel, dim3((unsigned)nprob), dim3(1024), lds, st, a);
     }
     return check_launch("batched ID");
 }

@@ -154,8 +154,9 @@ def cp_tensor(dims=(2000, 2000, 2000), R: int = 2000, nbase: int = 50, pert: flo
 
 # --------------------------------------------------------------------------
 # workload 4: batched problems, m ~ logU[256, 4096], n ~ logU[128, 1024],
-# sigma_i = exp(-i/8) (truncated at rank 256, where sigma < 2e-14 sigma_1),
-# stored BF16 (float64 -> float32 RNE -> bfloat16 RNE).
+# sigma_i = exp(-i/8) (truncated at rank 128, where sigma_i < 1.2e-7 sigma_1,
+# far below the BF16 rounding of the stored entries), stored BF16
+# (float64 -> float32 RNE -> bfloat16 RNE).
 # --------------------------------------------------------------------------
 def bf16_bits(x: np.ndarray) -> np.ndarray:
     """float64/float32 -> bfloat16 bit pattern (uint16), round-to-nearest-even
@@ -178,7 +179,7 @@ def batched_shapes(nprob: int = 4096, seed: int = 0, mrange=(256, 4096), nrange=
     return m, n
 
 
-def batched_problem(m: int, n: int, seed: int, p: int, rmax: int = 256) -> np.ndarray:
+def batched_problem(m: int, n: int, seed: int, p: int, rmax: int = 128) -> np.ndarray:
     r = min(m, n, rmax)
     sigma = np.exp(-np.arange(1, r + 1, dtype=np.float64) / 8.0)
     g = rng(seed, _T_BATCH, p + 1)
@@ -192,3 +193,37 @@ def fullrank_perm(m: int, L: int, seed: int = 0, tag: int = 0):
     iid uniform x_q in [L] (entries q < L are unused by the map)."""
     g = rng(seed, _T_PERM, tag)
     return g.permutation(m).astype(np.int64), g.integers(0, L, size=m, dtype=np.int32)
+
+
+def _batched_worker(args):
+    m, n, seed, p = args
+    return batched_problem(m, n, seed, p)
+
+
+def batched_inputs(nprob: int = 4096, seed: int = 0, workers: int = 0, mrange=(256, 4096), nrange=(128, 1024)):
+    """All problems of a batch: (m, n, flat bf16 bits of A_0, A_1, ... back to
+    back).  Problems are drawn independently (stream per problem), so the
+    result does not depend on `workers` (a process pool; 0 = serial)."""
+    m, n = batched_shapes(nprob, seed, mrange, nrange)
+    jobs = [(int(m[p]), int(n[p]), seed, p) for p in range(nprob)]
+    if workers and workers > 1:
+        import multiprocessing as mp
+        import os
+        # fresh interpreters (a forked BLAS thread pool can deadlock), one
+        # BLAS thread each
+        old = {v: os.environ.get(v) for v in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS")}
+        for v in old:
+            os.environ[v] = "1"
+        try:
+            with mp.get_context("spawn").Pool(workers) as pool:
+                parts = pool.map(_batched_worker, jobs, chunksize=16)
+        finally:
+            for v, val in old.items():
+                if val is None:
+                    os.environ.pop(v, None)
+                else:
+                    os.environ[v] = val
+    else:
+        parts = [_batched_worker(j) for j in jobs]
+    flat = np.concatenate([q.ravel() for q in parts])
+    return m, n, flat
