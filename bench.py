@@ -155,8 +155,12 @@ def run_batched(ids, torch, np, m, n, Abits, Gb, steps: int, check: bool):
 
 
 def source_hash(path: str) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256 (16 hex digits) of the dense CountSketch kernel's source text
+    (between its BEGIN / END markers), so edits elsewhere keep the counters."""
+    text = open(path).read()
+    a = text.index("(BEGIN dense CountSketch kernel)")
+    b = text.index("(END dense CountSketch kernel)")
+    return hashlib.sha256(text[a:b].encode()).hexdigest()[:16]
 
 
 def load_traffic(kernel_src: str):
@@ -200,6 +204,8 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the residual comparison with the oracle")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-precision workload")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 3 times (HBM counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -209,6 +215,17 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_launch": 1 << 30,
+                          "bytes_written_per_launch": 1 << 30, "launches": 3}), flush=True)
+        return
 
     # all inputs are generated before the GPU is touched
     A, G, l1 = workload()

@@ -528,19 +528,7 @@ __global__ __launch_bounds__(1024) void batched_trsm_kernel(BatchArgs a) {
         __syncthreads();
         for (int r = keff - 1; r >= 0; --r) {
             const double x = X[r * BT_COLS + c] * R11s[r * keff + r];
-            // rows i = rg + 16 q < r (q < 8 since keff <= 128): loads issued together
-            double xi[8], ri[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int i = rg + 16 * q;
-                xi[q] = (i < r) ? X[i * BT_COLS + c] : 0.0;
-                ri[q] = (i < r) ? R11s[i * keff + r] : 0.0;
-            }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int i = rg + 16 * q;
-                if (i < r) X[i * BT_COLS + c] = fma(-ri[q], x, xi[q]);
-            }
+            for (int i = rg; i < r; i += 16) X[i * BT_COLS + c] = fma(-R11s[i * keff + r], x, X[i * BT_COLS + c]);
             if (rg == 0 && jj >= 0) P[(int64_t)r * n + jj] = x;
             __syncthreads();
         }

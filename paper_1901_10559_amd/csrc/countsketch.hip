@@ -203,7 +203,7 @@ PlanBufs plan_carve(const PlanShape& ps, char*& p) {
 }
 
 // ---------------------------------------------------------------------------
-// dense gather
+// dense gather  (BEGIN dense CountSketch kernel)
 // ---------------------------------------------------------------------------
 template <typename T, int VEC>
 struct VecLoad;
@@ -350,6 +350,7 @@ ids_status cs_dense(int32_t dtype, int32_t acc, const void* A, int64_t lda, int6
     return check_launch("countsketch dense");
 }
 
+// (END dense CountSketch kernel)
 // ---------------------------------------------------------------------------
 // CSR scatter (FP64)
 // ---------------------------------------------------------------------------
