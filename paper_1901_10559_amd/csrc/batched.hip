@@ -23,6 +23,13 @@
 namespace ids {
 
 typedef __bf16 v8bf16 __attribute__((ext_vector_type(8)));
+typedef unsigned int bu4 __attribute__((ext_vector_type(4)));
+
+// A is read once: non-temporal 16-byte loads
+__device__ __forceinline__ uint4 load_nt16(const uint16_t* p) {
+    const bu4 v = __builtin_nontemporal_load(reinterpret_cast<const bu4*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
 typedef float v4f32 __attribute__((ext_vector_type(4)));
 
 struct BProb {
@@ -189,7 +196,7 @@ __global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a)
                             for (int u = 0; u < 4; ++u) {
                                 code[u] = rows[q + u];
                                 const int64_t i = code[u] >= 0 ? code[u] : -(int64_t)code[u] - 1;
-                                raw[u] = *reinterpret_cast<const uint4*>(Ap + i * n + cc);
+                                raw[u] = load_nt16(Ap + i * n + cc);
                             }
 #pragma unroll
                             for (int u = 0; u < 4; ++u) {
@@ -208,7 +215,7 @@ __global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a)
                         const uint16_t* rowp = Ap + i * n + cc;
                         float x[8];
                         if (full) {
-                            const uint4 raw = *reinterpret_cast<const uint4*>(rowp);
+                            const uint4 raw = load_nt16(rowp);
                             x[0] = bf16_to_f32(raw.x & 0xffff); x[1] = bf16_to_f32(raw.x >> 16);
                             x[2] = bf16_to_f32(raw.y & 0xffff); x[3] = bf16_to_f32(raw.y >> 16);
                             x[4] = bf16_to_f32(raw.z & 0xffff); x[5] = bf16_to_f32(raw.z >> 16);

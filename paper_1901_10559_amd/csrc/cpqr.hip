@@ -677,6 +677,220 @@ __global__ __launch_bounds__(NW * 64) void cpqr_lc_kernel(SelArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Short sketches, grouped-lane layout: column c of a wave lives in the G
+// consecutive lanes 8..: lane = G*c + p holds rows [p*R, p*R + R) of it.  Column
+// sums are G-lane DPP trees (quad_perm, half-mirror, mirror: every lane of the
+// group ends with the same bits); updates are branch-free; every wave resolves
+// the workgroup and device argmax itself from LDS, so a step has three
+// workgroup barriers plus the device-wide one.
+// ---------------------------------------------------------------------------
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    if (G >= 2) v += dpp_f64<0xB1, 0xf>(v);   // lanes i, i^1
+    if (G >= 4) v += dpp_f64<0x4E, 0xf>(v);   // lanes i, i^2
+    if (G >= 8) v += dpp_f64<0x141, 0xf>(v);  // half-row mirror (8 lanes)
+    if (G >= 16) v += dpp_f64<0x140, 0xf>(v); // row mirror (16 lanes)
+    return v;
+}
+
+template <int G, int R, int NW, bool ALL>
+__global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
+    extern __shared__ double sm[];
+    __shared__ double s_nu[NW];
+    __shared__ int s_j[NW];
+    constexpr int NT = NW * 64;
+    constexpr int CPWV = 64 / G;  // columns per wave
+
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int p = lane % G;       // row part
+    const int wcol0 = (blockIdx.x * NW + w) * CPWV;
+    const int j = wcol0 + lane / G;
+    const int n = (int)a.n, l = (int)a.l;
+    const int S = a.S;
+    const int row0 = p * R;
+
+    double y[R];
+    bool alive = j < n;
+    {
+        const int64_t jc = min(j, n - 1);
+        if (a.ydt == IDS_F64) {
+            const double* Yp = (const double*)a.Y;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = row0 + r;
+                const double v = Yp[(int64_t)min(i, l - 1) * a.rs + jc * a.cs];
+                y[r] = (alive && i < l) ? v : 0.0;
+            }
+        } else {
+            const float* Yp = (const float*)a.Y;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = row0 + r;
+                const double v = (double)Yp[(int64_t)min(i, l - 1) * a.rs + jc * a.cs];
+                y[r] = (alive && i < l) ? v : 0.0;
+            }
+        }
+    }
+    if (alive && p == 0) a.pos[j] = -1;
+    double nu;
+    {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) s = fma(y[r], y[r], s);
+        nu = group_sum<G>(s);
+    }
+
+    const int k = (int)a.k;
+    int keff = k;
+    for (int t = 0; t < k; ++t) {
+        const int par = t & 1;
+        double* slots = a.slot + (size_t)par * a.nb * S;
+        // ---- wave best, then workgroup best (every wave computes it)
+        {
+            double wn = alive ? nu : -1.0;
+            int wj = alive ? j : INT32_MAX;
+            wave_argmax(wn, wj);
+            if (lane == 0) {
+                s_nu[w] = wn;
+                s_j[w] = wj;
+            }
+        }
+        __syncthreads();
+        double bn = (lane < NW) ? s_nu[lane] : -1.0;
+        int bj = (lane < NW) ? s_j[lane] : INT32_MAX;
+        wave_argmax(bn, bj);
+        if (threadIdx.x == 0) {
+            double* sl = slots + (size_t)blockIdx.x * S;
+            slot_store(sl, bn);
+            slot_store(sl + 1, __longlong_as_double((bj == INT32_MAX) ? -1LL : (long long)bj));
+        }
+        if (j == bj) {  // the G lanes of the workgroup's best column publish it
+            double* sl = slots + (size_t)blockIdx.x * S + 2 + row0;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (row0 + r < l) slot_store(sl + r, y[r]);
+            __builtin_amdgcn_s_waitcnt(0);
+        }
+        // ---- device-wide barrier
+        grid_sync(a.bar, (uint32_t)(a.nb * (t + 1)));
+        // ---- every wave finds the winner
+        if (ALL) {
+            const int tot = a.nb * S;
+            for (int e0 = 0; e0 < tot; e0 += NT * 8) {
+                double tmp[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + u * NT + (int)threadIdx.x;
+                    tmp[u] = (e < tot) ? slot_load(slots + e) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + u * NT + (int)threadIdx.x;
+                    if (e < tot) sm[e] = tmp[u];
+                }
+            }
+            __syncthreads();
+        }
+        double wnu = -1.0;
+        int wj = INT32_MAX;
+        for (int q = lane; q < a.nb; q += 64) {
+            double nq;
+            long long jq;
+            if (ALL) {
+                nq = sm[(size_t)q * S];
+                jq = __double_as_longlong(sm[(size_t)q * S + 1]);
+            } else {
+                nq = slot_load(slots + (size_t)q * S);
+                jq = __double_as_longlong(slot_load(slots + (size_t)q * S + 1));
+            }
+            if (jq >= 0 && (nq > wnu || (nq == wnu && (int)jq < wj))) {
+                wnu = nq;
+                wj = (int)jq;
+            }
+        }
+        wave_argmax(wnu, wj);
+        if (wj == INT32_MAX || !(wnu > 0.0)) {
+            keff = t;
+            break;
+        }
+        const int wblk = wj / (NW * CPWV);
+        const double* xb;
+        if (ALL) {
+            xb = sm + (size_t)wblk * S + 2;
+        } else {
+            const double* wsl = slots + (size_t)wblk * S + 2;
+            for (int i = threadIdx.x; i < l; i += NT) sm[i] = slot_load(wsl + i);
+            __syncthreads();
+            xb = sm;
+        }
+        // ---- Householder reflector (every wave, same bits)
+        double sig2 = 0.0;
+        for (int i = t + 1 + lane; i < l; i += 64) sig2 = fma(xb[i], xb[i], sig2);
+        sig2 = wave_sum_dpp1(sig2);
+        const double alpha = xb[t];
+        double tau, beta, scal;
+        if (sig2 == 0.0) {
+            tau = 0.0;
+            beta = alpha;
+            scal = 0.0;
+        } else {
+            const double nrm = sqrt(alpha * alpha + sig2);
+            beta = (alpha >= 0.0) ? -nrm : nrm;
+            tau = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        double v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = row0 + r;
+            const double xi = xb[min(i, l - 1)];
+            v[r] = (i < t || i >= l) ? 0.0 : (i == t ? 1.0 : xi * scal);
+        }
+        // ---- apply H (branch-free: dead columns get a zero multiplier)
+        double d = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) d = fma(v[r], y[r], d);
+        d = group_sum<G>(d);
+        const double dt = alive ? d * tau : 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) y[r] = fma(-dt, v[r], y[r]);
+        if (j == wj) {
+            alive = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (row0 + r == t) y[r] = beta;
+            if (p == 0) a.pos[j] = t;
+        }
+        // ---- trailing norms for the next step (rows > t)
+        {
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double yr = (row0 + r > t) ? y[r] : 0.0;
+                s = fma(yr, yr, s);
+            }
+            nu = group_sum<G>(s);
+        }
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.J[t] = wj;
+        __syncthreads();  // LDS is rewritten next step
+    }
+
+    if (j < n) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = row0 + r;
+            if (i < keff) a.Rt[(int64_t)j * a.k + i] = y[r];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const bool timed_out = __hip_atomic_load(a.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        *a.keff = timed_out ? -1 : keff;
+        for (int t = keff; t < a.k; ++t) a.J[t] = -1;
+    }
+}
+
 __global__ void zero_u32_kernel(uint32_t* p, int count) {
     if ((int)threadIdx.x < count) p[threadIdx.x] = 0u;
 }
@@ -822,20 +1036,25 @@ static Inst inst() {
             (const void*)&cpqr_kernel<RPL, CPW, NW, false>};
 }
 
-// lane-column kernel: G lanes per column, R rows per lane; reported as
+// lane-column kernels: G lanes per column, R rows per lane; reported as
 // (rpl = -R, cpw = 64 / G) so the column count per workgroup is cpw * nw
 template <int G, int R, int NW>
 static Inst inst_lc() {
     return {-R, 64 / G, NW, (const void*)&cpqr_lc_kernel<G, R, NW, true>,
             (const void*)&cpqr_lc_kernel<G, R, NW, false>};
 }
+template <int G, int R, int NW>
+static Inst inst_gl() {
+    return {-R, 64 / G, NW, (const void*)&cpqr_gl_kernel<G, R, NW, true>,
+            (const void*)&cpqr_gl_kernel<G, R, NW, false>};
+}
 
 static bool pick(int64_t l, Inst& in) {
-    // measured best per sketch height (lane-column for l <= 64)
-    if (l <= 32) in = inst_lc<2, 16, 8>();
-    else if (l <= 64) in = inst_lc<4, 16, 8>();
-    else if (l <= 128) in = inst<2, 8, 8>();
-    else if (l <= 256) in = inst<4, 4, 8>();
+    // grouped-lane kernels for short sketches, column-per-wave beyond 256 rows
+    if (l <= 32) in = inst_gl<2, 16, 8>();
+    else if (l <= 64) in = inst_gl<4, 16, 8>();
+    else if (l <= 128) in = inst_gl<8, 16, 8>();
+    else if (l <= 256) in = inst_gl<16, 16, 8>();
     else if (l <= 512) in = inst<8, 2, 8>();
     else if (l <= 1024) in = inst<16, 1, 8>();
     else if (l <= 2048) in = inst<32, 1, 8>();
