@@ -154,6 +154,73 @@ def run_batched(ids, torch, np, m, n, Abits, Gb, steps: int, check: bool):
     return res
 
 
+def other_workloads(ids, torch, np, steps: int = 10):
+    """Timings of the parity workloads c0, c2, c3 (same kernels, resident inputs)."""
+    import synth
+    dev = torch.device("cuda:0")
+    res = {}
+
+    def timed(fn, names):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        ids.profile_reset()
+        ids.profile_enable(True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ids.profile_enable(False)
+        st = {}
+        for nme in names:
+            t, c = ids.profile_read(nme)
+            st[nme] = t / max(c, 1)
+        ids.profile_reset()
+        return e0.elapsed_time(e1) / steps, st
+
+    # c0: 2000 x 1000 FP64, k = 20, p = 10, l1 = 128 (latency of one small ID)
+    A0 = torch.from_numpy(synth.config0()).to(dev)
+    G0 = torch.from_numpy(synth.gaussian(30, 128, seed=0)).to(dev)
+    ms, st = timed(lambda: ids.matrix_id(A0, 20, 128, 30, seed=0, G=G0),
+                   ("plan", "countsketch", "project", "cpqr", "trsm"))
+    res["dense_2000x1000_f64"] = {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st}
+
+    # c2: CSR 1e6 x 2e4, ~3e7 stored entries, FP64, k = 50, p = 10, l1 = 240
+    rp, ci, v = synth.csr_zipf()
+    Ad = (torch.from_numpy(rp).to(dev), torch.from_numpy(ci).to(dev), torch.from_numpy(v).to(dev), 20000)
+    G2 = torch.from_numpy(synth.gaussian(60, 240, seed=0)).to(dev)
+    ms, st = timed(lambda: ids.matrix_id(Ad, 50, 240, 60, seed=0, G=G2),
+                   ("plan", "countsketch", "project", "cpqr", "trsm"))
+    nnz = v.shape[0]
+    cs_bytes = nnz * 12 + (rp.shape[0]) * 8 + 240 * 20000 * 8
+    gbs = cs_bytes / (st["countsketch"] / 1e3) / 1e9
+    res["csr_1e6x2e4_f64"] = {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st, "nnz": int(nnz),
+                              "countsketch_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBPS,
+                                                       "unit": "GB/s", "frac": gbs / HBM_PEAK_GBPS,
+                                                       "algorithmic_bytes": int(cs_bytes)}}
+
+    # c3: CP tensor 2000^3, R = 2000, J = 4096, k = 50, FP64
+    factors, lam, _ = synth.cp_tensor()
+    ft = [torch.from_numpy(np.ascontiguousarray(np.asarray(f).T)).to(dev).t() for f in factors]
+    lt = torch.from_numpy(lam).to(dev)
+    ms, st = timed(lambda: ids.tensor_id(ft, lt, 50, 4096, seed=0),
+                   ("plan", "tensorsketch", "cpqr", "trsm", "lambda_hat"))
+    ts_s = st["tensorsketch"] / 1e3
+    ts_bytes = 3 * 2000 * 2000 * 8 + 4096 * 2000 * 8
+    ts_flops = 1000 * 4 * 5 * 4096 * 12    # 4 complex FFTs of 4096 points per column pair
+    res["tensor_2000cubed_R2000_J4096_f64"] = {
+        "ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st,
+        "tensorsketch_roofline": {"hbm": {"achieved": ts_bytes / ts_s / 1e9, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                          "frac": ts_bytes / ts_s / 1e9 / HBM_PEAK_GBPS, "algorithmic_bytes": ts_bytes},
+                                  "fp64": {"achieved": ts_flops / ts_s / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                                           "frac": ts_flops / ts_s / 1e12 / 78.6, "algorithmic_flops": ts_flops},
+                                  "note": "factors (96 MB) fit in the 256 MB last-level cache: warm figure"}}
+    return res
+
+
 def source_hash(path: str) -> str:
     """sha256 (16 hex digits) of the dense CountSketch kernel's source text
     (between its BEGIN / END markers), so edits elsewhere keep the counters."""
@@ -204,6 +271,7 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the residual comparison with the oracle")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-precision workload")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--no-others", action="store_true", help="skip the c0 / c2 / c3 timings")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -318,6 +386,9 @@ def main():
         res_o = oracle.residual_fro(A64, oracle_out["J"], oracle_out["P"])
         out["residual"] = {"gpu": res_g, "oracle_f64": res_o, "ratio": res_g / res_o,
                            "J_overlap": int(len(set(Jg.tolist()) & set(oracle_out["J"].tolist())))}
+    if not args.no_others:
+        print("[bench] other workloads (dense 2000x1000, CSR 1e6x2e4, tensor 2000^3)", flush=True)
+        out["other_workloads"] = other_workloads(ids, torch, np)
     if batch is not None:
         print("[bench] batched workload", flush=True)
         out["batched"] = run_batched(ids, torch, np, *batch, steps=args.batched_steps, check=not args.no_check)

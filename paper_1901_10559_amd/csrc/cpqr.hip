@@ -891,6 +891,188 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Tall sketches (2048 < l <= 64 * (RREG + RLDS)): one column per wave; rows
+// lane + 64 r, r < RREG, in registers and the remaining RLDS chunks of 64 rows
+// in LDS (per wave), so a 4096-row FP64 column fits beside the winner's copy.
+// Same step structure and arithmetic as cpqr_kernel.
+// ---------------------------------------------------------------------------
+template <int RREG, int RLDS, int NW>
+__global__ __launch_bounds__(NW * 64) void cpqr_tall_kernel(SelArgs a) {
+    extern __shared__ double sm[];
+    constexpr int LP = 64 * (RREG + RLDS);           // rows covered (>= l)
+    double* xb = sm;                                 // winner column, LP entries (zero past l)
+    double* yl = sm + LP;                            // NW x RLDS x 64 rows held in LDS
+    __shared__ double s_nu[NW];
+    __shared__ int s_j[NW];
+    constexpr int NT = NW * 64;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int j = blockIdx.x * NW + w;
+    const int n = (int)a.n, l = (int)a.l, S = a.S;
+    double* myl = yl + (size_t)w * RLDS * 64 + lane;  // chunk RREG + q of this lane at myl[64 q]
+
+    // Row i = lane + 64 r.  Predicates on i are uniform per chunk r except for
+    // the one chunk that contains the boundary, which keeps the masks scalar.
+    double y[RREG];
+    bool alive = j < n;
+    {
+        const int64_t jc = min(j, n - 1);
+        auto ld = [&](int i) -> double {
+            double v;
+            if (a.ydt == IDS_F64)
+                v = ((const double*)a.Y)[(int64_t)min(i, l - 1) * a.rs + jc * a.cs];
+            else
+                v = (double)((const float*)a.Y)[(int64_t)min(i, l - 1) * a.rs + jc * a.cs];
+            return (alive && i < l) ? v : 0.0;
+        };
+#pragma unroll
+        for (int r = 0; r < RREG; ++r) y[r] = ld(lane + 64 * r);
+        for (int q = 0; q < RLDS; ++q) myl[64 * q] = ld(lane + 64 * (RREG + q));
+    }
+    if (alive && lane == 0) a.pos[j] = -1;
+    // sum of squares over rows i >= from
+    auto trailing = [&](int from) -> double {
+        const int c0 = from >> 6, lo = from & 63;
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < RREG; ++r) {
+            if (r < c0) continue;
+            const double yr = (r == c0 && lane < lo) ? 0.0 : y[r];
+            s = fma(yr, yr, s);
+        }
+        for (int q = max(c0 - RREG, 0); q < RLDS; ++q) {
+            const double yq = myl[64 * q];
+            const double yr = (RREG + q == c0 && lane < lo) ? 0.0 : yq;
+            s = fma(yr, yr, s);
+        }
+        return wave_sum_dpp1(s);
+    };
+    double nu = trailing(0);
+
+    const int k = (int)a.k;
+    int keff = k;
+    for (int t = 0; t < k; ++t) {
+        const int par = t & 1;
+        double* slots = a.slot + (size_t)par * a.nb * S;
+        if (lane == 0) {
+            s_nu[w] = alive ? nu : -1.0;
+            s_j[w] = alive ? j : INT32_MAX;
+        }
+        __syncthreads();
+        double bn = (lane < NW) ? s_nu[lane] : -1.0;
+        int bj = (lane < NW) ? s_j[lane] : INT32_MAX;
+        wave_argmax(bn, bj);
+        if (threadIdx.x == 0) {
+            double* sl = slots + (size_t)blockIdx.x * S;
+            slot_store(sl, bn);
+            slot_store(sl + 1, __longlong_as_double((bj == INT32_MAX) ? -1LL : (long long)bj));
+        }
+        if (j == bj) {  // rows < l only: the slot holds S >= l + 2 entries
+            double* sl = slots + (size_t)blockIdx.x * S + 2 + lane;
+#pragma unroll
+            for (int r = 0; r < RREG; ++r)
+                if (lane + 64 * r < l) slot_store(sl + 64 * r, y[r]);
+            for (int q = 0; q < RLDS; ++q)
+                if (lane + 64 * (RREG + q) < l) slot_store(sl + 64 * (RREG + q), myl[64 * q]);
+            __builtin_amdgcn_s_waitcnt(0);
+        }
+        grid_sync(a.bar, (uint32_t)(a.nb * (t + 1)));
+        double wnu = -1.0;
+        int wj = INT32_MAX;
+        for (int q = lane; q < a.nb; q += 64) {
+            const double nq = slot_load(slots + (size_t)q * S);
+            const long long jq = __double_as_longlong(slot_load(slots + (size_t)q * S + 1));
+            if (jq >= 0 && (nq > wnu || (nq == wnu && (int)jq < wj))) {
+                wnu = nq;
+                wj = (int)jq;
+            }
+        }
+        wave_argmax(wnu, wj);
+        if (wj == INT32_MAX || !(wnu > 0.0)) {
+            keff = t;
+            break;
+        }
+        {
+            const double* wsl = slots + (size_t)(wj / NW) * S + 2;
+            const int lp = LP;
+            for (int i0 = 0; i0 < lp; i0 += NT * 8) {
+                double tmp[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int i = i0 + u * NT + (int)threadIdx.x;
+                    tmp[u] = (i < l) ? slot_load(wsl + i) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int i = i0 + u * NT + (int)threadIdx.x;
+                    if (i < lp) xb[i] = tmp[u];
+                }
+            }
+        }
+        __syncthreads();
+        double sig2 = 0.0;
+        for (int i = t + 1 + lane; i < l; i += 64) sig2 = fma(xb[i], xb[i], sig2);
+        sig2 = wave_sum_dpp1(sig2);
+        const double alpha = xb[t];
+        double tau, beta, scal;
+        if (sig2 == 0.0) {
+            tau = 0.0;
+            beta = alpha;
+            scal = 0.0;
+        } else {
+            const double nrm = sqrt(alpha * alpha + sig2);
+            beta = (alpha >= 0.0) ? -nrm : nrm;
+            tau = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        const int c0 = t >> 6, lo = t & 63;
+        // reflector entry of chunk r for this lane: 0 above t, 1 at t, x_i scal below
+        auto vchunk = [&](int r) -> double {
+            const double x = xb[lane + 64 * r] * scal;
+            return (r == c0) ? (lane < lo ? 0.0 : (lane == lo ? 1.0 : x)) : x;
+        };
+        double d = 0.0;
+#pragma unroll
+        for (int r = 0; r < RREG; ++r)
+            if (r >= c0) d = fma(vchunk(r), y[r], d);
+        for (int q = max(c0 - RREG, 0); q < RLDS; ++q) d = fma(vchunk(RREG + q), myl[64 * q], d);
+        d = wave_sum_dpp1(d);
+        const double dt = alive ? d * tau : 0.0;
+#pragma unroll
+        for (int r = 0; r < RREG; ++r)
+            if (r >= c0) y[r] = fma(-dt, vchunk(r), y[r]);
+        for (int q = max(c0 - RREG, 0); q < RLDS; ++q) myl[64 * q] = fma(-dt, vchunk(RREG + q), myl[64 * q]);
+        if (j == wj) {
+            alive = false;
+            if (c0 < RREG) {
+#pragma unroll
+                for (int r = 0; r < RREG; ++r)
+                    if (r == c0 && lane == lo) y[r] = beta;
+            } else if (lane == lo) {
+                myl[64 * (c0 - RREG)] = beta;
+            }
+            if (lane == 0) a.pos[j] = t;
+        }
+        nu = trailing(t + 1);
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.J[t] = wj;
+        __syncthreads();
+    }
+    if (j < n) {
+        double* Rj = a.Rt + (int64_t)j * a.k;
+#pragma unroll
+        for (int r = 0; r < RREG; ++r)
+            if (lane + 64 * r < keff) Rj[lane + 64 * r] = y[r];
+        for (int q = 0; q < RLDS; ++q)
+            if (lane + 64 * (RREG + q) < keff) Rj[lane + 64 * (RREG + q)] = myl[64 * q];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const bool timed_out = __hip_atomic_load(a.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        *a.keff = timed_out ? -1 : keff;
+        for (int t = keff; t < a.k; ++t) a.J[t] = -1;
+    }
+}
+
 __global__ void zero_u32_kernel(uint32_t* p, int count) {
     if ((int)threadIdx.x < count) p[threadIdx.x] = 0u;
 }
@@ -1028,6 +1210,7 @@ struct Inst {
     int rpl, cpw, nw;
     const void* fn_all;
     const void* fn_one;
+    size_t lds_extra = 0;  // tall kernel: LDS-held rows (bytes per workgroup)
 };
 
 template <int RPL, int CPW, int NW>
@@ -1058,7 +1241,11 @@ static bool pick(int64_t l, Inst& in) {
     else if (l <= 512) in = inst<8, 2, 8>();
     else if (l <= 1024) in = inst<16, 1, 8>();
     else if (l <= 2048) in = inst<32, 1, 8>();
-    else if (l <= 4096) in = inst<64, 1, 8>();
+    else if (l <= 4096) {
+        // 40 chunks of 64 rows in registers, 24 in LDS (12 KB per wave)
+        const void* f = (const void*)&cpqr_tall_kernel<40, 24, 8>;
+        in = {64, 1, 8, f, f, sizeof(double) * 8 * 24 * 64};
+    }
     else return false;
     return true;
 }
@@ -1068,6 +1255,10 @@ constexpr size_t ALL_SLOTS_LDS_MAX = 64 * 1024;
 
 static size_t cpqr_lds(const SelectPlan& sp, bool& all) {
     const size_t S = (size_t)slot_stride(sp.l);
+    if (sp.l > 2048) {  // tall kernel: winner column (4096 rows) + LDS-held rows
+        all = false;
+        return sizeof(double) * 64 * 64 + sizeof(double) * 8 * 24 * 64;
+    }
     all = sizeof(double) * S * sp.nb <= ALL_SLOTS_LDS_MAX;
     return all ? sizeof(double) * S * sp.nb : sizeof(double) * S;
 }

@@ -149,7 +149,8 @@ def test_projection_f32():
 # select (Algorithm 1)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("l,n,k", [(30, 1000, 20), (12, 40, 5), (64, 64, 40), (120, 2000, 100), (60, 20000, 50),
-                                   (130, 700, 130), (300, 900, 64), (1500, 600, 50), (4096, 300, 30)])
+                                   (130, 700, 130), (300, 900, 64), (1500, 600, 50), (4096, 300, 30),
+                                   (3000, 500, 40), (2049, 260, 70), (4096, 2000, 12)])
 def test_select_f64(l, n, k):
     g = np.random.default_rng(l + n + k)
     Y = g.standard_normal((l, n)) * g.uniform(0.1, 10, n)[None, :]
