@@ -385,16 +385,37 @@ __global__ __launch_bounds__(CSR_THREADS) void cs_csr_lds_kernel(const int64_t* 
     const int64_t cnt = end - beg;
     const int p0 = beg + (int)(cnt * ch / nchunk);
     const int p1 = beg + (int)(cnt * (ch + 1) / nchunk);
+    // Each group of CSR_GROUP lanes takes CSR_GROUP consecutive rows of the
+    // list at a time: lane q fetches row q's code and extent (independent loads
+    // in flight), then the group walks the rows' entries together.
     const int g = threadIdx.x / CSR_GROUP;
     const int gl = threadIdx.x % CSR_GROUP;
     constexpr int NG = CSR_THREADS / CSR_GROUP;
-    for (int p = p0 + g; p < p1; p += NG) {
-        int32_t code = rows[p];
-        int64_t i = code >= 0 ? code : -(int64_t)code - 1;
-        const int64_t e0 = rowptr[i], e1 = rowptr[i + 1];
-        for (int64_t e = e0 + gl; e < e1; e += CSR_GROUP) {
-            double v = val[e];
-            atomicAdd(&ybuf[colind[e]], code < 0 ? -v : v);
+    for (int pb = p0 + g * CSR_GROUP; pb < p1; pb += NG * CSR_GROUP) {
+        const int pq = pb + gl;
+        int32_t code = 0;
+        int64_t e0 = 0, e1 = 0;
+        if (pq < p1) {
+            code = rows[pq];
+            const int64_t i = code >= 0 ? code : -(int64_t)code - 1;
+            e0 = rowptr[i];
+            e1 = rowptr[i + 1];
+        }
+#pragma unroll
+        for (int q = 0; q < CSR_GROUP; ++q) {
+            const int64_t b0 = __shfl(e0, q, CSR_GROUP), b1 = __shfl(e1, q, CSR_GROUP);
+            const bool neg = __shfl(code, q, CSR_GROUP) < 0;
+            int64_t e = b0 + gl;
+            for (; e + CSR_GROUP < b1; e += 2 * CSR_GROUP) {  // two entries per lane in flight
+                const double v0 = val[e], v1 = val[e + CSR_GROUP];
+                const int c0 = colind[e], c1 = colind[e + CSR_GROUP];
+                atomicAdd(&ybuf[c0], neg ? -v0 : v0);
+                atomicAdd(&ybuf[c1], neg ? -v1 : v1);
+            }
+            if (e < b1) {
+                const double v = val[e];
+                atomicAdd(&ybuf[colind[e]], neg ? -v : v);
+            }
         }
     }
     __syncthreads();

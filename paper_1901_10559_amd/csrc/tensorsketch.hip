@@ -10,10 +10,12 @@
 //     plan, so the result is deterministic), transformed by a radix-16
 //     Stockham FFT in LDS, and split into the two half spectra
 //     (Z[k] + conj Z[-k]) / 2 and (Z[k] - conj Z[-k]) / 2i, which are
-//     multiplied into two LDS product arrays (k = 0..J/2);
+//     multiplied into two running products (k = 0..J/2);
 //   * the products are recombined as Q = P(r) + i P(r+1) (Hermitian extension)
 //     and inverse transformed once: Re -> column r, Im -> column r+1.
-// LDS: padded complex work buffer (J * 17/16) + two half spectra (J/2 + 1).
+// LDS: the padded complex work buffer (J * 17/16); the two half-spectrum
+// products stay in registers (each thread owns up to 9 frequencies), so two
+// workgroups share a CU.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -129,15 +131,18 @@ struct TsArgs {
     double* Y;  // J x R column-major
 };
 
+// frequencies k = tid + 256 q (q < TS_NK) of the half spectrum 0..J/2 are owned
+// by thread tid, which keeps their running products in registers
+constexpr int TS_NK = 9;  // ceil((4096 / 2 + 1) / 256)
+
 __global__ __launch_bounds__(256) void tensorsketch_kernel(TsArgs a) {
     extern __shared__ double2 smem[];
     const int J = a.J;
-    double2* buf = smem;                           // padi(J) entries
-    double2* P1 = smem + (J + J / 16);             // J/2 + 1
-    double2* P2 = P1 + (J / 2 + 1);                // J/2 + 1
+    double2* buf = smem;  // padi(J) entries
     const int64_t r0 = (int64_t)blockIdx.x * 2;
     const bool two = r0 + 1 < a.R;
     const int tid = threadIdx.x;
+    double2 P1[TS_NK], P2[TS_NK];
 
     for (int md = 0; md < a.N; ++md) {
         const double* f0 = a.fac[md] + r0 * a.ld[md];
@@ -164,7 +169,10 @@ __global__ __launch_bounds__(256) void tensorsketch_kernel(TsArgs a) {
         __syncthreads();
         fft_lds(buf, J, a.tw);
         // split the packed spectrum, multiply into the products
-        for (int k = tid; k <= J / 2; k += 256) {
+#pragma unroll
+        for (int q = 0; q < TS_NK; ++q) {
+            const int k = tid + 256 * q;
+            if (k > J / 2) continue;
             const double2 z = buf[padi(k)];
             const double2 zc = conj2(buf[padi((J - k) & (J - 1))]);
             const double2 A = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y + zc.y));
@@ -172,27 +180,27 @@ __global__ __launch_bounds__(256) void tensorsketch_kernel(TsArgs a) {
             const double2 d = csub(z, zc);
             const double2 B = make_double2(0.5 * d.y, -0.5 * d.x);
             if (md == 0) {
-                P1[k] = A;
-                P2[k] = B;
+                P1[q] = A;
+                P2[q] = B;
             } else {
-                P1[k] = cmul(P1[k], A);
-                P2[k] = cmul(P2[k], B);
+                P1[q] = cmul(P1[q], A);
+                P2[q] = cmul(P2[q], B);
             }
         }
         __syncthreads();
     }
-    // Q = P1 + i P2 over the full circle; inverse FFT via conj(FFT(conj(Q))) / J
-    for (int k = tid; k < J; k += 256) {
-        double2 p1, p2;
-        if (k <= J / 2) {
-            p1 = P1[k];
-            p2 = P2[k];
-        } else {
-            p1 = conj2(P1[J - k]);
-            p2 = conj2(P2[J - k]);
+    // Q = P1 + i P2 over the full circle (Hermitian extension); inverse FFT via
+    // conj(FFT(conj(Q))) / J
+#pragma unroll
+    for (int q = 0; q < TS_NK; ++q) {
+        const int k = tid + 256 * q;
+        if (k > J / 2) continue;
+        const double2 p1 = P1[q], p2 = P2[q];
+        buf[padi(k)] = conj2(make_double2(p1.x - p2.y, p1.y + p2.x));
+        if (k > 0 && k < J / 2) {
+            const double2 c1 = conj2(p1), c2 = conj2(p2);
+            buf[padi(J - k)] = conj2(make_double2(c1.x - c2.y, c1.y + c2.x));
         }
-        const double2 q = make_double2(p1.x - p2.y, p1.y + p2.x);
-        buf[padi(k)] = conj2(q);
     }
     __syncthreads();
     fft_lds(buf, J, a.tw);
@@ -219,7 +227,7 @@ ids_status twiddles(int64_t Jlen, double2* tw, hipStream_t st) {
     return check_launch("twiddles");
 }
 
-size_t ts_lds_bytes(int64_t J) { return sizeof(double2) * (size_t)(J + J / 16 + 2 * (J / 2 + 1)); }
+size_t ts_lds_bytes(int64_t J) { return sizeof(double2) * (size_t)(J + J / 16); }
 
 ids_status tensorsketch(int32_t N, const int64_t* dims, int64_t R, const double* const* factors, const int64_t* ld,
                         const double* lambda, int64_t Jlen, const PlanBufs* plans, const double2* tw, double* Y,
