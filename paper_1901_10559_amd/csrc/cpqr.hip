@@ -1,26 +1,51 @@
 // Algorithm 1 on a sketch Y (l x n): rank-k column-pivoted QR, then
 // P = [I, R11^{-1} R12] Pi^T in the original column order.
 //
-// cpqr_kernel is a persistent cooperative kernel.  Each wave owns CPW columns
-// of Y held in registers for the whole factorisation (row i of a column lives
-// in lane i % 64, register slot i / 64).  One step t:
-//   1. every wave recomputes the trailing squared norms sum_{i>=t} y_ij^2 of its
-//      live columns in FP64 (no downdating, so no cancellation guard needed);
-//   2. the workgroup's best (largest norm, ties to the smallest column index)
-//      is published with a copy of that column to a per-workgroup slot;
-//   3. one device-wide barrier;
-//   4. every workgroup reads all candidates, picks the same winner, copies the
-//      winner's column to LDS and forms the Householder reflector
-//      (v_t = 1, beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta);
-//   5. the reflector is applied to every live column; row t of a column then
-//      holds R[t][j].
-// After k steps each column's top k rows are R[0:k, j] (original order).
-// trsm_p_kernel then solves R11 x = R[0:k, j] per column by back-substitution
-// and writes P.
+// The factorisation is one persistent cooperative kernel.  The columns of Y
+// are spread over the workgroups and stay in registers for all k steps.  One
+// step t:
+//   1. each workgroup finds its best live column (largest trailing squared
+//      norm, ties to the smallest column index) and publishes (norm, index);
+//   2. every workgroup reads all published candidates and picks the same
+//      winner;
+//   3. the winner's column reaches every workgroup, which forms the
+//      Householder reflector of its rows t..l-1 (v_t = 1,
+//      beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta) and applies it
+//      to its live columns; row t of a column then holds R[t][j];
+//   4. the trailing squared norms (rows > t) are recomputed in FP64 (no
+//      downdating, so no cancellation guard is needed).
+// After k steps the top k rows of column j hold R[0:k, j].  The trsm kernels
+// then solve R11 x = R[0:k, j] per column and write P.
+//
+// Exchange between workgroups: write-once mailboxes.  Step t owns its own
+// region of the workspace, filled with the sentinel pattern MB_SENT (a
+// signalling-NaN bit pattern) before the kernel starts.  Writers store each
+// 8-byte value once with agent-scope atomic stores; readers reload a value
+// until it differs from the sentinel.  A location only ever holds the
+// sentinel or its final value and 8-byte accesses are single-copy atomic, so
+// a value that is not the sentinel is the value: there is no barrier counter,
+// fence or flag per step, and a reader waits only for the data it needs.
+// Data whose bits equal MB_SENT are stored as the canonical quiet NaN.
+// Two ways to move the winner's column (chosen on the host by size):
+//   MB_SPEC  every publisher also writes its best column speculatively next
+//            to its header; after the vote everyone reads the winner's copy;
+//   MB_OWNER headers only; after the vote the owner of the winner publishes
+//            its column into the step's column box (long sketches and long
+//            factorisations, where the speculative copies would dominate).
+// The reflector norm is the winner's published trailing norm:
+// ||x_{t..l-1}||^2 = nu_winner, so beta = -sign(alpha) sqrt(nu_winner) and no
+// workgroup re-sums the column.  (nu_winner <= alpha^2 means the entries
+// below the diagonal vanish to rounding: H = I, as when they are exactly 0.)
+// Every wait is capped; on expiry a device flag is raised, every other wait
+// gives up at once, and k_eff is reported as -1.
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace ids {
+
+enum { MB_SPEC = 0, MB_OWNER = 1 };
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
 struct SelArgs {
     const void* Y;
@@ -28,62 +53,62 @@ struct SelArgs {
     int64_t l, n, rs, cs, k;
     int64_t* J;
     int64_t* keff;
-    double* Rt;        // n x k (column j's top rows contiguous)
-    int32_t* pos;      // n: step at which the column was chosen, -1 otherwise
-    double* slot;      // 2 x nb x S: [0] = norm^2, [1] = column index bits, [2..2+l) = column
-    uint32_t* bar;     // [0] barrier counter, [1] timeout flag
-    int32_t nb, S;
+    double* Rt;       // n x k (column j's top rows contiguous)
+    int32_t* pos;     // n: step at which the column was chosen, -1 otherwise
+    double* mb;       // k step regions of RS doubles each, sentinel-filled
+    uint32_t* flag;   // [0] timeout flag
+    int32_t nh;       // publishers (headers per step)
+    int32_t S;        // MB_SPEC: slot stride ([0] norm, [1] index, [2..2+l) column)
+    int32_t H0;       // MB_OWNER: offset of the column box (headers at 2 q)
+    int64_t RS;       // doubles per step region
 };
 
-__device__ __forceinline__ bool better(double nu1, int64_t j1, double nu2, int64_t j2) {
-    return nu1 > nu2 || (nu1 == nu2 && j1 < j2);
-}
+constexpr uint64_t MB_SENT = 0xFFF4A5A5A5A5A5A5ull;
+constexpr uint64_t MB_QNAN = 0x7FF8000000000000ull;
+constexpr uint32_t SPIN_LIMIT = 1u << 20;
 
-__device__ __forceinline__ double load_y(const SelArgs& a, int64_t off) {
-    return a.ydt == IDS_F64 ? ((const double*)a.Y)[off] : (double)((const float*)a.Y)[off];
+__device__ __forceinline__ void mb_put(double* p, double v) {
+    uint64_t b = (uint64_t)__double_as_longlong(v);
+    if (b == MB_SENT) b = MB_QNAN;
+    __hip_atomic_store((uint64_t*)p, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-
-// wave sums of CPW values at once (independent DPP chains overlap); the
-// result is broadcast from one lane, so every lane holds the same bits.
-template <int CPW>
-__device__ __forceinline__ void wave_sum_many(double (&v)[CPW]) {
-    wave_sum_dpp<CPW>(v);
+__device__ __forceinline__ uint64_t mb_load(const double* p) {
+    return __hip_atomic_load((uint64_t*)const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ double mb_val(uint64_t b) { return __longlong_as_double((long long)b); }
+__device__ __forceinline__ double idx_bits(int j) { return __longlong_as_double((long long)j); }
 
-constexpr uint32_t SPIN_LIMIT = 1u << 21;
-
-// Cross-workgroup data (candidate slots, the barrier counter) is only ever
-// accessed with agent-scope atomic loads and stores, which are coherent across
-// the whole device per location without L2 write-back or invalidation.  The
-// order "slot data before counter increment" is enforced by waiting for the
-// wave's outstanding memory operations (s_waitcnt 0) before the increment; the
-// order "counter observed before slot data read" by the control dependency on
-// the polled value.
-__device__ __forceinline__ void slot_store(double* p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double slot_load(const double* p) {
-    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Device-wide barrier for a cooperative launch (all workgroups co-resident).
-// Callers that stored slot data must have executed s_waitcnt 0 first.  The
-// spin is capped so every wave always exits; on timeout a flag is raised.
-__device__ void grid_sync(uint32_t* bar, uint32_t target) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_s_waitcnt(0);
-        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (++spins > SPIN_LIMIT) {
-                __hip_atomic_store(bar + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-        }
+// U values per lane from addr(u) (nullptr: unused, reads as 0).  Sentinel
+// entries are reloaded until every lane of the wave has final values; the
+// loop is wave-uniform.  On timeout the flag is raised and the remaining
+// entries keep the sentinel (a NaN).
+template <int U, class F>
+__device__ __forceinline__ void mb_read(uint64_t (&v)[U], F addr, uint32_t* flag) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const double* p = addr(u);
+        v[u] = p ? mb_load(p) : 0ull;
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    __syncthreads();
+    for (uint32_t spin = 0;; ++spin) {
+        bool pend = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) pend = pend || (v[u] == MB_SENT);
+        if (!__any(pend)) return;
+        if (spin >= SPIN_LIMIT ||
+            ((spin & 63) == 63 && __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+            if (pend) __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (v[u] == MB_SENT) v[u] = mb_load(addr(u));
+    }
+}
+
+__global__ void mb_fill_kernel(uint64_t* mb, int64_t count, uint32_t* flag) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 0u;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256)
+        mb[e] = MB_SENT;
 }
 
 // argmax over the wave of (nu, j): largest nu, then smallest j; j < 2^31.
@@ -118,572 +143,105 @@ __device__ __forceinline__ void wave_argmax(double& nu, int& j) {
     j = __builtin_amdgcn_readlane(q, 63);
 }
 
-// ALL = true: every workgroup copies all candidate slots to LDS with one bulk
-// load (one round trip after the barrier); otherwise it reads the headers, then
-// the winner's column.
-template <int RPL, int CPW, int NW, bool ALL>
-__global__ __launch_bounds__(NW * 64) void cpqr_kernel(SelArgs a) {
-    extern __shared__ double sm[];
-    __shared__ double s_nu[NW];
-    __shared__ int64_t s_j[NW];
-    __shared__ double s_wnu;
-    __shared__ int64_t s_wj;
+// fold one published header into a running (norm, index) best
+__device__ __forceinline__ void take(uint64_t nb_bits, uint64_t j_bits, double& bn, int& bj) {
+    const double nq = mb_val(nb_bits);
+    const long long jq = (long long)j_bits;
+    if (jq >= 0 && jq < INT32_MAX && (nq > bn || (nq == bn && (int)jq < bj))) {
+        bn = nq;
+        bj = (int)jq;
+    }
+}
+
+// The vote from headers: the nh headers (header q at reg + q * hs) are read
+// by all threads of the workgroup (up to 4 each), reduced per wave, then over
+// the waves through LDS; every wave returns the same winner.
+constexpr int VOTE_PER_THREAD = 4;
+template <int NW>
+__device__ __forceinline__ void vote_hdr(const SelArgs& a, const double* reg, int hs, double* s_vn, int* s_vj,
+                                         double& wnu, int& wj) {
     constexpr int NT = NW * 64;
-
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int64_t colbase = ((int64_t)blockIdx.x * NW + w) * CPW;
-    const int64_t l = a.l, n = a.n;
-    const int S = a.S;
-
-    double y[CPW][RPL];
-    bool alive[CPW];
-    // branch-free load: indices clamped into range, out-of-range entries zeroed
-    if (a.ydt == IDS_F64) {
-        const double* Yp = (const double*)a.Y;
+    constexpr int UH = VOTE_PER_THREAD;
+    uint64_t hv[2 * UH];
+    mb_read<2 * UH>(
+        hv,
+        [&](int u) -> const double* {
+            const int q = (int)threadIdx.x + NT * (u >> 1);
+            return q < a.nh ? reg + (size_t)q * hs + (u & 1) : nullptr;
+        },
+        a.flag);
+    double bn = -1.0;
+    int bj = INT32_MAX;
 #pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-            const int64_t jc = min(colbase + c, n - 1);
+    for (int u = 0; u < UH; ++u)
+        if ((int)threadIdx.x + NT * u < a.nh) take(hv[2 * u], hv[2 * u + 1], bn, bj);
+    wave_argmax(bn, bj);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        s_vn[w] = bn;
+        s_vj[w] = bj;
+    }
+    __syncthreads();
+    wnu = (lane < NW) ? s_vn[lane] : -1.0;
+    wj = (lane < NW) ? s_vj[lane] : INT32_MAX;
+    wave_argmax(wnu, wj);
+}
+
+// l published values at src -> LDS dst, zeros up to lpad (all threads), then a
+// workgroup barrier.  Row i is stored at i + (i >> PSH): one pad slot per
+// 2^PSH rows, so lane parts that read rows 2^PSH apart hit different banks.
+template <int NT, int PSH>
+__device__ __forceinline__ void fetch_col_lds(const SelArgs& a, const double* src, int l, int lpad, double* dst) {
+    for (int i = l + (int)threadIdx.x; i < lpad; i += NT) dst[i + (i >> PSH)] = 0.0;
+    for (int i0 = 0; i0 < l; i0 += NT * 8) {
+        uint64_t v[8];
+        mb_read<8>(
+            v,
+            [&](int u) -> const double* {
+                const int i = i0 + u * NT + (int)threadIdx.x;
+                return i < l ? src + i : nullptr;
+            },
+            a.flag);
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-                const int i = lane + 64 * r;
-                const double v = Yp[(int64_t)min(i, (int)l - 1) * a.rs + jc * a.cs];
-                y[c][r] = (colbase + c < n && i < l) ? v : 0.0;
-            }
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * NT + (int)threadIdx.x;
+            if (i < l) dst[i + (i >> PSH)] = mb_val(v[u]);
         }
+    }
+    __syncthreads();
+}
+
+// Householder scalars of the winner x (rows t..l-1) from alpha = x_t and the
+// published trailing norm nu2 = sum_{i>=t} x_i^2; v_i = x_i * scal below t.
+__device__ __forceinline__ void reflector(double alpha, double nu2, double& tau, double& beta, double& scal) {
+    if (!(nu2 > alpha * alpha)) {
+        tau = 0.0;
+        beta = alpha;
+        scal = 0.0;
     } else {
-        const float* Yp = (const float*)a.Y;
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-            const int64_t jc = min(colbase + c, n - 1);
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-                const int i = lane + 64 * r;
-                const double v = (double)Yp[(int64_t)min(i, (int)l - 1) * a.rs + jc * a.cs];
-                y[c][r] = (colbase + c < n && i < l) ? v : 0.0;
-            }
-        }
+        const double nrm = sqrt(nu2);
+        beta = (alpha >= 0.0) ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
     }
-#pragma unroll
-    for (int c = 0; c < CPW; ++c) {
-        const int64_t j = colbase + c;
-        alive[c] = j < n;
-        if (alive[c] && lane == 0) a.pos[j] = -1;
-    }
-    // trailing squared norms for step 0
-    double nu[CPW];
-#pragma unroll
-    for (int c = 0; c < CPW; ++c) {
-        double s = 0.0;
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) s = fma(y[c][r], y[c][r], s);
-        nu[c] = s;
-    }
-    wave_sum_many<CPW>(nu);
+}
 
-    int64_t keff = a.k;
-    for (int64_t t = 0; t < a.k; ++t) {
-        const int par = (int)(t & 1);
-        double* slots = a.slot + (size_t)par * a.nb * S;
-        // ---- 1. the wave's best live column (largest norm, smallest index)
-        double bnu = -1.0;
-        int64_t bj = INT64_MAX;
-        int bc = -1;
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-            const int64_t j = colbase + c;
-            if (alive[c] && better(nu[c], j, bnu, bj)) {
-                bnu = nu[c];
-                bj = j;
-                bc = c;
-            }
-        }
-        if (lane == 0) {
-            s_nu[w] = bnu;
-            s_j[w] = bj;
-        }
-        __syncthreads();
-        // ---- 2. workgroup best -> candidate slot
-        int bw = 0;
-        {
-            double wn = s_nu[0];
-            int64_t wj = s_j[0];
-            for (int q = 1; q < NW; ++q)
-                if (better(s_nu[q], s_j[q], wn, wj)) {
-                    wn = s_nu[q];
-                    wj = s_j[q];
-                    bw = q;
-                }
-            if (threadIdx.x == 0) {
-                double* sl = slots + (size_t)blockIdx.x * S;
-                slot_store(sl, wn);
-                slot_store(sl + 1, __longlong_as_double((wj == INT64_MAX) ? -1LL : (long long)wj));
-            }
-        }
-        if (w == bw && bc >= 0) {
-            double* sl = slots + (size_t)blockIdx.x * S + 2;
-#pragma unroll
-            for (int c = 0; c < CPW; ++c) {
-                if (c != bc) continue;
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) {
-                    const int64_t i = lane + 64 * r;
-                    if (i < l) slot_store(sl + i, y[c][r]);
-                }
-            }
-            __builtin_amdgcn_s_waitcnt(0);
-        }
-        // ---- 3. device-wide barrier
-        grid_sync(a.bar, (uint32_t)(a.nb * (t + 1)));
-        // ---- 4. winner (identical in every workgroup)
-        if (ALL) {
-            // all candidate slots -> LDS, 8 loads in flight per thread
-            const int tot = a.nb * S;
-            for (int e0 = 0; e0 < tot; e0 += NT * 8) {
-                double tmp[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int e = e0 + u * NT + (int)threadIdx.x;
-                    tmp[u] = (e < tot) ? slot_load(slots + e) : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int e = e0 + u * NT + (int)threadIdx.x;
-                    if (e < tot) sm[e] = tmp[u];
-                }
-            }
-            __syncthreads();
-        }
-        {
-            double wn = -1.0;
-            int wjj = INT32_MAX;
-            for (int q = threadIdx.x; q < a.nb; q += NT) {
-                double nuq;
-                int64_t jq;
-                if (ALL) {
-                    nuq = sm[(size_t)q * S];
-                    jq = (int64_t)__double_as_longlong(sm[(size_t)q * S + 1]);
-                } else {
-                    nuq = slot_load(slots + (size_t)q * S);
-                    jq = (int64_t)__double_as_longlong(slot_load(slots + (size_t)q * S + 1));
-                }
-                if (jq >= 0 && better(nuq, jq, wn, wjj)) {
-                    wn = nuq;
-                    wjj = (int)jq;
-                }
-            }
-            wave_argmax(wn, wjj);
-            if (lane == 0) {
-                s_nu[w] = wn;
-                s_j[w] = (wjj == INT32_MAX) ? INT64_MAX : (int64_t)wjj;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double bn = s_nu[0];
-                int64_t bjj = s_j[0];
-                for (int q = 1; q < NW; ++q)
-                    if (better(s_nu[q], s_j[q], bn, bjj)) {
-                        bn = s_nu[q];
-                        bjj = s_j[q];
-                    }
-                s_wnu = bn;
-                s_wj = bjj;
-            }
-            __syncthreads();
-        }
-        const double wnu = s_wnu;
-        const int64_t wj = s_wj;
-        if (wj == INT64_MAX || !(wnu > 0.0)) {
-            keff = t;
-            break;
-        }
-        const int wblk = (int)(wj / ((int64_t)NW * CPW));
-        const double* xb;
-        if (ALL) {
-            xb = sm + (size_t)wblk * S + 2;
-        } else {
-            const double* wsl = slots + (size_t)wblk * S + 2;
-            for (int i0 = 0; i0 < (int)l; i0 += NT * 8) {
-                double tmp[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int i = i0 + u * NT + (int)threadIdx.x;
-                    tmp[u] = (i < l) ? slot_load(wsl + i) : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int i = i0 + u * NT + (int)threadIdx.x;
-                    if (i < l) sm[i] = tmp[u];
-                }
-            }
-            __syncthreads();
-            xb = sm;
-        }
-        // ---- Householder reflector of the winner's rows t..l-1 (every wave
-        //      computes it redundantly from the same LDS data: same bits)
-        double sig2 = 0.0;
-        for (int64_t i = t + 1 + lane; i < l; i += 64) sig2 = fma(xb[i], xb[i], sig2);
-        sig2 = wave_sum_dpp1(sig2);
-        const double alpha = xb[t];
-        double tau, beta, scal;
-        if (sig2 == 0.0) {
-            tau = 0.0;
-            beta = alpha;
-            scal = 0.0;
-        } else {
-            const double nrm = sqrt(alpha * alpha + sig2);
-            beta = (alpha >= 0.0) ? -nrm : nrm;
-            tau = (beta - alpha) / beta;
-            scal = 1.0 / (alpha - beta);
-        }
-        // reflector entry of row i: 0 above t, 1 at t, x_i * scal below
-        const int ti = (int)t, li = (int)l;
-        auto vof = [&](int i) -> double {
-            return (i < ti || i >= li) ? 0.0 : (i == ti ? 1.0 : xb[i] * scal);
-        };
-        constexpr bool VREG = RPL <= 8;  // tall sketches re-read v from LDS
-        double v[VREG ? RPL : 1];
-        if (VREG) {
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) v[VREG ? r : 0] = vof(lane + 64 * r);
-        }
-        // ---- 5. apply H = I - tau v v^T to the live columns, then the new
-        //      trailing norms (rows > t), all columns' reductions interleaved
-        // (tall sketches: v is re-read from LDS in chunks of 8 rows, with a
-        //  compiler barrier per chunk so only a few entries are live at once)
-        double d[CPW];
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-            double s = 0.0;
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-                s = fma(VREG ? v[VREG ? r : 0] : vof(lane + 64 * r), y[c][r], s);
-                if (!VREG && (r & 7) == 7) asm volatile("" ::: "memory");
-            }
-            d[c] = s;
-        }
-        wave_sum_many<CPW>(d);
-        if (!VREG) asm volatile("" ::: "memory");
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-            if (!alive[c]) continue;
-            const double dt = d[c] * tau;
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-                y[c][r] = fma(-dt, VREG ? v[VREG ? r : 0] : vof(lane + 64 * r), y[c][r]);
-                if (!VREG && (r & 7) == 7) asm volatile("" ::: "memory");
-            }
-            const int64_t j = colbase + c;
-            if (j == wj) {
-                alive[c] = false;
-#pragma unroll
-                for (int r = 0; r < RPL; ++r)
-                    if (lane + 64 * r == ti) y[c][r] = beta;
-                if (lane == 0) a.pos[j] = (int32_t)t;
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-            double s = 0.0;
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-                const int i = lane + 64 * r;
-                s = fma(i > ti ? y[c][r] : 0.0, y[c][r], s);
-            }
-            nu[c] = s;
-        }
-        wave_sum_many<CPW>(nu);
-        if (blockIdx.x == 0 && threadIdx.x == 0) a.J[t] = wj;
-        __syncthreads();  // LDS is rewritten next step
-    }
-
-    // top keff rows of every column = R[0:keff, j]
-#pragma unroll
-    for (int c = 0; c < CPW; ++c) {
-        const int64_t j = colbase + c;
-        if (j >= n) continue;
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const int64_t i = lane + 64 * r;
-            if (i < keff) a.Rt[j * a.k + i] = y[c][r];
-        }
-    }
+__device__ __forceinline__ void finish(const SelArgs& a, int keff) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const bool timed_out = __hip_atomic_load(a.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        const bool timed_out = __hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
         *a.keff = timed_out ? -1 : keff;
         for (int64_t t = keff; t < a.k; ++t) a.J[t] = -1;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Short sketches (l <= 256): lane-column layout.  A group of G lanes holds one
-// column (lane part p holds rows [p*R, p*R + R)), so a wave holds 64/G
-// columns and the dot products and norms of a column are lane-local sums
-// combined over only log2(G) lane exchanges.  Same step structure, slot
-// protocol and arithmetic definitions as cpqr_kernel.
-// ---------------------------------------------------------------------------
-template <int N>
-__device__ __forceinline__ double tree_sum(double (&s)[N]) {
-#pragma unroll
-    for (int h = N / 2; h > 0; h >>= 1)
-#pragma unroll
-        for (int q = 0; q < h; ++q) s[q] += s[q + h];
-    return s[0];
-}
-
-template <int G>
-__device__ __forceinline__ double part_sum(double v) {
-#pragma unroll
-    for (int o = 64 / G; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-template <int G, int R, int NW, bool ALL>
-__global__ __launch_bounds__(NW * 64) void cpqr_lc_kernel(SelArgs a) {
-    extern __shared__ double sm[];
-    __shared__ double s_nu[NW];
-    __shared__ int64_t s_j[NW];
-    __shared__ double s_wnu;
-    __shared__ int64_t s_wj;
-    constexpr int NT = NW * 64;
-    constexpr int CPWV = 64 / G;  // columns per wave
-
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int cl = lane % CPWV;   // column within the wave
-    const int p = lane / CPWV;    // row part
-    const int64_t j = ((int64_t)blockIdx.x * NW + w) * CPWV + cl;
-    const int64_t l = a.l, n = a.n;
-    const int S = a.S;
-    const int64_t row0 = (int64_t)p * R;
-
-    double y[R];
-    bool alive = j < n;
-    {
-        const int64_t jc = min(j, n - 1);
-        if (a.ydt == IDS_F64) {
-            const double* Yp = (const double*)a.Y;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = (int)row0 + r;
-                const double v = Yp[(int64_t)min(i, (int)l - 1) * a.rs + jc * a.cs];
-                y[r] = (alive && i < l) ? v : 0.0;
-            }
-        } else {
-            const float* Yp = (const float*)a.Y;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = (int)row0 + r;
-                const double v = (double)Yp[(int64_t)min(i, (int)l - 1) * a.rs + jc * a.cs];
-                y[r] = (alive && i < l) ? v : 0.0;
-            }
-        }
-    }
-    if (alive && p == 0) a.pos[j] = -1;
-    // sums over a lane's rows use NACC interleaved accumulators (fixed order)
-    constexpr int NACC = R >= 8 ? 8 : R;
-    double nu;
-    {
-        double s[NACC];
-#pragma unroll
-        for (int q = 0; q < NACC; ++q) s[q] = 0.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) s[r % NACC] = fma(y[r], y[r], s[r % NACC]);
-        nu = part_sum<G>(tree_sum<NACC>(s));
-    }
-
-    int64_t keff = a.k;
-    for (int64_t t = 0; t < a.k; ++t) {
-        const int par = (int)(t & 1);
-        double* slots = a.slot + (size_t)par * a.nb * S;
-        // ---- 1. wave best, 2. workgroup best -> slot
-        double wn = alive ? nu : -1.0;
-        int wjj = alive ? (int)j : INT32_MAX;
-        wave_argmax(wn, wjj);
-        if (lane == 0) {
-            s_nu[w] = wn;
-            s_j[w] = (wjj == INT32_MAX) ? INT64_MAX : (int64_t)wjj;
-        }
-        __syncthreads();
-        {
-            double bn = s_nu[0];
-            int64_t bj = s_j[0];
-            for (int q = 1; q < NW; ++q)
-                if (better(s_nu[q], s_j[q], bn, bj)) {
-                    bn = s_nu[q];
-                    bj = s_j[q];
-                }
-            if (threadIdx.x == 0) {
-                double* sl = slots + (size_t)blockIdx.x * S;
-                slot_store(sl, bn);
-                slot_store(sl + 1, __longlong_as_double((bj == INT64_MAX) ? -1LL : (long long)bj));
-            }
-            if (alive && j == bj) {
-                double* sl = slots + (size_t)blockIdx.x * S + 2;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int64_t i = row0 + r;
-                    if (i < l) slot_store(sl + i, y[r]);
-                }
-                __builtin_amdgcn_s_waitcnt(0);
-            }
-        }
-        // ---- 3. device-wide barrier
-        grid_sync(a.bar, (uint32_t)(a.nb * (t + 1)));
-        // ---- 4. winner
-        if (ALL) {
-            const int tot = a.nb * S;
-            for (int e0 = 0; e0 < tot; e0 += NT * 8) {
-                double tmp[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int e = e0 + u * NT + (int)threadIdx.x;
-                    tmp[u] = (e < tot) ? slot_load(slots + e) : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int e = e0 + u * NT + (int)threadIdx.x;
-                    if (e < tot) sm[e] = tmp[u];
-                }
-            }
-            __syncthreads();
-        }
-        {
-            double bn = -1.0;
-            int bjj = INT32_MAX;
-            for (int q = threadIdx.x; q < a.nb; q += NT) {
-                double nuq;
-                int64_t jq;
-                if (ALL) {
-                    nuq = sm[(size_t)q * S];
-                    jq = (int64_t)__double_as_longlong(sm[(size_t)q * S + 1]);
-                } else {
-                    nuq = slot_load(slots + (size_t)q * S);
-                    jq = (int64_t)__double_as_longlong(slot_load(slots + (size_t)q * S + 1));
-                }
-                if (jq >= 0 && better(nuq, jq, bn, bjj)) {
-                    bn = nuq;
-                    bjj = (int)jq;
-                }
-            }
-            wave_argmax(bn, bjj);
-            if (lane == 0) {
-                s_nu[w] = bn;
-                s_j[w] = (bjj == INT32_MAX) ? INT64_MAX : (int64_t)bjj;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double b2 = s_nu[0];
-                int64_t j2 = s_j[0];
-                for (int q = 1; q < NW; ++q)
-                    if (better(s_nu[q], s_j[q], b2, j2)) {
-                        b2 = s_nu[q];
-                        j2 = s_j[q];
-                    }
-                s_wnu = b2;
-                s_wj = j2;
-            }
-            __syncthreads();
-        }
-        const double wnu = s_wnu;
-        const int64_t wj = s_wj;
-        if (wj == INT64_MAX || !(wnu > 0.0)) {
-            keff = t;
-            break;
-        }
-        const int wblk = (int)(wj / ((int64_t)NW * CPWV));
-        const double* xb;
-        if (ALL) {
-            xb = sm + (size_t)wblk * S + 2;
-        } else {
-            const double* wsl = slots + (size_t)wblk * S + 2;
-            for (int i = threadIdx.x; i < (int)l; i += NT) sm[i] = slot_load(wsl + i);
-            __syncthreads();
-            xb = sm;
-        }
-        // ---- Householder reflector (every wave, same bits)
-        double sig2 = 0.0;
-        for (int64_t i = t + 1 + lane; i < l; i += 64) sig2 = fma(xb[i], xb[i], sig2);
-        sig2 = wave_sum_dpp1(sig2);
-        const double alpha = xb[t];
-        double tau, beta, scal;
-        if (sig2 == 0.0) {
-            tau = 0.0;
-            beta = alpha;
-            scal = 0.0;
-        } else {
-            const double nrm = sqrt(alpha * alpha + sig2);
-            beta = (alpha >= 0.0) ? -nrm : nrm;
-            tau = (beta - alpha) / beta;
-            scal = 1.0 / (alpha - beta);
-        }
-        // ---- 5. apply to the live column held by this lane group
-        double dsum;
-        {
-            double s[NACC];
-#pragma unroll
-            for (int q = 0; q < NACC; ++q) s[q] = 0.0;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t i = row0 + r;
-                const double v = (i < t || i >= l) ? 0.0 : (i == t ? 1.0 : xb[i] * scal);
-                s[r % NACC] = fma(v, y[r], s[r % NACC]);
-            }
-            dsum = part_sum<G>(tree_sum<NACC>(s));
-        }
-        asm volatile("" ::: "memory");
-        if (alive) {
-            const double dt = dsum * tau;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t i = row0 + r;
-                const double v = (i < t || i >= l) ? 0.0 : (i == t ? 1.0 : xb[i] * scal);
-                y[r] = fma(-dt, v, y[r]);
-            }
-            if (j == wj) {
-                alive = false;
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    if (row0 + r == t) y[r] = beta;
-                if (p == 0) a.pos[j] = (int32_t)t;
-            }
-        }
-        {
-            double s[NACC];
-#pragma unroll
-            for (int q = 0; q < NACC; ++q) s[q] = 0.0;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t i = row0 + r;
-                if (i > t) s[r % NACC] = fma(y[r], y[r], s[r % NACC]);
-            }
-            nu = part_sum<G>(tree_sum<NACC>(s));
-        }
-        if (blockIdx.x == 0 && threadIdx.x == 0) a.J[t] = wj;
-        __syncthreads();
-    }
-
-    if (j < n) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t i = row0 + r;
-            if (i < keff) a.Rt[j * a.k + i] = y[r];
-        }
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const bool timed_out = __hip_atomic_load(a.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-        *a.keff = timed_out ? -1 : keff;
-        for (int64_t t = keff; t < a.k; ++t) a.J[t] = -1;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Short sketches, grouped-lane layout: column c of a wave lives in the G
-// consecutive lanes 8..: lane = G*c + p holds rows [p*R, p*R + R) of it.  Column
-// sums are G-lane DPP trees (quad_perm, half-mirror, mirror: every lane of the
-// group ends with the same bits); updates are branch-free; every wave resolves
-// the workgroup and device argmax itself from LDS, so a step has three
-// workgroup barriers plus the device-wide one.
+// Short sketches (l <= 256), grouped-lane layout: column c of a wave lives in
+// the G consecutive lanes G*c .. G*c+G-1; lane part p holds rows
+// [p*R, p*R + R).  Column sums are G-lane DPP trees (quad_perm, half-mirror,
+// mirror: every lane of the group ends with the same bits); updates are
+// branch-free.  The workgroup's best column is published once per step; the
+// LDS buffers alternate with the step parity, so a step has three workgroup
+// barriers (best, vote, winner column).
 // ---------------------------------------------------------------------------
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
@@ -694,22 +252,27 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
-template <int G, int R, int NW, bool ALL>
+template <int G, int R, int NW, int MODE>
 __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
-    extern __shared__ double sm[];
-    __shared__ double s_nu[NW];
-    __shared__ int s_j[NW];
+    extern __shared__ double sm[];  // two winner-column buffers (step parity)
+    __shared__ double s_nu[2][NW];
+    __shared__ int s_j[2][NW];
+    __shared__ double s_vn[2][NW];
+    __shared__ int s_vj[2][NW];
     constexpr int NT = NW * 64;
     constexpr int CPWV = 64 / G;  // columns per wave
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int p = lane % G;       // row part
-    const int wcol0 = (blockIdx.x * NW + w) * CPWV;
-    const int j = wcol0 + lane / G;
+    const int j = (blockIdx.x * NW + w) * CPWV + lane / G;
     const int n = (int)a.n, l = (int)a.l;
     const int S = a.S;
     const int row0 = p * R;
+    constexpr int LP = G * R;     // rows covered (>= l)
+    constexpr int PSH = ilog2(R); // LDS row padding (R is a power of two)
+    static_assert((1 << PSH) == R, "rows per lane must be a power of two");
+    constexpr int LB = LP + LP / R;  // doubles per LDS buffer
 
     double y[R];
     bool alive = j < n;
@@ -746,116 +309,80 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
     int keff = k;
     for (int t = 0; t < k; ++t) {
         const int par = t & 1;
-        double* slots = a.slot + (size_t)par * a.nb * S;
-        // ---- wave best, then workgroup best (every wave computes it)
+        double* reg = a.mb + (size_t)t * a.RS;
+        // ---- workgroup best (every wave computes it), published once
         {
             double wn = alive ? nu : -1.0;
-            int wj = alive ? j : INT32_MAX;
-            wave_argmax(wn, wj);
+            int wjw = alive ? j : INT32_MAX;
+            wave_argmax(wn, wjw);
             if (lane == 0) {
-                s_nu[w] = wn;
-                s_j[w] = wj;
+                s_nu[par][w] = wn;
+                s_j[par][w] = wjw;
             }
         }
         __syncthreads();
-        double bn = (lane < NW) ? s_nu[lane] : -1.0;
-        int bj = (lane < NW) ? s_j[lane] : INT32_MAX;
+        double bn = (lane < NW) ? s_nu[par][lane] : -1.0;
+        int bj = (lane < NW) ? s_j[par][lane] : INT32_MAX;
         wave_argmax(bn, bj);
+        double* hd = (MODE == MB_OWNER) ? reg + 2 * blockIdx.x : reg + (size_t)blockIdx.x * S;
         if (threadIdx.x == 0) {
-            double* sl = slots + (size_t)blockIdx.x * S;
-            slot_store(sl, bn);
-            slot_store(sl + 1, __longlong_as_double((bj == INT32_MAX) ? -1LL : (long long)bj));
+            mb_put(hd, bn);
+            mb_put(hd + 1, idx_bits(bj == INT32_MAX ? -1 : bj));
         }
-        if (j == bj) {  // the G lanes of the workgroup's best column publish it
-            double* sl = slots + (size_t)blockIdx.x * S + 2 + row0;
+        if (MODE == MB_SPEC && j == bj) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (row0 + r < l) slot_store(sl + r, y[r]);
-            __builtin_amdgcn_s_waitcnt(0);
+                if (row0 + r < l) mb_put(hd + 2 + row0 + r, y[r]);
         }
-        // ---- device-wide barrier
-        grid_sync(a.bar, (uint32_t)(a.nb * (t + 1)));
-        // ---- every wave finds the winner
-        if (ALL) {
-            const int tot = a.nb * S;
-            for (int e0 = 0; e0 < tot; e0 += NT * 8) {
-                double tmp[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int e = e0 + u * NT + (int)threadIdx.x;
-                    tmp[u] = (e < tot) ? slot_load(slots + e) : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int e = e0 + u * NT + (int)threadIdx.x;
-                    if (e < tot) sm[e] = tmp[u];
-                }
-            }
-            __syncthreads();
-        }
-        double wnu = -1.0;
-        int wj = INT32_MAX;
-        for (int q = lane; q < a.nb; q += 64) {
-            double nq;
-            long long jq;
-            if (ALL) {
-                nq = sm[(size_t)q * S];
-                jq = __double_as_longlong(sm[(size_t)q * S + 1]);
-            } else {
-                nq = slot_load(slots + (size_t)q * S);
-                jq = __double_as_longlong(slot_load(slots + (size_t)q * S + 1));
-            }
-            if (jq >= 0 && (nq > wnu || (nq == wnu && (int)jq < wj))) {
-                wnu = nq;
-                wj = (int)jq;
-            }
-        }
-        wave_argmax(wnu, wj);
+        // ---- vote, winner column -> LDS
+        double wnu;
+        int wj;
+        vote_hdr<NW>(a, reg, MODE == MB_OWNER ? 2 : S, s_vn[par], s_vj[par], wnu, wj);
         if (wj == INT32_MAX || !(wnu > 0.0)) {
             keff = t;
             break;
         }
-        const int wblk = wj / (NW * CPWV);
-        const double* xb;
-        if (ALL) {
-            xb = sm + (size_t)wblk * S + 2;
+        double* xb = sm + par * LB;
+        if (MODE == MB_SPEC) {
+            fetch_col_lds<NT, PSH>(a, reg + (size_t)(wj / (NW * CPWV)) * S + 2, l, LP, xb);
         } else {
-            const double* wsl = slots + (size_t)wblk * S + 2;
-            for (int i = threadIdx.x; i < l; i += NT) sm[i] = slot_load(wsl + i);
-            __syncthreads();
-            xb = sm;
+            double* cb = reg + a.H0;
+            if (j == wj) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (row0 + r < l) mb_put(cb + row0 + r, y[r]);
+            }
+            fetch_col_lds<NT, PSH>(a, cb, l, LP, xb);
         }
         // ---- Householder reflector (every wave, same bits)
-        double sig2 = 0.0;
-        for (int i = t + 1 + lane; i < l; i += 64) sig2 = fma(xb[i], xb[i], sig2);
-        sig2 = wave_sum_dpp1(sig2);
-        const double alpha = xb[t];
         double tau, beta, scal;
-        if (sig2 == 0.0) {
-            tau = 0.0;
-            beta = alpha;
-            scal = 0.0;
-        } else {
-            const double nrm = sqrt(alpha * alpha + sig2);
-            beta = (alpha >= 0.0) ? -nrm : nrm;
-            tau = (beta - alpha) / beta;
-            scal = 1.0 / (alpha - beta);
-        }
-        double v[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
+        reflector(xb[t + (t >> PSH)], wnu, tau, beta, scal);
+        // reflector entry of row row0 + r: 0 above t, 1 at t, x_i scal below
+        // (rows >= l read the LDS zero padding).  Short lane parts keep v in
+        // registers; long ones re-read it from LDS in the update.
+        auto vof = [&](int r) -> double {
             const int i = row0 + r;
-            const double xi = xb[min(i, l - 1)];
-            v[r] = (i < t || i >= l) ? 0.0 : (i == t ? 1.0 : xi * scal);
+            const double xi = xb[i + (i >> PSH)];
+            return (i < t) ? 0.0 : (i == t ? 1.0 : xi * scal);
+        };
+        constexpr bool VREG = R <= 16;
+        double v[VREG ? R : 1];
+        if (VREG) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[VREG ? r : 0] = vof(r);
         }
         // ---- apply H (branch-free: dead columns get a zero multiplier)
-        double d = 0.0;
+        double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) d = fma(v[r], y[r], d);
-        d = group_sum<G>(d);
+        for (int r = 0; r < R; r += 2) {
+            d0 = fma(VREG ? v[VREG ? r : 0] : vof(r), y[r], d0);
+            if (r + 1 < R) d1 = fma(VREG ? v[VREG ? r + 1 : 0] : vof(r + 1), y[r + 1], d1);
+        }
+        const double d = group_sum<G>(d0 + d1);
         const double dt = alive ? d * tau : 0.0;
+        if (!VREG) asm volatile("" ::: "memory");
 #pragma unroll
-        for (int r = 0; r < R; ++r) y[r] = fma(-dt, v[r], y[r]);
+        for (int r = 0; r < R; ++r) y[r] = fma(-dt, VREG ? v[VREG ? r : 0] : vof(r), y[r]);
         if (j == wj) {
             alive = false;
 #pragma unroll
@@ -865,16 +392,20 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
         }
         // ---- trailing norms for the next step (rows > t)
         {
-            double s = 0.0;
+            double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const double yr = (row0 + r > t) ? y[r] : 0.0;
-                s = fma(yr, yr, s);
+            for (int r = 0; r < R; r += 2) {
+                const double y0 = (row0 + r > t) ? y[r] : 0.0;
+                s0 = fma(y0, y0, s0);
+                if (r + 1 < R) {
+                    const double y1 = (row0 + r + 1 > t) ? y[r + 1] : 0.0;
+                    s1 = fma(y1, y1, s1);
+                }
             }
-            nu = group_sum<G>(s);
+            nu = group_sum<G>(s0 + s1);
         }
         if (blockIdx.x == 0 && threadIdx.x == 0) a.J[t] = wj;
-        __syncthreads();  // LDS is rewritten next step
+        // no barrier here: the LDS buffers alternate with the step parity
     }
 
     if (j < n) {
@@ -884,197 +415,239 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
             if (i < keff) a.Rt[(int64_t)j * a.k + i] = y[r];
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const bool timed_out = __hip_atomic_load(a.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-        *a.keff = timed_out ? -1 : keff;
-        for (int t = keff; t < a.k; ++t) a.J[t] = -1;
-    }
+    finish(a, keff);
 }
 
 // ---------------------------------------------------------------------------
-// Tall sketches (2048 < l <= 64 * (RREG + RLDS)): one column per wave; rows
-// lane + 64 r, r < RREG, in registers and the remaining RLDS chunks of 64 rows
-// in LDS (per wave), so a 4096-row FP64 column fits beside the winner's copy.
-// Same step structure and arithmetic as cpqr_kernel.
+// Long sketches (256 < l <= 4096), row-band layout: a workgroup of 8 waves
+// owns NC columns; wave w holds rows [64 RB w, 64 RB (w + 1)) of all of them,
+// row 64 RB w + 64 r + lane in y[c][r].  Each wave reads only its rows of the
+// winner's column, straight into registers.  With
+// v^T y_c = y_c[t] + scal * sum_{i>t} x_i y_ci, one workgroup reduction gives
+// all NC dot products, a second the new trailing norms.
 // ---------------------------------------------------------------------------
-template <int RREG, int RLDS, int NW>
-__global__ __launch_bounds__(NW * 64) void cpqr_tall_kernel(SelArgs a) {
-    extern __shared__ double sm[];
-    constexpr int LP = 64 * (RREG + RLDS);           // rows covered (>= l)
-    double* xb = sm;                                 // winner column, LP entries (zero past l)
-    double* yl = sm + LP;                            // NW x RLDS x 64 rows held in LDS
-    __shared__ double s_nu[NW];
-    __shared__ int s_j[NW];
-    constexpr int NT = NW * 64;
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int j = blockIdx.x * NW + w;
-    const int n = (int)a.n, l = (int)a.l, S = a.S;
-    double* myl = yl + (size_t)w * RLDS * 64 + lane;  // chunk RREG + q of this lane at myl[64 q]
-
-    // Row i = lane + 64 r.  Predicates on i are uniform per chunk r except for
-    // the one chunk that contains the boundary, which keeps the masks scalar.
-    double y[RREG];
-    bool alive = j < n;
-    {
-        const int64_t jc = min(j, n - 1);
-        auto ld = [&](int i) -> double {
-            double v;
-            if (a.ydt == IDS_F64)
-                v = ((const double*)a.Y)[(int64_t)min(i, l - 1) * a.rs + jc * a.cs];
-            else
-                v = (double)((const float*)a.Y)[(int64_t)min(i, l - 1) * a.rs + jc * a.cs];
-            return (alive && i < l) ? v : 0.0;
-        };
+// Sums over the workgroup of M per-lane values: the partials go to LDS
+// (red[w][m][lane]), wave m mod NW adds entry m over the waves and then over
+// its lanes, and every thread reads the M totals back.  The order is fixed,
+// so every workgroup gets the same bits for the same data.
+template <int M, int NW>
+__device__ __forceinline__ void wg_sum_t(double (&v)[M], double* red, double* res) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-        for (int r = 0; r < RREG; ++r) y[r] = ld(lane + 64 * r);
-        for (int q = 0; q < RLDS; ++q) myl[64 * q] = ld(lane + 64 * (RREG + q));
+    for (int m = 0; m < M; ++m) red[(w * M + m) * 64 + lane] = v[m];
+    __syncthreads();
+#pragma unroll
+    for (int mm = 0; mm < (M + NW - 1) / NW; ++mm) {
+        const int m = w + NW * mm;
+        if (m < M) {
+            double s = red[m * 64 + lane];
+#pragma unroll
+            for (int q = 1; q < NW; ++q) s += red[(q * M + m) * 64 + lane];
+            s = wave_sum_dpp1(s);
+            if (lane == 0) res[m] = s;
+        }
     }
-    if (alive && lane == 0) a.pos[j] = -1;
-    // sum of squares over rows i >= from
-    auto trailing = [&](int from) -> double {
-        const int c0 = from >> 6, lo = from & 63;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = res[m];
+}
+
+template <int NC, int RB>
+__device__ __forceinline__ double ysel(const double (&y)[NC][RB], int c, int r) {
+    double v = 0.0;
+#pragma unroll
+    for (int cc = 0; cc < NC; ++cc)
+        if (cc == c) v = y[cc][r];
+    return v;
+}
+
+constexpr int RB_NW = 8;
+template <int NC>
+constexpr size_t rb_lds_bytes() { return sizeof(double) * RB_NW * NC * 64; }
+
+template <int NC, int RB, int MODE>
+__global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
+    constexpr int NW = RB_NW;
+    constexpr int BAND = 64 * RB;  // rows per wave
+    extern __shared__ double red[];  // NW x NC x 64 partial sums
+    __shared__ double res[NC];
+    __shared__ double s_vn[2][NW];
+    __shared__ int s_vj[2][NW];
+    __shared__ double s_row[NC + 1];  // row t: y_c[t] (c < NC) and x_t (NC)
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int col0 = blockIdx.x * NC;
+    const int n = (int)a.n, l = (int)a.l;
+    const int rb0 = BAND * w + lane;  // row of y[c][r] is rb0 + 64 r
+
+    double y[NC][RB];
+    bool alive[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const int64_t jc = min(col0 + c, n - 1);
+        alive[c] = col0 + c < n;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int i = rb0 + 64 * r;
+            const int64_t off = (int64_t)min(i, l - 1) * a.rs + jc * a.cs;
+            const double v = (a.ydt == IDS_F64) ? ((const double*)a.Y)[off] : (double)((const float*)a.Y)[off];
+            y[c][r] = (alive[c] && i < l) ? v : 0.0;
+        }
+    }
+    if (w == 0 && lane < NC && col0 + lane < n) a.pos[col0 + lane] = -1;
+    double nu[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
         double s = 0.0;
 #pragma unroll
-        for (int r = 0; r < RREG; ++r) {
-            if (r < c0) continue;
-            const double yr = (r == c0 && lane < lo) ? 0.0 : y[r];
-            s = fma(yr, yr, s);
-        }
-        for (int q = max(c0 - RREG, 0); q < RLDS; ++q) {
-            const double yq = myl[64 * q];
-            const double yr = (RREG + q == c0 && lane < lo) ? 0.0 : yq;
-            s = fma(yr, yr, s);
-        }
-        return wave_sum_dpp1(s);
-    };
-    double nu = trailing(0);
+        for (int r = 0; r < RB; ++r) s = fma(y[c][r], y[c][r], s);
+        nu[c] = s;
+    }
+    wg_sum_t<NC, NW>(nu, red, res);
 
     const int k = (int)a.k;
     int keff = k;
     for (int t = 0; t < k; ++t) {
         const int par = t & 1;
-        double* slots = a.slot + (size_t)par * a.nb * S;
-        if (lane == 0) {
-            s_nu[w] = alive ? nu : -1.0;
-            s_j[w] = alive ? j : INT32_MAX;
-        }
-        __syncthreads();
-        double bn = (lane < NW) ? s_nu[lane] : -1.0;
-        int bj = (lane < NW) ? s_j[lane] : INT32_MAX;
-        wave_argmax(bn, bj);
-        if (threadIdx.x == 0) {
-            double* sl = slots + (size_t)blockIdx.x * S;
-            slot_store(sl, bn);
-            slot_store(sl + 1, __longlong_as_double((bj == INT32_MAX) ? -1LL : (long long)bj));
-        }
-        if (j == bj) {  // rows < l only: the slot holds S >= l + 2 entries
-            double* sl = slots + (size_t)blockIdx.x * S + 2 + lane;
+        double* reg = a.mb + (size_t)t * a.RS;
+        // ---- workgroup best (nu is identical in every thread)
+        double bn = -1.0;
+        int bc = -1;
 #pragma unroll
-            for (int r = 0; r < RREG; ++r)
-                if (lane + 64 * r < l) slot_store(sl + 64 * r, y[r]);
-            for (int q = 0; q < RLDS; ++q)
-                if (lane + 64 * (RREG + q) < l) slot_store(sl + 64 * (RREG + q), myl[64 * q]);
-            __builtin_amdgcn_s_waitcnt(0);
+        for (int c = 0; c < NC; ++c)
+            if (alive[c] && nu[c] > bn) {
+                bn = nu[c];
+                bc = c;
+            }
+        double* hd = (MODE == MB_OWNER) ? reg + 2 * blockIdx.x : reg + (size_t)blockIdx.x * a.S;
+        if (threadIdx.x == 0) {
+            mb_put(hd, bn);
+            mb_put(hd + 1, idx_bits(bc >= 0 ? col0 + bc : -1));
         }
-        grid_sync(a.bar, (uint32_t)(a.nb * (t + 1)));
-        double wnu = -1.0;
-        int wj = INT32_MAX;
-        for (int q = lane; q < a.nb; q += 64) {
-            const double nq = slot_load(slots + (size_t)q * S);
-            const long long jq = __double_as_longlong(slot_load(slots + (size_t)q * S + 1));
-            if (jq >= 0 && (nq > wnu || (nq == wnu && (int)jq < wj))) {
-                wnu = nq;
-                wj = (int)jq;
+        if (MODE == MB_SPEC && bc >= 0) {
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int i = rb0 + 64 * r;
+                if (i < l) mb_put(hd + 2 + i, ysel(y, bc, r));
             }
         }
-        wave_argmax(wnu, wj);
+        double wnu;
+        int wj;
+        vote_hdr<NW>(a, reg, MODE == MB_OWNER ? 2 : a.S, s_vn[par], s_vj[par], wnu, wj);
         if (wj == INT32_MAX || !(wnu > 0.0)) {
             keff = t;
             break;
         }
-        {
-            const double* wsl = slots + (size_t)(wj / NW) * S + 2;
-            const int lp = LP;
-            for (int i0 = 0; i0 < lp; i0 += NT * 8) {
-                double tmp[8];
+        const int wblk = wj / NC;
+        const double* src;
+        if (MODE == MB_OWNER) {
+            double* cb = reg + a.H0;
+            if (wblk == (int)blockIdx.x) {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int i = i0 + u * NT + (int)threadIdx.x;
-                    tmp[u] = (i < l) ? slot_load(wsl + i) : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int i = i0 + u * NT + (int)threadIdx.x;
-                    if (i < lp) xb[i] = tmp[u];
+                for (int r = 0; r < RB; ++r) {
+                    const int i = rb0 + 64 * r;
+                    if (i < l) mb_put(cb + i, ysel(y, wj - col0, r));
                 }
             }
-        }
-        __syncthreads();
-        double sig2 = 0.0;
-        for (int i = t + 1 + lane; i < l; i += 64) sig2 = fma(xb[i], xb[i], sig2);
-        sig2 = wave_sum_dpp1(sig2);
-        const double alpha = xb[t];
-        double tau, beta, scal;
-        if (sig2 == 0.0) {
-            tau = 0.0;
-            beta = alpha;
-            scal = 0.0;
+            src = cb;
         } else {
-            const double nrm = sqrt(alpha * alpha + sig2);
-            beta = (alpha >= 0.0) ? -nrm : nrm;
-            tau = (beta - alpha) / beta;
-            scal = 1.0 / (alpha - beta);
+            src = reg + (size_t)wblk * a.S + 2;
         }
-        const int c0 = t >> 6, lo = t & 63;
-        // reflector entry of chunk r for this lane: 0 above t, 1 at t, x_i scal below
-        auto vchunk = [&](int r) -> double {
-            const double x = xb[lane + 64 * r] * scal;
-            return (r == c0) ? (lane < lo ? 0.0 : (lane == lo ? 1.0 : x)) : x;
-        };
-        double d = 0.0;
+        double x[RB];
+        {
+            uint64_t xv[RB];
+            mb_read<RB>(
+                xv,
+                [&](int r) -> const double* {
+                    const int i = rb0 + 64 * r;
+                    return i < l ? src + i : nullptr;
+                },
+                a.flag);
 #pragma unroll
-        for (int r = 0; r < RREG; ++r)
-            if (r >= c0) d = fma(vchunk(r), y[r], d);
-        for (int q = max(c0 - RREG, 0); q < RLDS; ++q) d = fma(vchunk(RREG + q), myl[64 * q], d);
-        d = wave_sum_dpp1(d);
-        const double dt = alive ? d * tau : 0.0;
+            for (int r = 0; r < RB; ++r) x[r] = (rb0 + 64 * r < l) ? mb_val(xv[r]) : 0.0;
+        }
+        // ---- dot products with the rows below t
+        double pa[NC];
+        {
+            double xm[RB];
 #pragma unroll
-        for (int r = 0; r < RREG; ++r)
-            if (r >= c0) y[r] = fma(-dt, vchunk(r), y[r]);
-        for (int q = max(c0 - RREG, 0); q < RLDS; ++q) myl[64 * q] = fma(-dt, vchunk(RREG + q), myl[64 * q]);
-        if (j == wj) {
-            alive = false;
-            if (c0 < RREG) {
+            for (int r = 0; r < RB; ++r) xm[r] = (rb0 + 64 * r > t) ? x[r] : 0.0;
 #pragma unroll
-                for (int r = 0; r < RREG; ++r)
-                    if (r == c0 && lane == lo) y[r] = beta;
-            } else if (lane == lo) {
-                myl[64 * (c0 - RREG)] = beta;
+            for (int c = 0; c < NC; ++c) {
+                double s = 0.0;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) s = fma(xm[r], y[c][r], s);
+                pa[c] = s;
             }
-            if (lane == 0) a.pos[j] = t;
         }
-        nu = trailing(t + 1);
-        if (blockIdx.x == 0 && threadIdx.x == 0) a.J[t] = wj;
-        __syncthreads();
-    }
-    if (j < n) {
-        double* Rj = a.Rt + (int64_t)j * a.k;
+        if (w == t / BAND && lane == (t & 63)) {
+            const int rt = (t % BAND) >> 6;
 #pragma unroll
-        for (int r = 0; r < RREG; ++r)
-            if (lane + 64 * r < keff) Rj[lane + 64 * r] = y[r];
-        for (int q = 0; q < RLDS; ++q)
-            if (lane + 64 * (RREG + q) < keff) Rj[lane + 64 * (RREG + q)] = myl[64 * q];
+            for (int r = 0; r < RB; ++r)
+                if (r == rt) {
+                    s_row[NC] = x[r];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) s_row[c] = y[c][r];
+                }
+        }
+        wg_sum_t<NC, NW>(pa, red, res);
+        double tau, beta, scal;
+        reflector(s_row[NC], wnu, tau, beta, scal);
+        // ---- apply H to the live columns (dead ones get a zero multiplier)
+        {
+            double v[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int i = rb0 + 64 * r;
+                v[r] = (i < t) ? 0.0 : (i == t ? 1.0 : x[r] * scal);
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double dt = alive[c] ? (s_row[c] + scal * pa[c]) * tau : 0.0;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) y[c][r] = fma(-dt, v[r], y[c][r]);
+            }
+        }
+        if (wblk == (int)blockIdx.x) {
+            const int cw = wj - col0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (c == cw) {
+                    alive[c] = false;
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+                        if (rb0 + 64 * r == t) y[c][r] = beta;
+                }
+            if (threadIdx.x == 0) a.pos[wj] = t;
+        }
+        // ---- trailing norms for the next step (rows > t)
+        {
+            double msk[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) msk[r] = (rb0 + 64 * r > t) ? 1.0 : 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                double s = 0.0;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const double q = y[c][r] * msk[r];
+                    s = fma(q, q, s);
+                }
+                nu[c] = s;
+            }
+        }
+        wg_sum_t<NC, NW>(nu, red, res);
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.J[t] = wj;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const bool timed_out = __hip_atomic_load(a.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-        *a.keff = timed_out ? -1 : keff;
-        for (int t = keff; t < a.k; ++t) a.J[t] = -1;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (col0 + c >= n) continue;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int i = rb0 + 64 * r;
+            if (i < keff) a.Rt[(int64_t)(col0 + c) * a.k + i] = y[c][r];
+        }
     }
-}
-
-__global__ void zero_u32_kernel(uint32_t* p, int count) {
-    if ((int)threadIdx.x < count) p[threadIdx.x] = 0u;
+    finish(a, keff);
 }
 
 // P[:, j]: e_t for a chosen column, R11^{-1} R[0:keff, j] otherwise, by
@@ -1207,60 +780,58 @@ __global__ __launch_bounds__(256) void lambda_hat_kernel(int64_t k, int64_t n, c
 // host side
 // ---------------------------------------------------------------------------
 struct Inst {
-    int rpl, cpw, nw;
-    const void* fn_all;
-    const void* fn_one;
-    size_t lds_extra = 0;  // tall kernel: LDS-held rows (bytes per workgroup)
+    int cols;           // columns per workgroup
+    int pubs;           // candidate publishers per workgroup
+    int threads;        // threads per workgroup
+    bool gl;            // grouped-lane kernel (winner column staged in LDS)
+    int rows;           // grouped lanes: rows covered (G * R)
+    int lane_rows;      // grouped lanes: rows per lane (R)
+    size_t lds_fixed;   // dynamic LDS of a row-band kernel
+    const void* fn[2];  // per mailbox mode
 };
 
-template <int RPL, int CPW, int NW>
-static Inst inst() {
-    return {RPL, CPW, NW, (const void*)&cpqr_kernel<RPL, CPW, NW, true>,
-            (const void*)&cpqr_kernel<RPL, CPW, NW, false>};
-}
-
-// lane-column kernels: G lanes per column, R rows per lane; reported as
-// (rpl = -R, cpw = 64 / G) so the column count per workgroup is cpw * nw
-template <int G, int R, int NW>
-static Inst inst_lc() {
-    return {-R, 64 / G, NW, (const void*)&cpqr_lc_kernel<G, R, NW, true>,
-            (const void*)&cpqr_lc_kernel<G, R, NW, false>};
-}
 template <int G, int R, int NW>
 static Inst inst_gl() {
-    return {-R, 64 / G, NW, (const void*)&cpqr_gl_kernel<G, R, NW, true>,
-            (const void*)&cpqr_gl_kernel<G, R, NW, false>};
+    return {NW * (64 / G), 1, NW * 64, true, G * R, R, 0,
+            {(const void*)&cpqr_gl_kernel<G, R, NW, MB_SPEC>, (const void*)&cpqr_gl_kernel<G, R, NW, MB_OWNER>}};
+}
+template <int NC, int RB>
+static Inst inst_rb() {
+    return {NC, 1, 64 * RB_NW, false, 0, 1, rb_lds_bytes<NC>(),
+            {(const void*)&cpqr_rb_kernel<NC, RB, MB_SPEC>, (const void*)&cpqr_rb_kernel<NC, RB, MB_OWNER>}};
 }
 
 static bool pick(int64_t l, Inst& in) {
-    // grouped-lane kernels for short sketches, column-per-wave beyond 256 rows
+    // grouped-lane kernels for short sketches, row bands beyond 256 rows
     if (l <= 32) in = inst_gl<2, 16, 8>();
     else if (l <= 64) in = inst_gl<4, 16, 8>();
     else if (l <= 128) in = inst_gl<8, 16, 8>();
     else if (l <= 256) in = inst_gl<16, 16, 8>();
-    else if (l <= 512) in = inst<8, 2, 8>();
-    else if (l <= 1024) in = inst<16, 1, 8>();
-    else if (l <= 2048) in = inst<32, 1, 8>();
-    else if (l <= 4096) {
-        // 40 chunks of 64 rows in registers, 24 in LDS (12 KB per wave)
-        const void* f = (const void*)&cpqr_tall_kernel<40, 24, 8>;
-        in = {64, 1, 8, f, f, sizeof(double) * 8 * 24 * 64};
-    }
+    else if (l <= 512) in = inst_rb<16, 1>();
+    else if (l <= 1024) in = inst_rb<16, 2>();
+    else if (l <= 2048) in = inst_rb<8, 4>();
+    else if (l <= 4096) in = inst_rb<8, 8>();
     else return false;
     return true;
 }
 
-static int slot_stride(int64_t l) { return (int)((l + 2 + 31) / 32 * 32); }
-constexpr size_t ALL_SLOTS_LDS_MAX = 64 * 1024;
+static int64_t round32(int64_t x) { return (x + 31) / 32 * 32; }
+constexpr int SPEC_PUBS_MAX = 128;            // beyond: the speculative stores slow the vote
+constexpr size_t SPEC_STEP_MAX = 1u << 20;    // speculative columns of one step
+constexpr size_t SPEC_TOTAL_MAX = 64u << 20;  // speculative regions of all steps
 
-static size_t cpqr_lds(const SelectPlan& sp, bool& all) {
-    const size_t S = (size_t)slot_stride(sp.l);
-    if (sp.l > 2048) {  // tall kernel: winner column (4096 rows) + LDS-held rows
-        all = false;
-        return sizeof(double) * 64 * 64 + sizeof(double) * 8 * 24 * 64;
-    }
-    all = sizeof(double) * S * sp.nb <= ALL_SLOTS_LDS_MAX;
-    return all ? sizeof(double) * S * sp.nb : sizeof(double) * S;
+// mailbox mode and geometry (sp.l, sp.k, sp.nh set)
+static void mb_layout(SelectPlan& sp) {
+    sp.S = (int)round32(sp.l + 2);
+    const size_t step = sizeof(double) * (size_t)sp.S * sp.nh;
+    sp.mode = (sp.nh <= SPEC_PUBS_MAX && step <= SPEC_STEP_MAX && step * sp.k <= SPEC_TOTAL_MAX) ? MB_SPEC
+                                                                                                : MB_OWNER;
+    sp.H0 = (int)round32(2 * (int64_t)sp.nh);
+    sp.RS = (sp.mode == MB_OWNER) ? sp.H0 + round32(sp.l) : (int64_t)sp.S * sp.nh;
+}
+
+static size_t cpqr_lds(const SelectPlan& sp, const Inst& in) {
+    return in.gl ? 2 * sizeof(double) * (size_t)(in.rows + in.rows / in.lane_rows) : in.lds_fixed;
 }
 
 ids_status select_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp) {
@@ -1272,34 +843,36 @@ ids_status select_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp) {
     sp.l = l;
     sp.n = n;
     sp.k = k;
-    sp.rpl = in.rpl;
-    sp.cpw = in.cpw;
-    sp.nw = in.nw;
-    const int64_t per = (int64_t)in.cpw * in.nw;
-    sp.nb = (int)((n + per - 1) / per);
+    sp.cols = in.cols;
+    sp.threads = in.threads;
+    sp.nb = (int)((n + in.cols - 1) / in.cols);
+    sp.nh = sp.nb * in.pubs;
+    mb_layout(sp);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
         set_error("hipGetDevice failed");
         return IDS_EHIP;
     }
     int ncu = 0, per_cu = 0;
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    bool all = false;
-    const size_t lds = cpqr_lds(sp, all);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, all ? in.fn_all : in.fn_one, in.nw * 64, lds) !=
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        set_error("hipDeviceGetAttribute failed");
+        return IDS_EHIP;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, in.fn[sp.mode], in.threads, cpqr_lds(sp, in)) !=
         hipSuccess)
         per_cu = 1;
-    if ((int64_t)sp.nb > (int64_t)ncu * per_cu) {
+    const int64_t max_nb = std::min<int64_t>((int64_t)ncu * per_cu,
+                                             (int64_t)VOTE_PER_THREAD * in.threads / in.pubs);
+    if ((int64_t)sp.nb > max_nb) {
         set_error("id_select: n too large for the register-resident CPQR (n = " + std::to_string(n) +
-                  ", l = " + std::to_string(l) + ", max columns " + std::to_string((int64_t)ncu * per_cu * per) +
-                  ")");
+                  ", l = " + std::to_string(l) + ", max columns " + std::to_string(max_nb * in.cols) + ")");
         return IDS_EINVAL;
     }
     return IDS_OK;
 }
 
 size_t select_bytes(const SelectPlan& sp) {
-    return align256(sizeof(double) * 2 * sp.nb * (size_t)slot_stride(sp.l)) + align256(sizeof(uint32_t) * 2) +
+    return align256(sizeof(double) * (size_t)sp.k * sp.RS) + align256(sizeof(uint32_t) * 2) +
            align256(sizeof(double) * (size_t)sp.n * sp.k) + align256(sizeof(int32_t) * (size_t)sp.n);
 }
 
@@ -1315,12 +888,14 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
     a.k = sp.k;
     a.J = J;
     a.keff = keff;
-    a.nb = sp.nb;
-    a.S = slot_stride(sp.l);
+    a.nh = sp.nh;
+    a.S = sp.S;
+    a.H0 = sp.H0;
+    a.RS = sp.RS;
     char* p = ws;
-    a.slot = (double*)p;
-    p += align256(sizeof(double) * 2 * sp.nb * (size_t)a.S);
-    a.bar = (uint32_t*)p;
+    a.mb = (double*)p;
+    p += align256(sizeof(double) * (size_t)sp.k * sp.RS);
+    a.flag = (uint32_t*)p;
     p += align256(sizeof(uint32_t) * 2);
     a.Rt = (double*)p;
     p += align256(sizeof(double) * (size_t)sp.n * sp.k);
@@ -1328,14 +903,14 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
 
     Inst in;
     pick(sp.l, in);
-    bool all = false;
-    const size_t lds = cpqr_lds(sp, all);
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, st, a.bar, 2);
+    const int64_t cnt = sp.k * sp.RS;
+    const unsigned fg = (unsigned)std::min<int64_t>((cnt + 255) / 256, 4096);
+    hipLaunchKernelGGL(mb_fill_kernel, dim3(fg), dim3(256), 0, st, (uint64_t*)a.mb, cnt, a.flag);
     void* args[] = {&a};
     {
         ProfScope ps(PK_CPQR, st);
-        hipError_t e = hipLaunchCooperativeKernel(all ? in.fn_all : in.fn_one, dim3(sp.nb), dim3(in.nw * 64), args,
-                                                  (unsigned)lds, st);
+        hipError_t e = hipLaunchCooperativeKernel(in.fn[sp.mode], dim3(sp.nb), dim3(in.threads), args,
+                                                  (unsigned)cpqr_lds(sp, in), st);
         if (e != hipSuccess) {
             set_error(std::string("cpqr cooperative launch: ") + hipGetErrorString(e));
             return IDS_EHIP;

@@ -56,7 +56,10 @@ ids_status project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void* G
 // ---- CPQR + interpolation matrix --------------------------------------------
 struct SelectPlan {
     int64_t l, n, k;
-    int rpl, cpw, nw, nb;  // rows per lane, columns per wave, waves per WG, WGs
+    int cols, threads, nb;  // columns per workgroup, threads per workgroup, workgroups
+    int nh;                 // candidate publishers per step
+    int mode, S, H0;        // mailbox exchange: mode, slot stride, column box offset
+    int64_t RS;             // mailbox doubles per factorisation step
 };
 ids_status select_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp);
 size_t select_bytes(const SelectPlan& sp);

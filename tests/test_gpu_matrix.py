@@ -148,8 +148,13 @@ def test_projection_f32():
 # ---------------------------------------------------------------------------
 # select (Algorithm 1)
 # ---------------------------------------------------------------------------
+# shapes cover every kernel family (grouped lanes up to 256 rows, row bands of
+# 512 / 1024 / 2048 / 4096 rows) and every candidate exchange (whole region,
+# speculative columns, owner-published column)
 @pytest.mark.parametrize("l,n,k", [(30, 1000, 20), (12, 40, 5), (64, 64, 40), (120, 2000, 100), (60, 20000, 50),
-                                   (130, 700, 130), (300, 900, 64), (1500, 600, 50), (4096, 300, 30),
+                                   (130, 700, 130), (200, 6000, 150), (300, 900, 64), (400, 3000, 120),
+                                   (700, 400, 30), (800, 1200, 90), (900, 2400, 60), (1500, 600, 50),
+                                   (1500, 2000, 40), (4096, 300, 30),
                                    (3000, 500, 40), (2049, 260, 70), (4096, 2000, 12)])
 def test_select_f64(l, n, k):
     g = np.random.default_rng(l + n + k)
@@ -176,10 +181,11 @@ def test_select_column_major_f32_input():
     assert np.linalg.norm(P.cpu().numpy() - Po) <= 1e-10 * np.linalg.norm(Po)
 
 
-def test_select_rank_deficient():
+@pytest.mark.parametrize("l,n", [(10, 40), (60, 20000), (200, 6000), (300, 900), (3000, 500)])
+def test_select_rank_deficient(l, n):
     g = np.random.default_rng(6)
-    Y = np.zeros((10, 40))
-    Y[:, [3, 17, 29]] = g.standard_normal((10, 3))
+    Y = np.zeros((l, n))
+    Y[:, [3, 17, 29]] = g.standard_normal((l, 3))
     J, P, keff = ids.id_select(dev(Y), 6)
     Jo, Po, ko, _, _ = oracle.cpqr_id(Y, 6)
     assert int(keff.item()) == ko == 3
