@@ -381,8 +381,9 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
     double* Yout = Y ? Y : Yw;
     {
         ProfScope ps(PK_PLAN, st);
-        for (int n = 0; n < N; ++n)
-            if ((s = plan_build(T.ps[n], stream_key(seed, (uint64_t)n + 1), nullptr, nullptr, pb[n], st))) return s;
+        uint64_t keys[8];
+        for (int n = 0; n < N; ++n) keys[n] = stream_key(seed, (uint64_t)n + 1);
+        if ((s = plan_build_many(N, T.ps, keys, pb, st))) return s;
         if ((s = twiddles(Jlen, tw, st))) return s;
     }
     {

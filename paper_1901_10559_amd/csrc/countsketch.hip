@@ -5,7 +5,7 @@
 //   1. plan: every row i gets (h(i), D_ii) from the counter-based hash; a
 //      stable counting sort groups the signed row codes by bucket, rows of a
 //      bucket in increasing order (plan_count -> plan_rowscan -> plan_offsets
-//      -> plan_place).
+//      -> plan_place; one workgroup per plan for small inputs).
 //   2. dense gather: workgroup (panel, bucket) walks the rows of its bucket and
 //      accumulates them in registers, 16-byte loads per lane, several rows in
 //      flight, then writes its slice of Y1 once.  Every entry of Y1 is the sum
@@ -147,8 +147,94 @@ __global__ __launch_bounds__(64) void plan_place_kernel(PlanArgs a) {
     }
 }
 
-ids_status plan_build(const PlanShape& ps, uint64_t key, const int64_t* fr_pi, const int32_t* fr_x,
-                      const PlanBufs& pb, hipStream_t st) {
+// Small inputs (m <= PLAN_SMALL_M): the whole plan in one workgroup per plan,
+// one launch for several plans.  PS_W waves each own a contiguous quarter of
+// the rows: per-wave LDS histograms, one scan that turns them into per-wave
+// start offsets (bucket-major, waves in row order, so placement stays
+// stable), then each wave places its rows 64 at a time in increasing order.
+constexpr int PS_W = 4;
+constexpr int64_t PLAN_SMALL_M = 8192;
+constexpr int64_t PLAN_SMALL_L = 6144;  // PS_W x L int32 counters in LDS
+constexpr int PLAN_MANY = 8;
+struct PlanSmallArgs {
+    PlanArgs p[PLAN_MANY];
+};
+
+__global__ __launch_bounds__(64 * PS_W) void plan_small_kernel(PlanSmallArgs s) {
+    extern __shared__ int32_t h[];  // PS_W x L
+    __shared__ int32_t part[64 * PS_W];
+    const PlanArgs& a = s.p[blockIdx.x];
+    constexpr int NT = 64 * PS_W;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t L = a.L;
+    for (int64_t e = tid; e < PS_W * L; e += NT) h[e] = 0;
+    __syncthreads();
+    const int64_t per = (a.m + PS_W - 1) / PS_W;
+    const int64_t r0 = min(a.m, w * per), r1 = min(a.m, r0 + per);
+    for (int64_t i = r0 + lane; i < r1; i += 64) {
+        uint32_t b;
+        bool neg;
+        plan_hash(a, i, b, neg);
+        atomicAdd(&h[w * L + b], 1);
+    }
+    __syncthreads();
+    // thread t owns buckets [t cb, t cb + cb): totals, block scan, then
+    // h[w][b] <- start of wave w's rows of bucket b
+    const int64_t cb = (L + NT - 1) / NT;
+    const int64_t b0 = min(L, tid * cb), b1 = min(L, b0 + cb);
+    int32_t sum = 0;
+    for (int64_t b = b0; b < b1; ++b)
+#pragma unroll
+        for (int q = 0; q < PS_W; ++q) sum += h[q * L + b];
+    part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < NT; o <<= 1) {
+        const int32_t v = (tid >= o) ? part[tid - o] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int32_t run = part[tid] - sum;
+    for (int64_t b = b0; b < b1; ++b) {
+        a.off[b] = run;
+#pragma unroll
+        for (int q = 0; q < PS_W; ++q) {
+            const int32_t c = h[q * L + b];
+            h[q * L + b] = run;
+            run += c;
+        }
+    }
+    if (tid == NT - 1) a.off[L] = (int32_t)a.m;
+    __syncthreads();
+    // stable placement, wave w over its rows in order (no other wave touches
+    // h[w][.], and the read of a bucket's start precedes its update in the wave)
+    int32_t* hw = h + w * L;
+    for (int64_t c0 = r0; c0 < r1; c0 += 64) {
+        const int64_t i = c0 + lane;
+        const bool valid = i < r1;
+        uint32_t b = 0xffffffffu;
+        bool neg = false;
+        if (valid) plan_hash(a, i, b, neg);
+        int rank = 0, same = 0;
+#pragma unroll 8
+        for (int q = 0; q < 64; ++q) {
+            const uint32_t bq = __shfl(b, q, 64);
+            const int eq = (bq == b) ? 1 : 0;
+            rank += (q < lane) ? eq : 0;
+            same += eq;
+        }
+        const int32_t base = valid ? hw[b] : 0;
+        if (valid) {
+            a.rows[base + rank] = encode_row(i, neg);
+            if (rank == same - 1) hw[b] = base + same;
+        }
+    }
+}
+
+static bool plan_is_small(const PlanShape& ps) { return ps.m <= PLAN_SMALL_M && ps.L <= PLAN_SMALL_L; }
+
+static PlanArgs plan_args(const PlanShape& ps, uint64_t key, const int64_t* fr_pi, const int32_t* fr_x,
+                          const PlanBufs& pb) {
     PlanArgs a;
     a.m = ps.m;
     a.L = (uint32_t)ps.L;
@@ -160,6 +246,37 @@ ids_status plan_build(const PlanShape& ps, uint64_t key, const int64_t* fr_pi, c
     a.seg = pb.seg;
     a.off = pb.off;
     a.rows = pb.rows;
+    return a;
+}
+
+ids_status plan_build_many(int count, const PlanShape* ps, const uint64_t* keys, const PlanBufs* pb,
+                           hipStream_t st) {
+    bool small = count <= PLAN_MANY;
+    int64_t Lmax = 0;
+    for (int q = 0; q < count; ++q) {
+        small = small && plan_is_small(ps[q]);
+        Lmax = std::max<int64_t>(Lmax, ps[q].L);
+    }
+    if (!small) {
+        for (int q = 0; q < count; ++q)
+            if (ids_status s = plan_build(ps[q], keys[q], nullptr, nullptr, pb[q], st)) return s;
+        return IDS_OK;
+    }
+    PlanSmallArgs sa;
+    for (int q = 0; q < count; ++q) sa.p[q] = plan_args(ps[q], keys[q], nullptr, nullptr, pb[q]);
+    hipLaunchKernelGGL(plan_small_kernel, dim3(count), dim3(64 * PS_W), sizeof(int32_t) * PS_W * Lmax, st, sa);
+    return check_launch("countsketch plan");
+}
+
+ids_status plan_build(const PlanShape& ps, uint64_t key, const int64_t* fr_pi, const int32_t* fr_x,
+                      const PlanBufs& pb, hipStream_t st) {
+    PlanArgs a = plan_args(ps, key, fr_pi, fr_x, pb);
+    if (plan_is_small(ps)) {
+        PlanSmallArgs sa;
+        sa.p[0] = a;
+        hipLaunchKernelGGL(plan_small_kernel, dim3(1), dim3(64 * PS_W), sizeof(int32_t) * PS_W * ps.L, st, sa);
+        return check_launch("countsketch plan");
+    }
     size_t lds = sizeof(int32_t) * (size_t)ps.L;
     hipLaunchKernelGGL(plan_count_kernel, dim3(ps.nseg), dim3(64), lds, st, a);
     hipLaunchKernelGGL(plan_rowscan_kernel, dim3((unsigned)ps.L), dim3(64), 0, st, a, pb.tot);

@@ -54,6 +54,7 @@ struct SelArgs {
     int64_t* J;
     int64_t* keff;
     double* Rt;       // n x k (column j's top rows contiguous)
+    double* R11c;     // k x k: row t = top rows of the column chosen at step t
     int32_t* pos;     // n: step at which the column was chosen, -1 otherwise
     double* mb;       // k step regions of RS doubles each, sentinel-filled
     uint32_t* flag;   // [0] timeout flag
@@ -276,6 +277,7 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
 
     double y[R];
     bool alive = j < n;
+    int tsel = -1;  // step at which this column was chosen
     {
         const int64_t jc = min(j, n - 1);
         if (a.ydt == IDS_F64) {
@@ -389,6 +391,7 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
             for (int r = 0; r < R; ++r)
                 if (row0 + r == t) y[r] = beta;
             if (p == 0) a.pos[j] = t;
+            tsel = t;
         }
         // ---- trailing norms for the next step (rows > t)
         {
@@ -409,10 +412,14 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
     }
 
     if (j < n) {
+        double* rj = (tsel >= 0) ? a.R11c + (int64_t)tsel * a.k : nullptr;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = row0 + r;
-            if (i < keff) a.Rt[(int64_t)j * a.k + i] = y[r];
+            if (i < keff) {
+                a.Rt[(int64_t)j * a.k + i] = y[r];
+                if (rj) rj[i] = y[r];
+            }
         }
     }
     finish(a, keff);
@@ -481,10 +488,12 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
 
     double y[NC][RB];
     bool alive[NC];
+    int tsel[NC];  // step at which column c was chosen (uniform)
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const int64_t jc = min(col0 + c, n - 1);
         alive[c] = col0 + c < n;
+        tsel[c] = -1;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const int i = rb0 + 64 * r;
@@ -613,6 +622,7 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
             for (int c = 0; c < NC; ++c)
                 if (c == cw) {
                     alive[c] = false;
+                    tsel[c] = t;
 #pragma unroll
                     for (int r = 0; r < RB; ++r)
                         if (rb0 + 64 * r == t) y[c][r] = beta;
@@ -644,10 +654,46 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const int i = rb0 + 64 * r;
-            if (i < keff) a.Rt[(int64_t)(col0 + c) * a.k + i] = y[c][r];
+            if (i < keff) {
+                a.Rt[(int64_t)(col0 + c) * a.k + i] = y[c][r];
+                if (tsel[c] >= 0) a.R11c[(int64_t)tsel[c] * a.k + i] = y[c][r];
+            }
         }
     }
     finish(a, keff);
+}
+
+// count elements e -> LDS through registers, U independent loads in flight per
+// thread (a plain loop would wait for each load before issuing the next)
+template <int U, class Ld, class St>
+__device__ __forceinline__ void copy_batched(int count, int nthreads, Ld ld, St st) {
+    for (int e0 = threadIdx.x; e0 < count; e0 += U * nthreads) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * nthreads;
+            v[u] = (e < count) ? ld(e) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * nthreads;
+            if (e < count) st(e, v[u]);
+        }
+    }
+}
+
+// R11 (keff x keff, row-major, zero below the diagonal) into LDS from the
+// compact copy R11c (row t = top rows of the column chosen at step t, so
+// R11[r][c] = R11c[c][r]).
+__device__ __forceinline__ void stage_r11(double* R11s, const double* __restrict__ R11c, int64_t k, int keff,
+                                          int nthreads) {
+    copy_batched<16>(
+        keff * keff, nthreads,
+        [&](int e) {
+            const int r = e / keff, c = e - r * keff;
+            return (r <= c) ? R11c[(int64_t)c * k + r] : 0.0;
+        },
+        [&](int e, double v) { R11s[e] = v; });
 }
 
 // P[:, j]: e_t for a chosen column, R11^{-1} R[0:keff, j] otherwise, by
@@ -658,7 +704,7 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
 constexpr int TRSM_THREADS = 64;
 template <bool R11_LDS, bool X_LDS>
 __global__ __launch_bounds__(TRSM_THREADS) void trsm_p_kernel(int64_t n, int64_t k, const double* __restrict__ Rt,
-                                                              const int64_t* __restrict__ J,
+                                                              const double* __restrict__ R11c,
                                                               const int32_t* __restrict__ pos,
                                                               const int64_t* __restrict__ keffp, double* P) {
     extern __shared__ double sm[];
@@ -667,10 +713,7 @@ __global__ __launch_bounds__(TRSM_THREADS) void trsm_p_kernel(int64_t n, int64_t
     double* R11s = sm;
     double* xs = sm + (R11_LDS ? k * k : 0);
     if (R11_LDS) {
-        for (int64_t e = threadIdx.x; e < keff * keff; e += TRSM_THREADS) {
-            const int64_t r = e / keff, c = e % keff;
-            R11s[e] = (r <= c) ? Rt[J[c] * k + r] : 0.0;
-        }
+        stage_r11(R11s, R11c, k, (int)keff, TRSM_THREADS);
         __syncthreads();
     }
     const int tid = threadIdx.x;
@@ -684,11 +727,11 @@ __global__ __launch_bounds__(TRSM_THREADS) void trsm_p_kernel(int64_t n, int64_t
     for (int64_t r = keff - 1; r >= 0; --r) {
         double s = Rt[j * k + r];
         for (int64_t c = r + 1; c < keff; ++c) {
-            const double rc = R11_LDS ? R11s[r * keff + c] : Rt[J[c] * k + r];
+            const double rc = R11_LDS ? R11s[r * keff + c] : R11c[c * k + r];
             const double xc = X_LDS ? xs[c * TRSM_THREADS + tid] : P[c * n + j];
             s = fma(-rc, xc, s);
         }
-        const double d = R11_LDS ? R11s[r * keff + r] : Rt[J[r] * k + r];
+        const double d = R11_LDS ? R11s[r * keff + r] : R11c[r * k + r];
         const double x = s / d;
         if (X_LDS) xs[r * TRSM_THREADS + tid] = x;
         P[r * n + j] = x;
@@ -702,17 +745,14 @@ __global__ __launch_bounds__(TRSM_THREADS) void trsm_p_kernel(int64_t n, int64_t
 // summed with DPP row operations, and x_r = (that sum) / R11[r][r].
 template <int KS, bool R11_LDS>
 __global__ __launch_bounds__(256) void trsm_group_kernel(int64_t n, int64_t k, const double* __restrict__ Rt,
-                                                         const int64_t* __restrict__ J,
+                                                         const double* __restrict__ R11c,
                                                          const int32_t* __restrict__ pos,
                                                          const int64_t* __restrict__ keffp, double* P) {
     extern __shared__ double R11s[];
     const int64_t keff = *keffp;
     if (keff < 0) return;
     if (R11_LDS) {
-        for (int64_t e = threadIdx.x; e < keff * keff; e += 256) {
-            const int64_t r = e / keff, c = e % keff;
-            R11s[e] = (r <= c) ? Rt[J[c] * k + r] : 0.0;
-        }
+        stage_r11(R11s, R11c, k, (int)keff, 256);
         __syncthreads();
     }
     const int q = threadIdx.x & 15;
@@ -737,7 +777,7 @@ __global__ __launch_bounds__(256) void trsm_group_kernel(int64_t n, int64_t k, c
             const int64_t c = 16 * sl + q;
             if (c == r) part = b[sl];
             if (c > r && c < keff) {
-                const double rc = R11_LDS ? R11s[r * keff + c] : Rt[J[c] * k + r];
+                const double rc = R11_LDS ? R11s[r * keff + c] : R11c[c * k + r];
                 part = fma(-rc, x[sl], part);
             }
         }
@@ -745,7 +785,7 @@ __global__ __launch_bounds__(256) void trsm_group_kernel(int64_t n, int64_t k, c
         part += dpp_f64<0x4E, 0xf>(part);
         part += dpp_f64<0x141, 0xf>(part);
         part += dpp_f64<0x140, 0xf>(part);
-        const double d = R11_LDS ? R11s[r * keff + r] : Rt[J[r] * k + r];
+        const double d = R11_LDS ? R11s[r * keff + r] : R11c[r * k + r];
         const double xr = part / d;
         if (q == (int)(r & 15)) {
 #pragma unroll
@@ -755,6 +795,85 @@ __global__ __launch_bounds__(256) void trsm_group_kernel(int64_t n, int64_t k, c
         if (q == 0) P[r * n + j] = xr;
     }
     for (int64_t r = keff + q; r < k; r += 16) P[r * n + j] = 0.0;
+}
+
+// k <= 128: column-oriented (axpy) back-substitution.  GQ lanes per column,
+// lane q holds b_c, c = GQ s + q (s < 32), which becomes x_c once solved.
+// Step r: the owner lane forms x_r = b_r / R11[r][r] (reciprocal staged in
+// LDS), x_r reaches the GQ lanes of the column by a DPP quad permutation, and
+// every row c < r takes b_c -= R11[c][r] x_r with independent FMAs; the only
+// serial chain per step is one FMA, one multiply and one lane exchange.
+// R11 is staged transposed (row r = column r of R11, zero on and below the
+// diagonal and in the padding), so the update reads of a step are one LDS row.
+constexpr int TRSM_AX_KS = 32;
+template <int GQ>
+__device__ __forceinline__ double quad_bcast(double v, int qo) {
+    if (GQ == 1) return v;
+    if (GQ == 2) return (qo == 0) ? dpp_f64<0xA0, 0xf>(v) : dpp_f64<0xF5, 0xf>(v);  // [0,0,2,2] / [1,1,3,3]
+    switch (qo) {                                                                  // [qo,qo,qo,qo]
+        case 0: return dpp_f64<0x00, 0xf>(v);
+        case 1: return dpp_f64<0x55, 0xf>(v);
+        case 2: return dpp_f64<0xAA, 0xf>(v);
+        default: return dpp_f64<0xFF, 0xf>(v);
+    }
+}
+
+template <int GQ>
+__global__ __launch_bounds__(256) void trsm_axpy_kernel(int64_t n, int64_t k, const double* __restrict__ Rt,
+                                                        const double* __restrict__ R11c,
+                                                        const int32_t* __restrict__ pos,
+                                                        const int64_t* __restrict__ keffp, double* P) {
+    constexpr int KS = TRSM_AX_KS, LDK = GQ * KS;
+    extern __shared__ double sm[];
+    const int64_t keff64 = *keffp;
+    if (keff64 < 0) return;
+    const int keff = (int)keff64;
+    double* R11T = sm;                    // keff x LDK
+    double* rd = sm + (size_t)keff * LDK;  // keff reciprocal diagonals
+    const int tid = threadIdx.x, lane = tid & 63;
+    copy_batched<16>(
+        keff * LDK, 256,
+        [&](int e) {
+            const int r = e / LDK, c = e % LDK;
+            return (c < r) ? R11c[(int64_t)r * k + c] : 0.0;
+        },
+        [&](int e, double v) { R11T[e] = v; });
+    copy_batched<1>(
+        keff, 256, [&](int r) { return R11c[(int64_t)r * k + r]; }, [&](int r, double v) { rd[r] = 1.0 / v; });
+    __syncthreads();
+    const int q = lane % GQ;
+    const int64_t j = (int64_t)blockIdx.x * (256 / GQ) + tid / GQ;
+    if (j >= n) return;
+    const int32_t pj = pos[j];
+    if (pj >= 0) {
+        for (int64_t c = q; c < k; c += GQ) P[c * n + j] = (c == pj) ? 1.0 : 0.0;
+        return;
+    }
+    double b[KS];
+#pragma unroll
+    for (int sl = 0; sl < KS; ++sl) {
+        const int c = GQ * sl + q;
+        b[sl] = (c < keff) ? Rt[j * k + c] : 0.0;
+    }
+    // slot so of the owner is a compile-time index: the outer loop is unrolled
+#pragma unroll
+    for (int so = KS - 1; so >= 0; --so) {
+        if (GQ * so >= keff) continue;
+        for (int qo = GQ - 1; qo >= 0; --qo) {
+            const int r = GQ * so + qo;
+            if (r >= keff) continue;
+            const double xr = quad_bcast<GQ>(b[so] * rd[r], qo);
+            const double* row = R11T + r * LDK + q;
+#pragma unroll
+            for (int sl = 0; sl < so; ++sl) b[sl] = fma(-row[GQ * sl], xr, b[sl]);
+            b[so] = (q == qo) ? xr : fma(-row[GQ * so], xr, b[so]);
+        }
+    }
+#pragma unroll
+    for (int sl = 0; sl < KS; ++sl) {
+        const int c = GQ * sl + q;
+        if (c < k) P[(int64_t)c * n + j] = (c < keff) ? b[sl] : 0.0;
+    }
 }
 
 __global__ __launch_bounds__(256) void lambda_hat_kernel(int64_t k, int64_t n, const double* __restrict__ P,
@@ -873,7 +992,8 @@ ids_status select_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp) {
 
 size_t select_bytes(const SelectPlan& sp) {
     return align256(sizeof(double) * (size_t)sp.k * sp.RS) + align256(sizeof(uint32_t) * 2) +
-           align256(sizeof(double) * (size_t)sp.n * sp.k) + align256(sizeof(int32_t) * (size_t)sp.n);
+           align256(sizeof(double) * (size_t)sp.n * sp.k) + align256(sizeof(double) * (size_t)sp.k * sp.k) +
+           align256(sizeof(int32_t) * (size_t)sp.n);
 }
 
 ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t rs, int64_t cs, int64_t* J,
@@ -899,6 +1019,8 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
     p += align256(sizeof(uint32_t) * 2);
     a.Rt = (double*)p;
     p += align256(sizeof(double) * (size_t)sp.n * sp.k);
+    a.R11c = (double*)p;
+    p += align256(sizeof(double) * (size_t)sp.k * sp.k);
     a.pos = (int32_t*)p;
 
     Inst in;
@@ -922,35 +1044,44 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
     const unsigned g = (unsigned)((sp.n + TRSM_THREADS - 1) / TRSM_THREADS);
     const size_t lim = lds_limit();
     const double* Rt = a.Rt;
+    const double* R11c = a.R11c;
     const int32_t* pos = a.pos;
     const unsigned g16 = (unsigned)((sp.n + 15) / 16);
+#define IDS_TRSM_AXPY(GQ)                                                                                          \
+    hipLaunchKernelGGL((trsm_axpy_kernel<GQ>), dim3((unsigned)((sp.n + 256 / GQ - 1) / (256 / GQ))), dim3(256),     \
+                       sizeof(double) * (size_t)sp.k * (GQ * TRSM_AX_KS + 1), st, sp.n, sp.k, Rt, R11c, pos,       \
+                       (const int64_t*)keff, P)
 #define IDS_TRSM_GROUP(KS)                                                                                         \
     do {                                                                                                           \
         if (r11 <= lim)                                                                                            \
             hipLaunchKernelGGL((trsm_group_kernel<KS, true>), dim3(g16), dim3(256), r11, st, sp.n, sp.k, Rt,       \
-                               (const int64_t*)J, pos, (const int64_t*)keff, P);                                   \
+                               R11c, pos, (const int64_t*)keff, P);                                   \
         else                                                                                                       \
             hipLaunchKernelGGL((trsm_group_kernel<KS, false>), dim3(g16), dim3(256), 0, st, sp.n, sp.k, Rt,        \
-                               (const int64_t*)J, pos, (const int64_t*)keff, P);                                   \
+                               R11c, pos, (const int64_t*)keff, P);                                   \
     } while (0)
+    const size_t ax = sizeof(double) * (size_t)sp.k * (4 * TRSM_AX_KS + 1);
     if (sp.k <= 32)
-        IDS_TRSM_GROUP(2);
+        IDS_TRSM_AXPY(1);
     else if (sp.k <= 64)
-        IDS_TRSM_GROUP(4);
+        IDS_TRSM_AXPY(2);
+    else if (sp.k <= 128 && ax <= lim)
+        IDS_TRSM_AXPY(4);
     else if (sp.k <= 128)
         IDS_TRSM_GROUP(8);
     else if (sp.k <= 256)
         IDS_TRSM_GROUP(16);
 #undef IDS_TRSM_GROUP
+#undef IDS_TRSM_AXPY
     else if (r11 + xb <= lim)
         hipLaunchKernelGGL((trsm_p_kernel<true, true>), dim3(g), dim3(TRSM_THREADS), r11 + xb, st, sp.n, sp.k, Rt,
-                           (const int64_t*)J, pos, (const int64_t*)keff, P);
+                           R11c, pos, (const int64_t*)keff, P);
     else if (xb <= lim)
         hipLaunchKernelGGL((trsm_p_kernel<false, true>), dim3(g), dim3(TRSM_THREADS), xb, st, sp.n, sp.k, Rt,
-                           (const int64_t*)J, pos, (const int64_t*)keff, P);
+                           R11c, pos, (const int64_t*)keff, P);
     else
         hipLaunchKernelGGL((trsm_p_kernel<false, false>), dim3(g), dim3(TRSM_THREADS), 0, st, sp.n, sp.k, Rt,
-                           (const int64_t*)J, pos, (const int64_t*)keff, P);
+                           R11c, pos, (const int64_t*)keff, P);
     return check_launch("cpqr / interpolation matrix");
 }
 

@@ -41,6 +41,9 @@ size_t plan_bytes(const PlanShape& ps);
 PlanBufs plan_carve(const PlanShape& ps, char*& p);
 ids_status plan_build(const PlanShape& ps, uint64_t key, const int64_t* fr_pi, const int32_t* fr_x,
                       const PlanBufs& pb, hipStream_t st);
+// several plans (plain hash) at once: one launch when all are small
+ids_status plan_build_many(int count, const PlanShape* ps, const uint64_t* keys, const PlanBufs* pb,
+                           hipStream_t st);
 
 // ---- CountSketch -------------------------------------------------------------
 ids_status cs_dense(int32_t dtype, int32_t acc, const void* A, int64_t lda, int64_t n, const PlanBufs& pb,

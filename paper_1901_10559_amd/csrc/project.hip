@@ -2,7 +2,7 @@
 // Section 1.3.1) on the matrix cores: v_mfma_f64_16x16x4f64 (FP64) and
 // v_mfma_f32_16x16x4f32 (FP32).  64x64 output tile per 256-thread workgroup,
 // each wave a 32x32 quadrant of 2x2 16x16 MFMA blocks; K staged through LDS in
-// slices of 16.  The output is written column-major (column j of Y
+// slices of 64 (FP32) or 32 (FP64), the next slice prefetched into registers.  The output is written column-major (column j of Y
 // contiguous), the layout the column-pivoted QR reads.
 #include "common.hpp"
 #include "kernels.hpp"
@@ -33,17 +33,26 @@ struct Mfma<float> {
     }
 };
 
-constexpr int PBM = 64, PBN = 64, PBK = 16;
+constexpr int PBM = 64, PBN = 64;
+template <typename T>
+struct Pbk {
+    static constexpr int K = sizeof(T) == 4 ? 64 : 32;  // K slice staged per barrier
+};
 
 // MFMA 16x16x4 operand layout (lane = 0..63):
 //   A operand: A[lane % 16][lane / 16]      (16 x 4)
 //   B operand: B[lane / 16][lane % 16]      (4 x 16)
 //   result r : C[Mfma<T>::row(lane, r)][lane % 16]; the FP32 and FP64
 //              instructions order the four result rows of a lane differently.
+// The next K slice is loaded into registers while the current one is
+// multiplied from LDS, so one barrier pair covers PBK = 64 (FP32) or 32 (FP64)
+// columns of G.
 template <typename T>
 __global__ __launch_bounds__(256) void project_kernel(int64_t l, int64_t q, int64_t n, const T* __restrict__ G,
                                                       const T* __restrict__ Y1, int64_t ld1, T* __restrict__ Y,
                                                       int64_t ldy) {
+    constexpr int PBK = Pbk<T>::K;
+    constexpr int NGA = PBM * PBK / 256, NBA = PBK * PBN / 256;  // staged elements per thread
     __shared__ T Gs[PBM][PBK + 1];
     __shared__ T Bs[PBK][PBN + 1];
     using M = Mfma<T>;
@@ -60,37 +69,58 @@ __global__ __launch_bounds__(256) void project_kernel(int64_t l, int64_t q, int6
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
 
+    T gv[NGA], bv[NBA];
+    auto load = [&](int64_t k0) {
+#pragma unroll
+        for (int e = 0; e < NGA; ++e) {
+            const int idx = tid + e * 256;
+            const int r = idx / PBK, c = idx % PBK;
+            const int64_t gr = row0 + r, gc = k0 + c;
+            gv[e] = (gr < l && gc < q) ? G[gr * q + gc] : (T)0;
+        }
+#pragma unroll
+        for (int e = 0; e < NBA; ++e) {
+            const int idx = tid + e * 256;
+            const int r = idx / PBN, c = idx % PBN;
+            const int64_t gr = k0 + r, gc = col0 + c;
+            bv[e] = (gr < q && gc < n) ? Y1[gr * ld1 + gc] : (T)0;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int e = 0; e < NGA; ++e) {
+            const int idx = tid + e * 256;
+            Gs[idx / PBK][idx % PBK] = gv[e];
+        }
+#pragma unroll
+        for (int e = 0; e < NBA; ++e) {
+            const int idx = tid + e * 256;
+            Bs[idx / PBN][idx % PBN] = bv[e];
+        }
+    };
+    load(0);
+    store();
+    __syncthreads();
     for (int64_t k0 = 0; k0 < q; k0 += PBK) {
-        // G tile: 64 x 16
-#pragma unroll
-        for (int e = 0; e < (PBM * PBK) / 256; ++e) {
-            int idx = tid + e * 256;
-            int r = idx / PBK, c = idx % PBK;
-            int64_t gr = row0 + r, gc = k0 + c;
-            Gs[r][c] = (gr < l && gc < q) ? G[gr * q + gc] : (T)0;
-        }
-        // Y1 tile: 16 x 64
-#pragma unroll
-        for (int e = 0; e < (PBK * PBN) / 256; ++e) {
-            int idx = tid + e * 256;
-            int r = idx / PBN, c = idx % PBN;
-            int64_t gr = k0 + r, gc = col0 + c;
-            Bs[r][c] = (gr < q && gc < n) ? Y1[gr * ld1 + gc] : (T)0;
-        }
-        __syncthreads();
+        const bool more = k0 + PBK < q;
+        if (more) load(k0 + PBK);
 #pragma unroll
         for (int kk = 0; kk < PBK; kk += 4) {
-            T av[2], bv[2];
+            T av[2], bw[2];
 #pragma unroll
             for (int a = 0; a < 2; ++a) av[a] = Gs[wm * 32 + a * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + (lane >> 4)][wn * 32 + b * 16 + (lane & 15)];
+            for (int b = 0; b < 2; ++b) bw[b] = Bs[kk + (lane >> 4)][wn * 32 + b * 16 + (lane & 15)];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) acc[a][b] = M::run(av[a], bv[b], acc[a][b]);
+                for (int b = 0; b < 2; ++b) acc[a][b] = M::run(av[a], bw[b], acc[a][b]);
         }
         __syncthreads();
+        if (more) {
+            store();
+            __syncthreads();
+        }
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
