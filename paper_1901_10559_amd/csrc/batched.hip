@@ -11,7 +11,7 @@
 //       j (rows 0..RL-1 in LDS, rows RL.. in registers), FP32 data and
 //       Householder updates, trailing norms recomputed in FP64 each step.
 //   batched_trsm_kernel    one workgroup per problem: R11 in LDS, FP64
-//       back-substitution, 16 lanes per column; writes P_p.
+//       axpy back-substitution, up to 4 lanes per column; writes P_p.
 // Problem p draws its CountSketch from the stream (seed, tag = p) and uses
 // the first l1_p = min(m_p, l1max) columns of the shared l x l1max G.
 #include <algorithm>
@@ -19,6 +19,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "solve.hpp"
 
 namespace ids {
 
@@ -65,6 +66,7 @@ struct BatchArgs {
     uint64_t seed;
     const uint16_t* A;
     const uint16_t* G;  // l x l1max BF16
+    int32_t g_vec;      // G rows 16-byte aligned (l1max % 8 == 0, G aligned)
     float* Y;
     double* Rt;
     int32_t* pos;
@@ -83,6 +85,7 @@ constexpr int BS_BG = 32;       // buckets per group (= MFMA K)
 constexpr int BS_LMAX = 128;    // padded sketch height (l <= 128)
 constexpr int BS_MMAX = 4096;   // rows per problem
 constexpr int BS_L1MAX = 512;   // buckets per problem
+constexpr int BS_RIF = 8;       // bucket rows in flight per gather thread
 
 __device__ __forceinline__ uint16_t f2bf_rne(float f) {
     uint32_t u = __float_as_uint(f);
@@ -176,6 +179,26 @@ __global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a)
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = v4f32{0.f, 0.f, 0.f, 0.f};
         for (int g0 = 0; g0 < L1; g0 += BS_BG) {
+            // G[:, g0 .. g0 + 32) -> LDS, one 16-byte row chunk per thread (rows
+            // >= l and columns >= L1 are zero); issued first so its latency
+            // overlaps the gather
+            {
+                static_assert(BS_THREADS == BS_LMAX * BS_BG / 8, "one G chunk per thread");
+                const int r = tid >> 2, c8 = (tid & 3) * 8, gc = g0 + c8;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (r < l) {
+                    const uint16_t* gp = a.G + (int64_t)r * a.l1max + gc;
+                    if (a.g_vec && gc + 8 <= L1) {
+                        v = *reinterpret_cast<const uint4*>(gp);
+                    } else {
+                        uint32_t e[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) e[u] = (gc + u < L1) ? gp[u] : 0u;
+                        v = make_uint4(e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16), e[6] | (e[7] << 16));
+                    }
+                }
+                *reinterpret_cast<uint4*>(&Gs[r][c8]) = v;
+            }
             // gather: Y1[b][c0 + 8ch .. +8] for b = g0 + bl
             {
                 const int b = g0 + bl;
@@ -188,18 +211,18 @@ __global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a)
                     int q = off[b];
                     const int qe = off[b + 1];
                     if (full) {
-                        // four rows in flight, then added in increasing row order
-                        for (; q + 4 <= qe; q += 4) {
-                            uint4 raw[4];
-                            int32_t code[4];
+                        // BS_RIF rows in flight, then added in increasing row order
+                        for (; q + BS_RIF <= qe; q += BS_RIF) {
+                            uint4 raw[BS_RIF];
+                            int32_t code[BS_RIF];
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
+                            for (int u = 0; u < BS_RIF; ++u) {
                                 code[u] = rows[q + u];
                                 const int64_t i = code[u] >= 0 ? code[u] : -(int64_t)code[u] - 1;
                                 raw[u] = load_nt16(Ap + i * n + cc);
                             }
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
+                            for (int u = 0; u < BS_RIF; ++u) {
                                 const uint32_t wv[4] = {raw[u].x, raw[u].y, raw[u].z, raw[u].w};
 #pragma unroll
                                 for (int e = 0; e < 8; ++e) {
@@ -235,11 +258,6 @@ __global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a)
                     Y1h[8 * ch + e][bl] = h;
                     Y1l[8 * ch + e][bl] = f2bf_rne(s[e] - hf);
                 }
-            }
-            // G[:, g0 .. g0 + 32] -> LDS (rows >= l and columns >= L1 are zero)
-            for (int e = tid; e < BS_LMAX * BS_BG; e += BS_THREADS) {
-                const int r = e / BS_BG, c = e % BS_BG;
-                Gs[r][c] = (r < l && g0 + c < L1) ? a.G[(int64_t)r * a.l1max + g0 + c] : (uint16_t)0;
             }
             __syncthreads();
             // Y(rows rt*16.., cols ct*16..) += G tile (16 x 32) * Y1 (32 x 16), hi and lo
@@ -354,13 +372,14 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
             y[r] = (alive && i < l) ? v : 0.f;
         }
     }
-    auto norm_from = [&](int t0) -> double {  // FP64 sum of squares over rows i >= t0
+    // FP64 sum of squares over rows i >= t0 (the LDS rows' loop is unrolled by
+    // 4 so their reads overlap; a full unroll would spill at 1024 threads)
+    auto norm_from = [&](int t0) -> double {
         double s[4] = {0.0, 0.0, 0.0, 0.0};
-        if (t0 < BC_RL) {
-            for (int r = t0; r < BC_RL; ++r) {
-                const double v = (double)ylds[r * BC_THREADS + j];
-                s[r & 3] = fma(v, v, s[r & 3]);
-            }
+#pragma unroll 4
+        for (int r = t0; r < BC_RL; ++r) {
+            const double v = (double)ylds[r * BC_THREADS + j];
+            s[r & 3] = fma(v, v, s[r & 3]);
         }
 #pragma unroll
         for (int c = 0; c < BC_RR; c += 8) {
@@ -412,21 +431,16 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
         }
         if (j < BC_RL) xf[j] = ylds[j * BC_THREADS + wj];
         __syncthreads();
-        // ---- Householder reflector in FP64 (every wave, same bits)
-        double sig2 = 0.0;
-        for (int i = t + 1 + lane; i < l; i += 64) {
-            const double xi = (double)xf[i];
-            sig2 = fma(xi, xi, sig2);
-        }
-        sig2 = wave_sum_dpp1(sig2);
+        // ---- Householder reflector in FP64 (every wave, same bits); the norm of
+        //      the pivot's rows t.. is its published trailing norm wnu
         const double alpha = (double)xf[t];
         double tau, beta, scal;
-        if (sig2 == 0.0) {
+        if (!(wnu > alpha * alpha)) {
             tau = 0.0;
             beta = alpha;
             scal = 0.0;
         } else {
-            const double nrm = sqrt(alpha * alpha + sig2);
+            const double nrm = sqrt(wnu);
             beta = (alpha >= 0.0) ? -nrm : nrm;
             tau = (beta - alpha) / beta;
             scal = 1.0 / (alpha - beta);
@@ -437,8 +451,10 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
         if (wave_live) {
             if (alive) {
                 float d[4] = {0.f, 0.f, 0.f, 0.f};
-                if (t < BC_RL)
+                if (t < BC_RL) {
+#pragma unroll 4
                     for (int r = t; r < BC_RL; ++r) d[r & 3] = fmaf(vb[r], ylds[r * BC_THREADS + j], d[r & 3]);
+                }
 #pragma unroll
                 for (int c = 0; c < BC_RR; c += 8)
                     if (BC_RL + c + 8 > t) {
@@ -447,9 +463,11 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
                             if (BC_RL + r < BS_LMAX) d[r & 3] = fmaf(vb[BC_RL + r], y[r], d[r & 3]);
                     }
                 const float dt = ((d[0] + d[1]) + (d[2] + d[3])) * (float)tau;
-                if (t < BC_RL)
+                if (t < BC_RL) {
+#pragma unroll 4
                     for (int r = t; r < BC_RL; ++r)
                         ylds[r * BC_THREADS + j] = fmaf(-dt, vb[r], ylds[r * BC_THREADS + j]);
+                }
 #pragma unroll
                 for (int c = 0; c < BC_RR; c += 8)
                     if (BC_RL + c + 8 > t) {
@@ -487,60 +505,61 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
 // ---------------------------------------------------------------------------
 // K3: interpolation matrix per problem (FP64)
 // ---------------------------------------------------------------------------
-constexpr int BT_COLS = 64;
-// Column-block back-substitution: X (keff x 64 columns) starts as R12's block;
-// for r = keff-1 .. 0 every thread recomputes x_r = X[r][c] / R11[r][r] for its
-// column and removes R11[i][r] x_r from its rows i < r; one barrier per r.
-__global__ __launch_bounds__(1024) void batched_trsm_kernel(BatchArgs a) {
+// One workgroup per problem: R11 staged transposed in LDS (the columns J[r] of
+// Rt, rows above the diagonal; reciprocal diagonals from the FP64 beta), then
+// the non-pivot columns are solved 512 / GQ at a time with the axpy
+// back-substitution (no workgroup barrier inside the solve).
+constexpr int BT_THREADS = 512;  // 32 right-hand-side slots per lane need up to 256 VGPRs
+template <int GQ>
+__global__ __launch_bounds__(BT_THREADS) void batched_trsm_kernel(BatchArgs a) {
+    constexpr int KS = TRSM_AX_KS, LDK = GQ * KS, NT = BT_THREADS;
     extern __shared__ double sm3[];
+    __shared__ int32_t Js[BS_LMAX];
     const int p = blockIdx.x;
     const BProb pr = a.prob[p];
     const int n = pr.n;
     const int k = (int)a.k;
     const int keff = (int)a.keff[p];
+    const int tid = threadIdx.x;
     const int64_t* J = a.J + (int64_t)p * k;
     const double* bt = a.beta + (int64_t)p * k;
     const double* Rt = a.Rt + pr.r_off * (int64_t)k;
     const int32_t* pos = a.pos + pr.r_off;
     double* P = a.P + pr.p_off;
-    double* R11s = sm3;                  // keff x keff, diagonal holds 1 / R11[r][r]
-    double* X = sm3 + (size_t)k * k;     // keff x BT_COLS
-    __shared__ int cols[BT_COLS];
-    __shared__ int ncols_s;
-    for (int e = threadIdx.x; e < keff * keff; e += 1024) {
-        const int r = e / keff, c = e % keff;
-        R11s[e] = (r < c) ? Rt[J[c] * k + r] : (r == c ? 1.0 / bt[r] : 0.0);
-    }
-    // chosen columns: P[:, j] = e_pos
-    for (int e = threadIdx.x; e < n * 16; e += 1024) {
-        const int j = e >> 4, q = e & 15;
-        const int pj = pos[j];
-        if (pj >= 0)
-            for (int r = q; r < k; r += 16) P[(int64_t)r * n + j] = (r == pj) ? 1.0 : 0.0;
-    }
-    const int c = threadIdx.x & (BT_COLS - 1);   // column within block
-    const int rg = threadIdx.x / BT_COLS;        // row group (16 groups)
-    for (int j0 = 0; j0 < n; j0 += BT_COLS) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int cnt = 0;
-            for (int j = j0; j < min(n, j0 + BT_COLS); ++j)
-                if (pos[j] < 0) cols[cnt++] = j;
-            ncols_s = cnt;
+    double* R11T = sm3;                       // keff x LDK
+    double* rd = sm3 + (size_t)keff * LDK;    // keff
+    if (tid < keff) Js[tid] = (int32_t)J[tid];
+    __syncthreads();
+    copy_batched<8>(
+        keff * LDK, NT,
+        [&](int e) {
+            const int r = e / LDK, c = e % LDK;
+            return (c < r) ? Rt[(int64_t)Js[r] * k + c] : 0.0;
+        },
+        [&](int e, double v) { R11T[e] = v; });
+    copy_batched<1>(keff, NT, [&](int r) { return bt[r]; }, [&](int r, double v) { rd[r] = 1.0 / v; });
+    __syncthreads();
+    const int q = tid % GQ;
+    for (int j0 = 0; j0 < n; j0 += NT / GQ) {
+        const int j = j0 + tid / GQ;
+        if (j >= n) continue;
+        const int32_t pj = pos[j];
+        if (pj >= 0) {  // P[:, j] = e_pos
+            for (int c = q; c < k; c += GQ) P[(int64_t)c * n + j] = (c == pj) ? 1.0 : 0.0;
+            continue;
         }
-        __syncthreads();
-        const int nc = ncols_s;
-        const int jj = (c < nc) ? cols[c] : -1;
-        for (int r = rg; r < keff; r += 16) X[r * BT_COLS + c] = (jj >= 0) ? Rt[(int64_t)jj * k + r] : 0.0;
-        __syncthreads();
-        for (int r = keff - 1; r >= 0; --r) {
-            const double x = X[r * BT_COLS + c] * R11s[r * keff + r];
-            for (int i = rg; i < r; i += 16) X[i * BT_COLS + c] = fma(-R11s[i * keff + r], x, X[i * BT_COLS + c]);
-            if (rg == 0 && jj >= 0) P[(int64_t)r * n + jj] = x;
-            __syncthreads();
+        double b[KS];
+#pragma unroll
+        for (int sl = 0; sl < KS; ++sl) {
+            const int c = GQ * sl + q;
+            b[sl] = (c < keff) ? Rt[(int64_t)j * k + c] : 0.0;
         }
-        if (jj >= 0)
-            for (int r = keff + rg; r < k; r += 16) P[(int64_t)r * n + jj] = 0.0;
+        axpy_solve<GQ>(b, R11T, rd, keff, q);
+#pragma unroll
+        for (int sl = 0; sl < KS; ++sl) {
+            const int c = GQ * sl + q;
+            if (c < k) P[(int64_t)c * n + j] = (c < keff) ? b[sl] : 0.0;
+        }
     }
 }
 
@@ -624,6 +643,7 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
     a.seed = seed;
     a.A = (const uint16_t*)A;
     a.G = (const uint16_t*)G;
+    a.g_vec = (l1max % 8 == 0) && (((uintptr_t)G & 15) == 0);
     char* p = (char*)ws;
     a.Y = (float*)p;
     p += align256(sizeof(float) * (size_t)y_elems);
@@ -649,8 +669,14 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
     }
     {
         ProfScope ps(PK_TRSM, st);
-        const size_t lds = sizeof(double) * ((size_t)k * k + (size_t)k * BT_COLS);
-        hipLaunchKernelGGL(batched_trsm_kernel, dim3((unsigned)nprob), dim3(1024), lds, st, a);
+        const int gq = k <= 32 ? 1 : (k <= 64 ? 2 : 4);
+        const size_t lds = sizeof(double) * (size_t)k * (gq * TRSM_AX_KS + 1);
+        if (gq == 1)
+            hipLaunchKernelGGL(batched_trsm_kernel<1>, dim3((unsigned)nprob), dim3(BT_THREADS), lds, st, a);
+        else if (gq == 2)
+            hipLaunchKernelGGL(batched_trsm_kernel<2>, dim3((unsigned)nprob), dim3(BT_THREADS), lds, st, a);
+        else
+            hipLaunchKernelGGL(batched_trsm_kernel<4>, dim3((unsigned)nprob), dim3(BT_THREADS), lds, st, a);
     }
     return check_launch("batched ID");
 }

@@ -70,21 +70,30 @@ __global__ __launch_bounds__(64) void plan_count_kernel(PlanArgs a) {
 //   plan_offsets: one workgroup, exclusive scan of the L totals -> off[b].
 // plan_place then places row i of segment s at off[b] + seg[b][s] + rank.
 __global__ __launch_bounds__(64) void plan_rowscan_kernel(PlanArgs a, int32_t* tot) {
+    constexpr int U = 16;  // loads in flight per lane
     const int b = blockIdx.x;
     const int lane = threadIdx.x;
     int32_t* row = a.seg + (int64_t)b * a.nseg;
     int32_t carry = 0;
-    for (int s0 = 0; s0 < a.nseg; s0 += 64) {
-        const int s = s0 + lane;
-        const int32_t v = s < a.nseg ? row[s] : 0;
-        int32_t x = v;
+    for (int s0 = 0; s0 < a.nseg; s0 += 64 * U) {
+        int32_t v[U];
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
+        for (int u = 0; u < U; ++u) {
+            const int s = s0 + 64 * u + lane;
+            v[u] = s < a.nseg ? row[s] : 0;
         }
-        if (s < a.nseg) row[s] = carry + x - v;
-        carry += __shfl(x, 63, 64);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int s = s0 + 64 * u + lane;
+            int32_t x = v[u];
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
+            }
+            if (s < a.nseg) row[s] = carry + x - v[u];
+            carry += __shfl(x, 63, 64);
+        }
     }
     if (lane == 0) tot[b] = carry;
 }
@@ -118,7 +127,23 @@ __global__ __launch_bounds__(64) void plan_place_kernel(PlanArgs a) {
     extern __shared__ int32_t run[];
     const int s = blockIdx.x;
     const int lane = threadIdx.x;
-    for (uint32_t b = lane; b < a.L; b += 64) run[b] = a.off[b] + a.seg[(int64_t)b * a.nseg + s];
+    {
+        constexpr int U = 8;  // loads in flight per lane
+        for (uint32_t b0 = 0; b0 < a.L; b0 += 64 * U) {
+            int32_t o[U], c[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t b = b0 + 64 * u + lane;
+                o[u] = b < a.L ? a.off[b] : 0;
+                c[u] = b < a.L ? a.seg[(int64_t)b * a.nseg + s] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t b = b0 + 64 * u + lane;
+                if (b < a.L) run[b] = o[u] + c[u];
+            }
+        }
+    }
     __syncthreads();
     const int64_t r0 = (int64_t)s * a.seg_rows;
     const int64_t r1 = min(a.m, r0 + a.seg_rows);

@@ -40,6 +40,7 @@
 // gives up at once, and k_eff is reported as -1.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "solve.hpp"
 
 namespace ids {
 
@@ -663,25 +664,6 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
     finish(a, keff);
 }
 
-// count elements e -> LDS through registers, U independent loads in flight per
-// thread (a plain loop would wait for each load before issuing the next)
-template <int U, class Ld, class St>
-__device__ __forceinline__ void copy_batched(int count, int nthreads, Ld ld, St st) {
-    for (int e0 = threadIdx.x; e0 < count; e0 += U * nthreads) {
-        double v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * nthreads;
-            v[u] = (e < count) ? ld(e) : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * nthreads;
-            if (e < count) st(e, v[u]);
-        }
-    }
-}
-
 // R11 (keff x keff, row-major, zero below the diagonal) into LDS from the
 // compact copy R11c (row t = top rows of the column chosen at step t, so
 // R11[r][c] = R11c[c][r]).
@@ -797,27 +779,7 @@ __global__ __launch_bounds__(256) void trsm_group_kernel(int64_t n, int64_t k, c
     for (int64_t r = keff + q; r < k; r += 16) P[r * n + j] = 0.0;
 }
 
-// k <= 128: column-oriented (axpy) back-substitution.  GQ lanes per column,
-// lane q holds b_c, c = GQ s + q (s < 32), which becomes x_c once solved.
-// Step r: the owner lane forms x_r = b_r / R11[r][r] (reciprocal staged in
-// LDS), x_r reaches the GQ lanes of the column by a DPP quad permutation, and
-// every row c < r takes b_c -= R11[c][r] x_r with independent FMAs; the only
-// serial chain per step is one FMA, one multiply and one lane exchange.
-// R11 is staged transposed (row r = column r of R11, zero on and below the
-// diagonal and in the padding), so the update reads of a step are one LDS row.
-constexpr int TRSM_AX_KS = 32;
-template <int GQ>
-__device__ __forceinline__ double quad_bcast(double v, int qo) {
-    if (GQ == 1) return v;
-    if (GQ == 2) return (qo == 0) ? dpp_f64<0xA0, 0xf>(v) : dpp_f64<0xF5, 0xf>(v);  // [0,0,2,2] / [1,1,3,3]
-    switch (qo) {                                                                  // [qo,qo,qo,qo]
-        case 0: return dpp_f64<0x00, 0xf>(v);
-        case 1: return dpp_f64<0x55, 0xf>(v);
-        case 2: return dpp_f64<0xAA, 0xf>(v);
-        default: return dpp_f64<0xFF, 0xf>(v);
-    }
-}
-
+// k <= 128: the axpy back-substitution, GQ = 1, 2, 4 lanes per column
 template <int GQ>
 __global__ __launch_bounds__(256) void trsm_axpy_kernel(int64_t n, int64_t k, const double* __restrict__ Rt,
                                                         const double* __restrict__ R11c,
@@ -855,20 +817,7 @@ __global__ __launch_bounds__(256) void trsm_axpy_kernel(int64_t n, int64_t k, co
         const int c = GQ * sl + q;
         b[sl] = (c < keff) ? Rt[j * k + c] : 0.0;
     }
-    // slot so of the owner is a compile-time index: the outer loop is unrolled
-#pragma unroll
-    for (int so = KS - 1; so >= 0; --so) {
-        if (GQ * so >= keff) continue;
-        for (int qo = GQ - 1; qo >= 0; --qo) {
-            const int r = GQ * so + qo;
-            if (r >= keff) continue;
-            const double xr = quad_bcast<GQ>(b[so] * rd[r], qo);
-            const double* row = R11T + r * LDK + q;
-#pragma unroll
-            for (int sl = 0; sl < so; ++sl) b[sl] = fma(-row[GQ * sl], xr, b[sl]);
-            b[so] = (q == qo) ? xr : fma(-row[GQ * so], xr, b[so]);
-        }
-    }
+    axpy_solve<GQ>(b, R11T, rd, keff, q);
 #pragma unroll
     for (int sl = 0; sl < KS; ++sl) {
         const int c = GQ * sl + q;

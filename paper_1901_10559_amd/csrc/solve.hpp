@@ -1,0 +1,73 @@
+// Column-oriented (axpy) back-substitution shared by the single-problem and
+// batched interpolation-matrix kernels (Algorithm 1, last step: R11 x = b per
+// column, x = R11^{-1} R12[:, j]).
+//
+// GQ lanes per column; lane q holds b_c, c = GQ s + q (s < TRSM_AX_KS), which
+// becomes x_c once solved.  Step r: the owner lane forms x_r = b_r / R11[r][r]
+// (reciprocal staged in LDS), x_r reaches the GQ lanes of the column by a DPP
+// quad permutation, and every row c < r takes b_c -= R11[c][r] x_r with
+// independent FMAs; the serial chain per step is one multiply, one lane
+// exchange and one FMA.  R11 is staged transposed (row r = column r of R11,
+// zero on and below the diagonal and in the padding up to GQ * TRSM_AX_KS).
+#pragma once
+#include "common.hpp"
+
+namespace ids {
+
+constexpr int TRSM_AX_KS = 32;
+
+template <int GQ>
+__device__ __forceinline__ double quad_bcast(double v, int qo) {
+    if (GQ == 1) return v;
+    if (GQ == 2) return (qo == 0) ? dpp_f64<0xA0, 0xf>(v) : dpp_f64<0xF5, 0xf>(v);  // [0,0,2,2] / [1,1,3,3]
+    switch (qo) {                                                                  // [qo,qo,qo,qo]
+        case 0: return dpp_f64<0x00, 0xf>(v);
+        case 1: return dpp_f64<0x55, 0xf>(v);
+        case 2: return dpp_f64<0xAA, 0xf>(v);
+        default: return dpp_f64<0xFF, 0xf>(v);
+    }
+}
+
+// b (this lane's rows of the right-hand side) -> x in place.  R11T: keff rows
+// of GQ * TRSM_AX_KS doubles; rd: keff reciprocal diagonals.  The GQ lanes of a
+// column must be active together.
+template <int GQ>
+__device__ __forceinline__ void axpy_solve(double (&b)[TRSM_AX_KS], const double* R11T, const double* rd, int keff,
+                                           int q) {
+    constexpr int KS = TRSM_AX_KS, LDK = GQ * KS;
+    // slot so of the owner is a compile-time index: the outer loop is unrolled
+#pragma unroll
+    for (int so = KS - 1; so >= 0; --so) {
+        if (GQ * so >= keff) continue;
+        for (int qo = GQ - 1; qo >= 0; --qo) {
+            const int r = GQ * so + qo;
+            if (r >= keff) continue;
+            const double xr = quad_bcast<GQ>(b[so] * rd[r], qo);
+            const double* row = R11T + r * LDK + q;
+#pragma unroll
+            for (int sl = 0; sl < so; ++sl) b[sl] = fma(-row[GQ * sl], xr, b[sl]);
+            b[so] = (q == qo) ? xr : fma(-row[GQ * so], xr, b[so]);
+        }
+    }
+}
+
+// count elements e -> LDS through registers, U independent loads in flight per
+// thread (a plain loop would wait for each load before issuing the next)
+template <int U, class Ld, class St>
+__device__ __forceinline__ void copy_batched(int count, int nthreads, Ld ld, St st) {
+    for (int e0 = threadIdx.x; e0 < count; e0 += U * nthreads) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * nthreads;
+            v[u] = (e < count) ? ld(e) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * nthreads;
+            if (e < count) st(e, v[u]);
+        }
+    }
+}
+
+}  // namespace ids

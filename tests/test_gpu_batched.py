@@ -35,6 +35,7 @@ def run_batch(ms, ns, k, l, l1max, seed=0):
 @pytest.mark.parametrize("ms,ns,k,l,l1max", [
     ([300, 700, 121, 4096, 1500, 497], [130, 1024, 640, 200, 333, 257], 111, 121, 496),
     ([64, 200, 90, 1000], [50, 77, 300, 1000], 20, 40, 128),
+    ([150, 333, 2000], [90, 700, 129], 50, 60, 130),   # G rows not 16-byte aligned
 ])
 def test_batched_sketch_matches_oracle(ms, ns, k, l, l1max):
     As, G64, plan, out = run_batch(ms, ns, k, l, l1max)
@@ -55,6 +56,7 @@ def test_batched_sketch_matches_oracle(ms, ns, k, l, l1max):
 @pytest.mark.parametrize("ms,ns,k,l,l1max", [
     ([300, 700, 121, 4096, 1500, 497], [130, 1024, 640, 200, 333, 257], 111, 121, 496),
     ([64, 200, 90, 1000], [50, 77, 300, 1000], 20, 40, 128),
+    ([150, 333, 2000], [90, 700, 129], 50, 60, 130),
 ])
 def test_batched_id_residual_within_2x_of_oracle(ms, ns, k, l, l1max):
     As, G64, plan, out = run_batch(ms, ns, k, l, l1max)
