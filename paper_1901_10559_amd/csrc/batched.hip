@@ -7,9 +7,10 @@
 //       BF16 hi + lo, and multiplied by the BF16 Gaussian G on the matrix cores
 //       (v_mfma_f32_16x16x32_bf16, FP32 accumulation): Y_p = G (S A_p) stays in
 //       registers per panel and is written once (FP32, column-major).
-//   batched_cpqr_kernel    one workgroup per problem: column j of Y_p in lane
-//       j (rows 0..RL-1 in LDS, rows RL.. in registers), FP32 data and
-//       Householder updates, trailing norms recomputed in FP64 each step.
+//   batched_cpqr_kernel    one workgroup per problem (1024, 512 or 256
+//       threads by n_p): column j of Y_p in lane j (rows 0..RL-1 in LDS, rows
+//       RL.. in registers), FP32 data and Householder updates, trailing norms
+//       recomputed in FP64 each step.
 //   batched_trsm_kernel    one workgroup per problem: R11 in LDS, FP64
 //       axpy back-substitution, up to 4 lanes per column; writes P_p.
 // Problem p draws its CountSketch from the stream (seed, tag = p) and uses
@@ -294,9 +295,11 @@ __global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a)
 // ---------------------------------------------------------------------------
 // K2: CPQR, FP32 data, FP64 norms
 // ---------------------------------------------------------------------------
-constexpr int BC_THREADS = 1024;
-constexpr int BC_RL = 38;   // rows held in LDS (the first ones: frozen after step RL)
-constexpr int BC_RR = 84;   // rows held in registers (RL + RR >= l)
+constexpr int BC_THREADS = 1024;  // largest workgroup: n_p <= 1024 columns, one per thread
+constexpr int BC_RL = 36;   // rows held in LDS (the first ones: frozen after step RL);
+                            // a multiple of 4, so the register rows' reflector entries
+                            // start 16-byte aligned in LDS
+constexpr int BC_RR = 86;   // rows held in registers (RL + RR >= l)
 static_assert(BC_RL + BC_RR >= 122 && BC_RL + BC_RR <= BS_LMAX, "batched CPQR row split");
 
 // wave argmax of (nu, j): DPP max tree for nu, then DPP min tree over the j
@@ -340,16 +343,21 @@ __device__ __forceinline__ double tree_sum_d(double (&s)[N]) {
     return s[0];
 }
 
-__global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
-    extern __shared__ float ylds[];           // BC_RL x BC_THREADS
+// NT threads per problem, launched for the problems with NT/2 < n_p <= NT
+// (n_p <= NT for the smallest NT), so small problems share a CU and hide each
+// other's per-step latency.
+template <int NT>
+__global__ __launch_bounds__(NT) void batched_cpqr_kernel(BatchArgs a, int nt_min) {
+    extern __shared__ float ylds[];           // BC_RL x NT
     __shared__ __attribute__((aligned(16))) float xf[BS_LMAX];  // pivot column (FP32)
-    __shared__ float vb[BS_LMAX];             // reflector (FP32)
+    __shared__ __attribute__((aligned(16))) float vb[BS_LMAX];  // reflector (FP32)
     __shared__ double s_nu[16];
     __shared__ int s_j[16];
 
     const int p = a.order[blockIdx.x];
     const BProb pr = a.prob[p];
     const int n = pr.n;
+    if (n > NT || n <= nt_min) return;  // another launch owns this problem
     const int l = (int)a.l, k = (int)a.k;
     const int j = threadIdx.x;
     const int lane = j & 63, w = j >> 6;
@@ -363,7 +371,7 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
 #pragma unroll
         for (int r = 0; r < BC_RL; ++r) {
             const float v = Yp[(int64_t)jc * l + min(r, l - 1)];
-            ylds[r * BC_THREADS + j] = (alive && r < l) ? v : 0.f;
+            ylds[r * NT + j] = (alive && r < l) ? v : 0.f;
         }
 #pragma unroll
         for (int r = 0; r < BC_RR; ++r) {
@@ -372,26 +380,32 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
             y[r] = (alive && i < l) ? v : 0.f;
         }
     }
-    // FP64 sum of squares over rows i >= t0 (the LDS rows' loop is unrolled by
-    // 4 so their reads overlap; a full unroll would spill at 1024 threads)
+    // sum of squares over rows i >= t0: squares summed in FP32 over chunks of 8
+    // rows, the chunk sums accumulated in FP64 (relative error <= 8 * 2^-24,
+    // below the FP32 rounding of the data itself).  The LDS rows' loop is
+    // unrolled by 4 so their reads overlap; a full unroll spills at 1024 threads.
     auto norm_from = [&](int t0) -> double {
-        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        double s = 0.0;
+        float f[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
         for (int r = t0; r < BC_RL; ++r) {
-            const double v = (double)ylds[r * BC_THREADS + j];
-            s[r & 3] = fma(v, v, s[r & 3]);
+            const float v = ylds[r * NT + j];
+            f[r & 3] = fmaf(v, v, f[r & 3]);
         }
+        s = (double)((f[0] + f[1]) + (f[2] + f[3]));
 #pragma unroll
         for (int c = 0; c < BC_RR; c += 8) {
             if (BC_RL + c + 8 > t0) {
+                float q = 0.f;
 #pragma unroll
                 for (int r = c; r < c + 8 && r < BC_RR; ++r) {
-                    const double v = (BC_RL + r >= t0) ? (double)y[r] : 0.0;
-                    s[r & 3] = fma(v, v, s[r & 3]);
+                    const float v = (BC_RL + r >= t0) ? y[r] : 0.f;
+                    q = fmaf(v, v, q);
                 }
+                s += (double)q;
             }
         }
-        return tree_sum_d<4>(s);
+        return s;
     };
     double nu = wave_live ? norm_from(0) : 0.0;
     int keff = k;
@@ -413,8 +427,8 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
         double wnu;
         int wj;
         {
-            double m2 = (lane < BC_THREADS / 64) ? s_nu[lane] : -1.0;
-            int q2 = (lane < BC_THREADS / 64) ? s_j[lane] : INT32_MAX;
+            double m2 = (lane < NT / 64) ? s_nu[lane] : -1.0;
+            int q2 = (lane < NT / 64) ? s_j[lane] : INT32_MAX;
             wave_argmax_dpp(m2, q2);
             wnu = m2;
             wj = q2;
@@ -429,7 +443,7 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
 #pragma unroll
             for (int r = 0; r < BC_RR; ++r) xf[BC_RL + r] = y[r];
         }
-        if (j < BC_RL) xf[j] = ylds[j * BC_THREADS + wj];
+        if (j < BC_RL) xf[j] = ylds[j * NT + wj];
         __syncthreads();
         // ---- Householder reflector in FP64 (every wave, same bits); the norm of
         //      the pivot's rows t.. is its published trailing norm wnu
@@ -453,7 +467,7 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
                 float d[4] = {0.f, 0.f, 0.f, 0.f};
                 if (t < BC_RL) {
 #pragma unroll 4
-                    for (int r = t; r < BC_RL; ++r) d[r & 3] = fmaf(vb[r], ylds[r * BC_THREADS + j], d[r & 3]);
+                    for (int r = t; r < BC_RL; ++r) d[r & 3] = fmaf(vb[r], ylds[r * NT + j], d[r & 3]);
                 }
 #pragma unroll
                 for (int c = 0; c < BC_RR; c += 8)
@@ -466,7 +480,7 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
                 if (t < BC_RL) {
 #pragma unroll 4
                     for (int r = t; r < BC_RL; ++r)
-                        ylds[r * BC_THREADS + j] = fmaf(-dt, vb[r], ylds[r * BC_THREADS + j]);
+                        ylds[r * NT + j] = fmaf(-dt, vb[r], ylds[r * NT + j]);
                 }
 #pragma unroll
                 for (int c = 0; c < BC_RR; c += 8)
@@ -491,7 +505,7 @@ __global__ __launch_bounds__(BC_THREADS) void batched_cpqr_kernel(BatchArgs a) {
     // top keff rows of every column -> Rt (FP64); the pivots' diagonal is beta
     if (j < n) {
         double* Rj = a.Rt + roff * (int64_t)k + (int64_t)j * k;
-        for (int i = 0; i < min(keff, BC_RL); ++i) Rj[i] = (double)ylds[i * BC_THREADS + j];
+        for (int i = 0; i < min(keff, BC_RL); ++i) Rj[i] = (double)ylds[i * NT + j];
 #pragma unroll
         for (int r = 0; r < BC_RR; ++r)
             if (BC_RL + r < keff) Rj[BC_RL + r] = (double)y[r];
@@ -664,8 +678,12 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
     {
         ProfScope ps(PK_CPQR, st);
         a.order = (const int32_t*)((const char*)plan + o2);
-        hipLaunchKernelGGL(batched_cpqr_kernel, dim3((unsigned)nprob), dim3(BC_THREADS),
-                           sizeof(float) * BC_RL * BC_THREADS, st, a);
+        hipLaunchKernelGGL(batched_cpqr_kernel<1024>, dim3((unsigned)nprob), dim3(1024),
+                           sizeof(float) * BC_RL * 1024, st, a, 512);
+        hipLaunchKernelGGL(batched_cpqr_kernel<512>, dim3((unsigned)nprob), dim3(512), sizeof(float) * BC_RL * 512,
+                           st, a, 256);
+        hipLaunchKernelGGL(batched_cpqr_kernel<256>, dim3((unsigned)nprob), dim3(256), sizeof(float) * BC_RL * 256,
+                           st, a, 0);
     }
     {
         ProfScope ps(PK_TRSM, st);
