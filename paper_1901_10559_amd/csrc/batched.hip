@@ -2,7 +2,7 @@
 // A_p (m_p x n_p, BF16, row-major), each through Algorithm 2 with a Gaussian
 // second stage and Algorithm 1:
 //   batched_sketch_kernel  one workgroup per problem (largest first): the
-//       CountSketch plan in LDS, then per 256-column panel and per group of 32
+//       CountSketch plan in LDS, then per 128-column panel and per group of 64
 //       buckets, Y1 rows summed in FP32 from 16-byte BF16 loads, split into
 //       BF16 hi + lo, and multiplied by the BF16 Gaussian G on the matrix cores
 //       (v_mfma_f32_16x16x32_bf16, FP32 accumulation): Y_p = G (S A_p) stays in
@@ -82,11 +82,17 @@ struct BatchArgs {
 // ---------------------------------------------------------------------------
 constexpr int BS_THREADS = 512;  // two problems per CU (LDS and registers allow it)
 constexpr int BS_PANEL = 128;   // columns per panel
-constexpr int BS_BG = 32;       // buckets per group (= MFMA K)
+constexpr int BS_BG = 64;       // buckets per group (two MFMA K steps of 32)
+constexpr int BS_YS = BS_BG + 8;  // LDS row of a sketch-tile column (u16; 16-byte multiple)
+// column c of the sketch tile starts at ys_off(c): one extra 16-byte slot every
+// 8 columns, so the gather's 8-column chunks (otherwise 8 * 144 B apart, all in
+// one bank) spread over the banks
+__device__ __forceinline__ int ys_off(int c) { return c * BS_YS + (c >> 3) * 8; }
+constexpr int BS_YN = BS_PANEL * BS_YS + (BS_PANEL / 8) * 8;
 constexpr int BS_LMAX = 128;    // padded sketch height (l <= 128)
 constexpr int BS_MMAX = 4096;   // rows per problem
 constexpr int BS_L1MAX = 512;   // buckets per problem
-constexpr int BS_RIF = 8;       // bucket rows in flight per gather thread
+constexpr int BS_RIF = 2;       // rows in flight per bucket and gather thread (two buckets)
 
 __device__ __forceinline__ uint16_t f2bf_rne(float f) {
     uint32_t u = __float_as_uint(f);
@@ -94,15 +100,15 @@ __device__ __forceinline__ uint16_t f2bf_rne(float f) {
     return (uint16_t)(u >> 16);
 }
 
-__global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a) {
+__global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs a) {  // 2 workgroups per CU
     __shared__ int32_t cnt[BS_L1MAX + 1];
     __shared__ int32_t off[BS_L1MAX + 1];
     __shared__ int32_t rows[BS_MMAX];
     // transposed sketch tile [column][bucket]; rows of 40 entries (80 bytes,
     // a multiple of 16) so each MFMA operand is one 16-byte LDS read
-    __shared__ __attribute__((aligned(16))) uint16_t Y1h[BS_PANEL][BS_BG + 8];
-    __shared__ __attribute__((aligned(16))) uint16_t Y1l[BS_PANEL][BS_BG + 8];
-    __shared__ __attribute__((aligned(16))) uint16_t Gs[BS_LMAX][BS_BG + 8];
+    __shared__ __attribute__((aligned(16))) uint16_t Y1h[BS_YN];
+    __shared__ __attribute__((aligned(16))) uint16_t Y1l[BS_YN];
+    __shared__ __attribute__((aligned(16))) uint16_t Gs[BS_LMAX][BS_YS];
 
     const int p = a.order[blockIdx.x];
     const BProb pr = a.prob[p];
@@ -170,7 +176,7 @@ __global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a)
     const int w = tid >> 6, lane = tid & 63;
     const int rt = w;               // row tile (16 rows of Y), 8 waves = 128 rows
     const int ct0 = 0;              // 8 column tiles = the 128-column panel
-    const int bl = tid >> 4;        // bucket within group (gather phase)
+    const int bl = tid >> 4;        // buckets bl and 32 + bl of the group (gather phase)
     const int ch = tid & 15;        // 8-column chunk within panel (gather phase)
     const uint16_t* Ap = a.A + pr.a_off;
     float* Yp = a.Y + pr.y_off;
@@ -180,12 +186,15 @@ __global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a)
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = v4f32{0.f, 0.f, 0.f, 0.f};
         for (int g0 = 0; g0 < L1; g0 += BS_BG) {
-            // G[:, g0 .. g0 + 32) -> LDS, one 16-byte row chunk per thread (rows
-            // >= l and columns >= L1 are zero); issued first so its latency
-            // overlaps the gather
-            {
-                static_assert(BS_THREADS == BS_LMAX * BS_BG / 8, "one G chunk per thread");
-                const int r = tid >> 2, c8 = (tid & 3) * 8, gc = g0 + c8;
+            // G[:, g0 .. g0 + 64): two 16-byte row chunks per thread (rows >= l
+            // and columns >= L1 are zero), loaded first and stored to LDS after
+            // the gather, so the two loads' latencies overlap
+            uint4 gvals[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                static_assert(2 * BS_THREADS == BS_LMAX * BS_BG / 8, "two G chunks per thread");
+                const int id = tid + u * BS_THREADS;
+                const int r = id >> 3, c8 = (id & 7) * 8, gc = g0 + c8;
                 uint4 v = make_uint4(0u, 0u, 0u, 0u);
                 if (r < l) {
                     const uint16_t* gp = a.G + (int64_t)r * a.l1max + gc;
@@ -194,84 +203,92 @@ __global__ __launch_bounds__(BS_THREADS) void batched_sketch_kernel(BatchArgs a)
                     } else {
                         uint32_t e[8];
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) e[u] = (gc + u < L1) ? gp[u] : 0u;
+                        for (int q = 0; q < 8; ++q) e[q] = (gc + q < L1) ? gp[q] : 0u;
                         v = make_uint4(e[0] | (e[1] << 16), e[2] | (e[3] << 16), e[4] | (e[5] << 16), e[6] | (e[7] << 16));
                     }
                 }
-                *reinterpret_cast<uint4*>(&Gs[r][c8]) = v;
+                gvals[u] = v;
             }
-            // gather: Y1[b][c0 + 8ch .. +8] for b = g0 + bl
+            // gather: Y1[b][c0 + 8ch .. +8] for the two buckets b = g0 + bl and
+            // g0 + 32 + bl; BS_RIF rows of each in flight, each bucket's rows
+            // added in increasing row order
             {
-                const int b = g0 + bl;
                 const int cc = c0 + 8 * ch;
-                float s[8];
+                const bool full = cc + 8 <= n && (n % 8) == 0 && (pr.a_off % 8) == 0;
+                int qb[2], qn[2];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) s[e] = 0.f;
-                if (b < L1 && cc < n) {
-                    const bool full = cc + 8 <= n && (n % 8) == 0 && (pr.a_off % 8) == 0;
-                    int q = off[b];
-                    const int qe = off[b + 1];
-                    if (full) {
-                        // BS_RIF rows in flight, then added in increasing row order
-                        for (; q + BS_RIF <= qe; q += BS_RIF) {
-                            uint4 raw[BS_RIF];
-                            int32_t code[BS_RIF];
+                for (int h = 0; h < 2; ++h) {
+                    const int b = g0 + 32 * h + bl;
+                    const bool ok = b < L1 && cc < n;
+                    qb[h] = ok ? off[b] : 0;
+                    qn[h] = ok ? off[b + 1] - off[b] : 0;
+                }
+                float s[2][8];
 #pragma unroll
-                            for (int u = 0; u < BS_RIF; ++u) {
-                                code[u] = rows[q + u];
-                                const int64_t i = code[u] >= 0 ? code[u] : -(int64_t)code[u] - 1;
-                                raw[u] = load_nt16(Ap + i * n + cc);
-                            }
+                for (int h = 0; h < 2; ++h)
 #pragma unroll
-                            for (int u = 0; u < BS_RIF; ++u) {
-                                const uint32_t wv[4] = {raw[u].x, raw[u].y, raw[u].z, raw[u].w};
+                    for (int e = 0; e < 8; ++e) s[h][e] = 0.f;
+                for (int q0 = 0; q0 < max(qn[0], qn[1]); q0 += BS_RIF) {
+                    uint32_t raw[2][BS_RIF][4];
+                    int32_t code[2][BS_RIF];
 #pragma unroll
-                                for (int e = 0; e < 8; ++e) {
-                                    const float xe = bf16_to_f32((uint16_t)(wv[e >> 1] >> (16 * (e & 1))));
-                                    s[e] = code[u] < 0 ? s[e] - xe : s[e] + xe;
-                                }
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int u = 0; u < BS_RIF; ++u) {
+                            const bool in = q0 + u < qn[h];
+                            code[h][u] = in ? rows[qb[h] + q0 + u] : 0;
+                            const int64_t i = code[h][u] >= 0 ? code[h][u] : -(int64_t)code[h][u] - 1;
+                            const uint16_t* rowp = Ap + i * n + cc;
+                            if (in && full) {
+                                const uint4 v = load_nt16(rowp);
+                                raw[h][u][0] = v.x; raw[h][u][1] = v.y; raw[h][u][2] = v.z; raw[h][u][3] = v.w;
+                            } else {
+                                uint32_t hh[8];
+#pragma unroll
+                                for (int e = 0; e < 8; ++e) hh[e] = (in && cc + e < n) ? rowp[e] : 0u;
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) raw[h][u][e] = hh[2 * e] | (hh[2 * e + 1] << 16);
                             }
                         }
-                    }
-                    for (; q < qe; ++q) {
-                        const int32_t code = rows[q];
-                        const int64_t i = code >= 0 ? code : -(int64_t)code - 1;
-                        const uint16_t* rowp = Ap + i * n + cc;
-                        float x[8];
-                        if (full) {
-                            const uint4 raw = load_nt16(rowp);
-                            x[0] = bf16_to_f32(raw.x & 0xffff); x[1] = bf16_to_f32(raw.x >> 16);
-                            x[2] = bf16_to_f32(raw.y & 0xffff); x[3] = bf16_to_f32(raw.y >> 16);
-                            x[4] = bf16_to_f32(raw.z & 0xffff); x[5] = bf16_to_f32(raw.z >> 16);
-                            x[6] = bf16_to_f32(raw.w & 0xffff); x[7] = bf16_to_f32(raw.w >> 16);
-                        } else {
 #pragma unroll
-                            for (int e = 0; e < 8; ++e) x[e] = (cc + e < n) ? bf16_to_f32(rowp[e]) : 0.f;
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int u = 0; u < BS_RIF; ++u) {
+                            if (q0 + u >= qn[h]) break;
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) {
+                                const float xe = bf16_to_f32((uint16_t)(raw[h][u][e >> 1] >> (16 * (e & 1))));
+                                s[h][e] = code[h][u] < 0 ? s[h][e] - xe : s[h][e] + xe;
+                            }
                         }
+                }
 #pragma unroll
-                        for (int e = 0; e < 8; ++e) s[e] = code < 0 ? s[e] - x[e] : s[e] + x[e];
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const uint16_t hi = f2bf_rne(s[h][e]);
+                        const float hf = bf16_to_f32(hi);
+                        const int o = ys_off(8 * ch + e) + 32 * h + bl;
+                        Y1h[o] = hi;
+                        Y1l[o] = f2bf_rne(s[h][e] - hf);
                     }
-                }
+            }
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const uint16_t h = f2bf_rne(s[e]);
-                    const float hf = bf16_to_f32(h);
-                    Y1h[8 * ch + e][bl] = h;
-                    Y1l[8 * ch + e][bl] = f2bf_rne(s[e] - hf);
-                }
+            for (int u = 0; u < 2; ++u) {
+                const int id = tid + u * BS_THREADS;
+                *reinterpret_cast<uint4*>(&Gs[id >> 3][(id & 7) * 8]) = gvals[u];
             }
             __syncthreads();
-            // Y(rows rt*16.., cols ct*16..) += G tile (16 x 32) * Y1 (32 x 16), hi and lo
-            {
-                const v8bf16 av =
-                    __builtin_bit_cast(v8bf16, *reinterpret_cast<const uint4*>(&Gs[rt * 16 + (lane & 15)][8 * (lane >> 4)]));
+            // Y(rows rt*16.., cols ct*16..) += G tile (16 x 64) * Y1 (64 x 16), hi and lo
+#pragma unroll
+            for (int kk = 0; kk < BS_BG / 32; ++kk) {
+                const v8bf16 av = __builtin_bit_cast(
+                    v8bf16, *reinterpret_cast<const uint4*>(&Gs[rt * 16 + (lane & 15)][32 * kk + 8 * (lane >> 4)]));
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    const int col = (ct0 + q) * 16 + (lane & 15);
-                    const v8bf16 bh =
-                        __builtin_bit_cast(v8bf16, *reinterpret_cast<const uint4*>(&Y1h[col][8 * (lane >> 4)]));
-                    const v8bf16 blo =
-                        __builtin_bit_cast(v8bf16, *reinterpret_cast<const uint4*>(&Y1l[col][8 * (lane >> 4)]));
+                    const int o = ys_off((ct0 + q) * 16 + (lane & 15)) + 32 * kk + 8 * (lane >> 4);
+                    const v8bf16 bh = __builtin_bit_cast(v8bf16, *reinterpret_cast<const uint4*>(&Y1h[o]));
+                    const v8bf16 blo = __builtin_bit_cast(v8bf16, *reinterpret_cast<const uint4*>(&Y1l[o]));
                     acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bh, acc[q], 0, 0, 0);
                     acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, blo, acc[q], 0, 0, 0);
                 }
