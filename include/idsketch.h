@@ -142,18 +142,24 @@ ids_status id_select(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t r
  *   lambda   double[R] s-values.
  *   Jlen     TensorSketch length L (power of two, 16 <= Jlen <= 4096).
  *   k        target rank, k < R, k <= Jlen.
+ *   l, G     optional Gaussian second stage (the Gaussian sketch of Section
+ *            1.3.1 applied to the TensorSketch): l = 0 factors T M itself
+ *            (Algorithm 3 as printed); k <= l <= Jlen factors G (T M), G an
+ *            l x Jlen row-major FP64 device buffer (caller-owned, e.g. N(0,1)
+ *            entries; NULL is an error when l > 0).
  *   Y        optional output (may be NULL): the sketch T M, Jlen x R
- *            column-major (leading dimension Jlen).
+ *            column-major (leading dimension Jlen), before any projection.
  *   J, P, k_eff  as in id_select; lambda_hat double[k] (entries >= k_eff
  *            are zero).
  * Random maps h_n, s_n: stream (seed, tag n + 1) over [0, I_n) into Jlen.
  */
 ids_status ids_tensor_workspace_size(int32_t N, const int64_t* dims, int64_t R, int64_t k,
-                                     int64_t Jlen, size_t* bytes);
+                                     int64_t Jlen, int64_t l, size_t* bytes);
 ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* const* factors,
                      const int64_t* ld, const double* lambda, int64_t k, int64_t Jlen,
-                     uint64_t seed, double* Y, int64_t* J, double* P, double* lambda_hat,
-                     int64_t* k_eff, void* ws, size_t ws_bytes, void* stream);
+                     int64_t l, const double* G, uint64_t seed, double* Y, int64_t* J,
+                     double* P, double* lambda_hat, int64_t* k_eff, void* ws, size_t ws_bytes,
+                     void* stream);
 
 /*
  * Batched mixed-precision matrix ID (hierarchical-matrix style block

@@ -231,10 +231,13 @@ def tensor_maps(seed: int, dims, Jlen: int):
     return [hash_maps(seed, n + 1, int(d), Jlen) for n, d in enumerate(dims)]
 
 
-def tensor_id(factors, lam, *, k: int, Jlen: int, seed: int, trace: bool = False):
+def tensor_id(factors, lam, *, k: int, Jlen: int, seed: int, G=None, trace: bool = False):
+    """Algorithm 3; with G (l x Jlen) the Gaussian second stage G (T M) is
+    factored instead of T M (Section 1.3.1's Gaussian sketch on the sketch)."""
     maps = tensor_maps(seed, [f.shape[0] for f in factors], Jlen)
     Y = tensorsketch(factors, lam, maps, Jlen)
-    J, P, keff, R, nu = cpqr_id(Y, k, trace=trace)
+    Yf = Y if G is None else gemm(G, Y)
+    J, P, keff, R, nu = cpqr_id(Yf, k, trace=trace)
     lh = lambda_hat(P[:keff], J[:keff], lam)
     return dict(Y=Y, J=J, P=P, k_eff=keff, lambda_hat=lh, nu=nu, R=R)
 

@@ -74,8 +74,8 @@ def lib():
         L.id_project.argtypes = [c_i32, c_i64, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp]
         L.ids_select_workspace_size.argtypes = [c_i64, c_i64, c_i64, P(c_sz)]
         L.id_select.argtypes = [c_vp, c_i32, c_i64, c_i64, c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]
-        L.ids_tensor_workspace_size.argtypes = [c_i32, c_vp, c_i64, c_i64, c_i64, P(c_sz)]
-        L.tensor_id.argtypes = [c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_u64, c_vp, c_vp, c_vp,
+        L.ids_tensor_workspace_size.argtypes = [c_i32, c_vp, c_i64, c_i64, c_i64, c_i64, P(c_sz)]
+        L.tensor_id.argtypes = [c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_u64, c_vp, c_vp, c_vp,
                                 c_vp, c_vp, c_vp, c_sz, c_vp]
         L.ids_batched_plan_size.argtypes = [c_i64, P(c_sz)]
         L.ids_batched_plan.argtypes = [c_i64, c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_sz, P(c_sz), c_vp]
@@ -244,9 +244,11 @@ def matrix_id(A, k: int, l1: int, l: int | None = None, *, seed: int = 0, tag: i
     return dict(Y=Y, J=J, P=P, k_eff=keff)
 
 
-def tensor_id(factors, lam, k: int, Jlen: int, *, seed: int = 0, return_Y: bool = False, stream=None):
+def tensor_id(factors, lam, k: int, Jlen: int, *, seed: int = 0, l: int = 0, G=None, return_Y: bool = False,
+              stream=None):
     """Algorithm 3.  factors: list of I_n x R float64 device tensors with unit
-    row stride (column-major, e.g. ``F.t().contiguous().t()``)."""
+    row stride (column-major, e.g. ``F.t().contiguous().t()``).  l > 0 with an
+    l x Jlen float64 G adds the Gaussian second stage before the CPQR."""
     torch = _torch()
     N = len(factors)
     R = factors[0].shape[1]
@@ -257,8 +259,11 @@ def tensor_id(factors, lam, k: int, Jlen: int, *, seed: int = 0, return_Y: bool 
     ld = (c_i64 * N)(*[f.stride(1) for f in factors])
     fptr = (c_vp * N)(*[f.data_ptr() for f in factors])
     dev = factors[0].device
+    if l:
+        if G is None or G.dtype != torch.float64 or tuple(G.shape) != (l, Jlen) or not G.is_contiguous():
+            raise IdsError("G must be a contiguous float64 l x Jlen tensor when l > 0")
     nbytes = c_sz(0)
-    _check(lib().ids_tensor_workspace_size(N, ctypes.cast(dims, c_vp), R, k, Jlen, ctypes.byref(nbytes)),
+    _check(lib().ids_tensor_workspace_size(N, ctypes.cast(dims, c_vp), R, k, Jlen, l, ctypes.byref(nbytes)),
            "ids_tensor_workspace_size")
     ws, wsb = _workspace(torch, nbytes.value, dev, stream)
     Y = torch.empty((R, Jlen), dtype=torch.float64, device=dev) if return_Y else None
@@ -267,7 +272,8 @@ def tensor_id(factors, lam, k: int, Jlen: int, *, seed: int = 0, return_Y: bool 
     lh = torch.empty(k, dtype=torch.float64, device=dev)
     keff = torch.empty(1, dtype=torch.int64, device=dev)
     _check(lib().tensor_id(N, ctypes.cast(dims, c_vp), R, ctypes.cast(fptr, c_vp), ctypes.cast(ld, c_vp),
-                           c_vp(lam.data_ptr()), k, Jlen, seed, c_vp(Y.data_ptr()) if Y is not None else None,
+                           c_vp(lam.data_ptr()), k, Jlen, l, c_vp(G.data_ptr()) if l else None, seed,
+                           c_vp(Y.data_ptr()) if Y is not None else None,
                            c_vp(J.data_ptr()), c_vp(P.data_ptr()), c_vp(lh.data_ptr()), c_vp(keff.data_ptr()),
                            c_vp(ws[1]) if ws else None, wsb, _stream(torch, stream)), "tensor_id")
     out = dict(J=J, P=P, lambda_hat=lh, k_eff=keff)

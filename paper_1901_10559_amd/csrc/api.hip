@@ -310,11 +310,11 @@ ids_status id_select(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t r
 // ---------------------------------------------------------------------------
 struct TensorLayout {
     PlanShape ps[8];
-    size_t plans, tw, y, sel, total;
+    size_t plans, tw, y, yp, sel, total;
     SelectPlan sp;
 };
 
-static ids_status validate_tensor(int32_t N, const int64_t* dims, int64_t R, int64_t k, int64_t Jlen) {
+static ids_status validate_tensor(int32_t N, const int64_t* dims, int64_t R, int64_t k, int64_t Jlen, int64_t l) {
     if (N < 1 || N > 8) return fail(IDS_EINVAL, "N must be in [1, 8]");
     if (!dims) return fail(IDS_EINVAL, "dims is NULL");
     for (int n = 0; n < N; ++n)
@@ -322,10 +322,11 @@ static ids_status validate_tensor(int32_t N, const int64_t* dims, int64_t R, int
     if (R < 2) return fail(IDS_EINVAL, "R must be >= 2");
     if (Jlen < 16 || Jlen > 4096 || (Jlen & (Jlen - 1))) return fail(IDS_EINVAL, "Jlen must be a power of two in [16, 4096]");
     if (k < 1 || k >= R || k > Jlen) return fail(IDS_EINVAL, "k must satisfy 1 <= k < R and k <= Jlen");
+    if (l != 0 && (l < k || l > Jlen)) return fail(IDS_EINVAL, "l must be 0 (no projection) or satisfy k <= l <= Jlen");
     return IDS_OK;
 }
 
-static ids_status tensor_layout(int32_t N, const int64_t* dims, int64_t R, int64_t k, int64_t Jlen,
+static ids_status tensor_layout(int32_t N, const int64_t* dims, int64_t R, int64_t k, int64_t Jlen, int64_t l,
                                 TensorLayout& T) {
     T.plans = 0;
     for (int n = 0; n < N; ++n) {
@@ -334,31 +335,34 @@ static ids_status tensor_layout(int32_t N, const int64_t* dims, int64_t R, int64
     }
     T.tw = align256(sizeof(double2) * (size_t)Jlen);
     T.y = align256(sizeof(double) * (size_t)Jlen * R);
-    ids_status s = select_plan(Jlen, R, k, T.sp);
+    T.yp = l ? align256(sizeof(double) * (size_t)l * R) : 0;
+    ids_status s = select_plan(l ? l : Jlen, R, k, T.sp);
     if (s) return s;
     T.sel = select_bytes(T.sp);
-    T.total = T.plans + T.tw + T.y + T.sel;
+    T.total = T.plans + T.tw + T.y + T.yp + T.sel;
     return IDS_OK;
 }
 
 ids_status ids_tensor_workspace_size(int32_t N, const int64_t* dims, int64_t R, int64_t k, int64_t Jlen,
-                                     size_t* bytes) {
+                                     int64_t l, size_t* bytes) {
     g_err.clear();
     if (!bytes) return fail(IDS_EINVAL, "bytes is NULL");
-    ids_status s = validate_tensor(N, dims, R, k, Jlen);
+    ids_status s = validate_tensor(N, dims, R, k, Jlen, l);
     if (s) return s;
     TensorLayout T;
-    if ((s = tensor_layout(N, dims, R, k, Jlen, T))) return s;
+    if ((s = tensor_layout(N, dims, R, k, Jlen, l, T))) return s;
     *bytes = T.total;
     return IDS_OK;
 }
 
 ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* const* factors, const int64_t* ld,
-                     const double* lambda, int64_t k, int64_t Jlen, uint64_t seed, double* Y, int64_t* J, double* P,
-                     double* lambda_hat, int64_t* k_eff, void* ws, size_t ws_bytes, void* stream) {
+                     const double* lambda, int64_t k, int64_t Jlen, int64_t l, const double* G, uint64_t seed,
+                     double* Y, int64_t* J, double* P, double* lambda_hat, int64_t* k_eff, void* ws,
+                     size_t ws_bytes, void* stream) {
     g_err.clear();
-    ids_status s = validate_tensor(N, dims, R, k, Jlen);
+    ids_status s = validate_tensor(N, dims, R, k, Jlen, l);
     if (s) return s;
+    if (l && !G) return fail(IDS_EINVAL, "G must be non-NULL when l > 0");
     if (!factors || !ld || !lambda || !J || !P || !lambda_hat || !k_eff)
         return fail(IDS_EINVAL, "factors, ld, lambda, J, P, lambda_hat and k_eff must be non-NULL");
     for (int n = 0; n < N; ++n) {
@@ -367,7 +371,7 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
     }
     if (ts_lds_bytes(Jlen) > lds_limit()) return fail(IDS_EINVAL, "Jlen too large for the LDS FFT on this device");
     TensorLayout T;
-    if ((s = tensor_layout(N, dims, R, k, Jlen, T))) return s;
+    if ((s = tensor_layout(N, dims, R, k, Jlen, l, T))) return s;
     if ((s = check_ws(ws, ws_bytes, T.total))) return s;
     hipStream_t st = (hipStream_t)stream;
     char* p = (char*)ws;
@@ -377,6 +381,8 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
     p += T.tw;
     double* Yw = (double*)p;
     p += T.y;
+    double* Yp = (double*)p;
+    p += T.yp;
     char* sel = p;
     double* Yout = Y ? Y : Yw;
     {
@@ -390,7 +396,12 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
         ProfScope ps(PK_TS, st);
         if ((s = tensorsketch(N, dims, R, factors, ld, lambda, Jlen, pb, tw, Yout, st))) return s;
     }
-    if ((s = select_run(T.sp, Yout, IDS_F64, 1, Jlen, J, P, k_eff, sel, st))) return s;
+    if (l) {
+        // Gaussian second stage: Yp (l x R, column-major) = G (l x Jlen) T M
+        ProfScope ps(PK_PROJ, st);
+        if ((s = project(IDS_F64, l, Jlen, R, G, Yout, Jlen, Yp, l, st, true))) return s;
+    }
+    if ((s = select_run(T.sp, l ? Yp : Yout, IDS_F64, 1, l ? l : Jlen, J, P, k_eff, sel, st))) return s;
     ProfScope ps(PK_LHAT, st);
     return ids::lambda_hat(k, R, P, J, k_eff, lambda, lambda_hat, st);
 }

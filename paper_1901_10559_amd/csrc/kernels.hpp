@@ -54,7 +54,7 @@ ids_status cs_csr(const int64_t* rowptr, const int32_t* colind, const double* va
 
 // ---- projection GEMM (MFMA): Y(col-major, ldy) = G (l x q) * Y1 (q x n, ld1) --
 ids_status project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void* G, const void* Y1, int64_t ld1,
-                   void* Y, int64_t ldy, hipStream_t st);
+                   void* Y, int64_t ldy, hipStream_t st, bool y1_colmajor = false);
 
 // ---- CPQR + interpolation matrix --------------------------------------------
 struct SelectPlan {

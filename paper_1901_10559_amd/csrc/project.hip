@@ -47,7 +47,10 @@ struct Pbk {
 // The next K slice is loaded into registers while the current one is
 // multiplied from LDS, so one barrier pair covers PBK = 64 (FP32) or 32 (FP64)
 // columns of G.
-template <typename T>
+// BCOL: Y1 column-major (entry (k, j) at Y1[j * ld1 + k]; the staging threads
+// then walk k fastest so the loads stay coalesced), else row-major
+// (Y1[k * ld1 + j]).
+template <typename T, bool BCOL>
 __global__ __launch_bounds__(256) void project_kernel(int64_t l, int64_t q, int64_t n, const T* __restrict__ G,
                                                       const T* __restrict__ Y1, int64_t ld1, T* __restrict__ Y,
                                                       int64_t ldy) {
@@ -81,9 +84,9 @@ __global__ __launch_bounds__(256) void project_kernel(int64_t l, int64_t q, int6
 #pragma unroll
         for (int e = 0; e < NBA; ++e) {
             const int idx = tid + e * 256;
-            const int r = idx / PBN, c = idx % PBN;
+            const int r = BCOL ? idx % PBK : idx / PBN, c = BCOL ? idx / PBK : idx % PBN;
             const int64_t gr = k0 + r, gc = col0 + c;
-            bv[e] = (gr < q && gc < n) ? Y1[gr * ld1 + gc] : (T)0;
+            bv[e] = (gr < q && gc < n) ? (BCOL ? Y1[gc * ld1 + gr] : Y1[gr * ld1 + gc]) : (T)0;
         }
     };
     auto store = [&]() {
@@ -95,7 +98,10 @@ __global__ __launch_bounds__(256) void project_kernel(int64_t l, int64_t q, int6
 #pragma unroll
         for (int e = 0; e < NBA; ++e) {
             const int idx = tid + e * 256;
-            Bs[idx / PBN][idx % PBN] = bv[e];
+            if (BCOL)
+                Bs[idx % PBK][idx / PBK] = bv[e];
+            else
+                Bs[idx / PBN][idx % PBN] = bv[e];
         }
     };
     load(0);
@@ -135,16 +141,20 @@ __global__ __launch_bounds__(256) void project_kernel(int64_t l, int64_t q, int6
 }
 
 ids_status project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void* G, const void* Y1, int64_t ld1,
-                   void* Y, int64_t ldy, hipStream_t st) {
+                   void* Y, int64_t ldy, hipStream_t st, bool y1_colmajor) {
     dim3 grid((unsigned)((n + PBN - 1) / PBN), (unsigned)((l + PBM - 1) / PBM));
     if (dtype == IDS_F64) {
-        hipLaunchKernelGGL(project_kernel<double>, grid, dim3(256), 0, st, l, q, n, (const double*)G,
-                           (const double*)Y1, ld1, (double*)Y, ldy);
-    } else if (dtype == IDS_F32) {
-        hipLaunchKernelGGL(project_kernel<float>, grid, dim3(256), 0, st, l, q, n, (const float*)G,
+        if (y1_colmajor)
+            hipLaunchKernelGGL((project_kernel<double, true>), grid, dim3(256), 0, st, l, q, n, (const double*)G,
+                               (const double*)Y1, ld1, (double*)Y, ldy);
+        else
+            hipLaunchKernelGGL((project_kernel<double, false>), grid, dim3(256), 0, st, l, q, n, (const double*)G,
+                               (const double*)Y1, ld1, (double*)Y, ldy);
+    } else if (dtype == IDS_F32 && !y1_colmajor) {
+        hipLaunchKernelGGL((project_kernel<float, false>), grid, dim3(256), 0, st, l, q, n, (const float*)G,
                            (const float*)Y1, ld1, (float*)Y, ldy);
     } else {
-        set_error("projection supports IDS_F64 and IDS_F32");
+        set_error("projection supports IDS_F64 and IDS_F32 (row-major sketch)");
         return IDS_EDTYPE;
     }
     return check_launch("projection");

@@ -20,7 +20,7 @@ from __future__ import annotations
 import numpy as np
 
 # purpose tags for independent generator streams
-_T_U, _T_V, _T_NOISE, _T_G, _T_CSR, _T_CP, _T_BATCH, _T_PERM = range(1, 9)
+_T_U, _T_V, _T_NOISE, _T_G, _T_CSR, _T_CP, _T_BATCH, _T_PERM, _T_SPARSE = range(1, 10)
 
 
 def rng(seed: int, tag: int, *more: int) -> np.random.Generator:
@@ -150,6 +150,29 @@ def cp_tensor(dims=(2000, 2000, 2000), R: int = 2000, nbase: int = 50, pert: flo
     lo, hi = np.log10(lam_range[0]), np.log10(lam_range[1])
     lam = 10.0 ** g.uniform(lo, hi, size=R)
     return factors, lam, base_of
+
+
+def cp_sparse(N: int = 5, I: int = 10000, R: int = 2000, K: int = 200, density: float = 0.01, seed: int = 0):
+    """Sparse N-way CP tensor of the paper's synthetic tensor experiment (Section
+    on tensor ID experiments, experiment 1): every factor column is a random
+    sparse vector with the given density (nonzero positions uniform without
+    replacement, N(0, 1) values), scaled to unit 2-norm as the CP form requires;
+    lambda_r = 10^(-8 (r - 1) / R) for r <= K and 10^-8 beyond (the schedule
+    as printed, with the paper's R = 10000 and K = 1000 scaled down to R, K).
+    Factors are returned dense, I x R, column-major."""
+    g = rng(seed, _T_SPARSE)
+    nnz = max(1, int(round(density * I)))
+    factors = []
+    for _ in range(N):
+        F = np.zeros((I, R), dtype=np.float64, order="F")
+        for r in range(R):
+            rows = g.choice(I, size=nnz, replace=False)
+            v = g.standard_normal(nnz)
+            F[rows, r] = v / np.linalg.norm(v)
+        factors.append(F)
+    r = np.arange(1, R + 1)
+    lam = np.where(r <= K, 10.0 ** (-8.0 * (r - 1) / R), 1e-8)
+    return factors, lam
 
 
 # --------------------------------------------------------------------------

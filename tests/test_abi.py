@@ -75,10 +75,12 @@ def test_tensor_rejects_bad_arguments_without_gpu():
     nb = ctypes.c_size_t(0)
     dims = (ctypes.c_int64 * 3)(10, 10, 10)
     p = ctypes.cast(dims, ctypes.c_void_p)
-    assert L.ids_tensor_workspace_size(3, p, 20, 5, 100, ctypes.byref(nb)) == 1   # Jlen not power of 2
-    assert L.ids_tensor_workspace_size(3, p, 20, 20, 64, ctypes.byref(nb)) == 1   # k >= R
-    assert L.ids_tensor_workspace_size(9, p, 20, 5, 64, ctypes.byref(nb)) == 1    # N > 8
-    assert L.ids_tensor_workspace_size(3, p, 20, 5, 8192, ctypes.byref(nb)) == 1  # Jlen > 4096
+    assert L.ids_tensor_workspace_size(3, p, 20, 5, 100, 0, ctypes.byref(nb)) == 1   # Jlen not power of 2
+    assert L.ids_tensor_workspace_size(3, p, 20, 20, 64, 0, ctypes.byref(nb)) == 1   # k >= R
+    assert L.ids_tensor_workspace_size(9, p, 20, 5, 64, 0, ctypes.byref(nb)) == 1    # N > 8
+    assert L.ids_tensor_workspace_size(3, p, 20, 5, 8192, 0, ctypes.byref(nb)) == 1  # Jlen > 4096
+    assert L.ids_tensor_workspace_size(3, p, 20, 5, 64, 4, ctypes.byref(nb)) == 1    # projection l < k
+    assert L.ids_tensor_workspace_size(3, p, 20, 5, 64, 65, ctypes.byref(nb)) == 1   # projection l > Jlen
 
 
 def test_binding_refuses_without_gpu():

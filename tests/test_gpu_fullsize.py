@@ -106,6 +106,44 @@ def test_tensor_id_2000cubed_R2000_J4096():
         assert abs(lh[t] - grp) <= 1e-6 * abs(grp)
 
 
+def test_tensor_id_2000cubed_projected_l60():
+    factors, lam, base_of = synth.cp_tensor()
+    Jlen, k, l = 4096, 50, 60
+    G = synth.gaussian(l, Jlen, seed=0)
+    ft = [dev(np.asarray(f).T).t() for f in factors]
+    r = ids.tensor_id(ft, dev(lam), k, Jlen, seed=0, l=l, G=dev(G))
+    J = r["J"].cpu().numpy()
+    P = r["P"].cpu().numpy()
+    lh = r["lambda_hat"].cpu().numpy()
+    assert int(r["k_eff"].item()) == k
+    assert np.array_equal(P[:, J], np.eye(k))
+    assert len(set(base_of[J].tolist())) == k
+    for t in range(k):
+        grp = lam[base_of == base_of[J[t]]].sum()
+        assert abs(lh[t] - grp) <= 1e-6 * abs(grp)
+
+
+def test_sparse5way_I10000_R2000_projected():
+    # the sparse 5-way workload in the launch configuration the benchmark
+    # times: sampled sketch columns against the direct convolution, and the
+    # properties of the ID at full size
+    factors, lam = synth.cp_sparse(N=5, I=10000, R=2000, K=200, density=0.01, seed=0)
+    Jlen, k, l = 2048, 200, 210
+    G = synth.gaussian(l, Jlen, seed=0)
+    ft = [dev(np.asarray(f).T).t() for f in factors]
+    r = ids.tensor_id(ft, dev(lam), k, Jlen, seed=0, l=l, G=dev(G), return_Y=True)
+    torch.cuda.synchronize()
+    cols = np.linspace(0, 1999, 10).astype(np.int64)
+    Yo = oracle.tensorsketch(factors, lam, oracle.tensor_maps(0, [10000] * 5, Jlen), Jlen, cols=cols)
+    Yg = r["Y"][:, torch.from_numpy(cols).to(DEV)].cpu().numpy()
+    scale = np.linalg.norm(Yo, axis=0, keepdims=True)
+    assert np.max(np.abs(Yg - Yo) / scale) <= 1e-13
+    J = r["J"].cpu().numpy()
+    P = r["P"].cpu().numpy()
+    assert int(r["k_eff"].item()) == k
+    assert np.array_equal(P[:, J], np.eye(k))
+
+
 def test_batched_full_shape_sample():
     # 192 problems drawn from the full shape distribution, same launch
     # configuration per problem as the 4096-problem benchmark batch

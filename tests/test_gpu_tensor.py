@@ -75,3 +75,63 @@ def test_tensor_id_duplicated_terms_closed_form():
     assert sorted(base_of[J]) == [0, 1, 2, 3, 4]
     for t, b in enumerate(base_of[J]):
         np.testing.assert_allclose(lh[t], lam[base_of == b].sum(), rtol=1e-10)
+
+
+def tie_aware_J(Jg, Jo, nu, rel=1e-12):
+    if np.array_equal(Jg, Jo):
+        return True
+    t = int(np.argmax(Jg != Jo))
+    row = np.sort(nu[t][nu[t] >= 0])[::-1]
+    return len(row) > 1 and (row[0] - row[1]) <= rel * row[0]
+
+
+# Gaussian second stage on the TensorSketch (G (T M), l = k + p rows), the same
+# G buffer on both sides
+@pytest.mark.parametrize("dims,R,nbase,Jlen,k,l", [((60, 50, 40), 120, 8, 128, 8, 18),
+                                                   ((200, 150, 100), 400, 20, 512, 20, 30),
+                                                   ((300, 300, 300), 301, 30, 2048, 30, 40),
+                                                   ((100, 90, 80), 200, 12, 4096, 12, 300)])
+def test_tensor_id_projected_parity(dims, R, nbase, Jlen, k, l):
+    factors, lam, base_of = synth.cp_tensor(dims=dims, R=R, nbase=nbase, pert=1e-8, seed=R + 1)
+    G = synth.gaussian(l, Jlen, seed=l)
+    r = ids.tensor_id([dev_cols(f) for f in factors], torch.from_numpy(lam).to(DEV), k, Jlen, seed=4, l=l,
+                      G=torch.from_numpy(G).to(DEV))
+    o = oracle.tensor_id(factors, lam, k=k, Jlen=Jlen, seed=4, G=G, trace=True)
+    J = r["J"].cpu().numpy()
+    assert int(r["k_eff"].item()) == o["k_eff"] == k
+    assert tie_aware_J(J, o["J"], o["nu"])
+    assert len(set(base_of[J])) == k
+    if np.array_equal(J, o["J"]):
+        P = r["P"].cpu().numpy()
+        assert np.linalg.norm(P - o["P"]) <= 1e-10 * np.linalg.norm(o["P"])
+        lh = r["lambda_hat"].cpu().numpy()
+        assert np.max(np.abs(lh - o["lambda_hat"]) / np.abs(o["lambda_hat"])) <= 1e-10
+
+
+# the paper's synthetic sparse 5-way CP tensors (density 1%), scaled down
+@pytest.mark.parametrize("I,R,K,Jlen,l", [(1000, 500, 50, 512, 60), (400, 120, 12, 256, 0)])
+def test_tensor_id_sparse5_parity(I, R, K, Jlen, l):
+    factors, lam = synth.cp_sparse(N=5, I=I, R=R, K=K, density=0.01, seed=I)
+    G = synth.gaussian(l, Jlen, seed=9) if l else None
+    r = ids.tensor_id([dev_cols(f) for f in factors], torch.from_numpy(lam).to(DEV), K, Jlen, seed=5, l=l,
+                      G=torch.from_numpy(G).to(DEV) if l else None)
+    o = oracle.tensor_id(factors, lam, k=K, Jlen=Jlen, seed=5, G=G, trace=True)
+    J = r["J"].cpu().numpy()
+    assert int(r["k_eff"].item()) == o["k_eff"] == K
+    assert tie_aware_J(J, o["J"], o["nu"])
+    if np.array_equal(J, o["J"]):
+        P = r["P"].cpu().numpy()
+        assert np.linalg.norm(P - o["P"]) <= 1e-10 * np.linalg.norm(o["P"])
+        lh = r["lambda_hat"].cpu().numpy()
+        assert np.max(np.abs(lh - o["lambda_hat"]) / np.abs(o["lambda_hat"])) <= 1e-10
+    if R <= 200:
+        # the same error as the oracle's skeleton (Gram identity in long double)
+        eg = oracle.tensor_error(factors, lam, J, r["lambda_hat"].cpu().numpy())
+        eo = oracle.tensor_error(factors, lam, o["J"], o["lambda_hat"])
+        assert eg <= 1.01 * eo + 1e-12
+
+
+def test_tensor_id_projection_rejects_missing_G():
+    factors, lam, _ = synth.cp_tensor(dims=(20, 20, 20), R=30, nbase=5, seed=1)
+    with pytest.raises(ids.IdsError):
+        ids.tensor_id([dev_cols(f) for f in factors], torch.from_numpy(lam).to(DEV), 5, 64, l=10, G=None)
