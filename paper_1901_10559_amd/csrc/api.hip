@@ -310,7 +310,8 @@ ids_status id_select(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t r
 // ---------------------------------------------------------------------------
 struct TensorLayout {
     PlanShape ps[8];
-    size_t plans, tw, y, yp, sel, total;
+    size_t plans, tw, y, yp, part, sel, total;
+    int splits;
     SelectPlan sp;
 };
 
@@ -336,10 +337,12 @@ static ids_status tensor_layout(int32_t N, const int64_t* dims, int64_t R, int64
     T.tw = align256(sizeof(double2) * (size_t)Jlen);
     T.y = align256(sizeof(double) * (size_t)Jlen * R);
     T.yp = l ? align256(sizeof(double) * (size_t)l * R) : 0;
+    T.splits = l ? project_splits(l, Jlen, R) : 1;
+    T.part = T.splits > 1 ? align256(sizeof(double) * (size_t)T.splits * l * R) : 0;
     ids_status s = select_plan(l ? l : Jlen, R, k, T.sp);
     if (s) return s;
     T.sel = select_bytes(T.sp);
-    T.total = T.plans + T.tw + T.y + T.yp + T.sel;
+    T.total = T.plans + T.tw + T.y + T.yp + T.part + T.sel;
     return IDS_OK;
 }
 
@@ -383,6 +386,8 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
     p += T.y;
     double* Yp = (double*)p;
     p += T.yp;
+    double* part = (double*)p;
+    p += T.part;
     char* sel = p;
     double* Yout = Y ? Y : Yw;
     {
@@ -399,7 +404,7 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
     if (l) {
         // Gaussian second stage: Yp (l x R, column-major) = G (l x Jlen) T M
         ProfScope ps(PK_PROJ, st);
-        if ((s = project(IDS_F64, l, Jlen, R, G, Yout, Jlen, Yp, l, st, true))) return s;
+        if ((s = project_split_f64(l, Jlen, R, G, Yout, Jlen, true, Yp, l, T.splits, part, st))) return s;
     }
     if ((s = select_run(T.sp, l ? Yp : Yout, IDS_F64, 1, l ? l : Jlen, J, P, k_eff, sel, st))) return s;
     ProfScope ps(PK_LHAT, st);

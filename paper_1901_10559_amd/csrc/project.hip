@@ -4,6 +4,8 @@
 // each wave a 32x32 quadrant of 2x2 16x16 MFMA blocks; K staged through LDS in
 // slices of 64 (FP32) or 32 (FP64), the next slice prefetched into registers.  The output is written column-major (column j of Y
 // contiguous), the layout the column-pivoted QR reads.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -50,10 +52,13 @@ struct Pbk {
 // BCOL: Y1 column-major (entry (k, j) at Y1[j * ld1 + k]; the staging threads
 // then walk k fastest so the loads stay coalesced), else row-major
 // (Y1[k * ld1 + j]).
+// Split K: workgroup (x, y, z) takes K range [z kchunk, min(q, (z+1) kchunk))
+// and writes its partial product to Y + z * zstride (zstride = 0, kchunk = q:
+// one pass straight into Y).
 template <typename T, bool BCOL>
 __global__ __launch_bounds__(256) void project_kernel(int64_t l, int64_t q, int64_t n, const T* __restrict__ G,
                                                       const T* __restrict__ Y1, int64_t ld1, T* __restrict__ Y,
-                                                      int64_t ldy) {
+                                                      int64_t ldy, int64_t kchunk, int64_t zstride) {
     constexpr int PBK = Pbk<T>::K;
     constexpr int NGA = PBM * PBK / 256, NBA = PBK * PBN / 256;  // staged elements per thread
     __shared__ T Gs[PBM][PBK + 1];
@@ -66,6 +71,9 @@ __global__ __launch_bounds__(256) void project_kernel(int64_t l, int64_t q, int6
     const int wm = w >> 1, wn = w & 1;
     const int64_t row0 = (int64_t)blockIdx.y * PBM;
     const int64_t col0 = (int64_t)blockIdx.x * PBN;
+    const int64_t kb = (int64_t)blockIdx.z * kchunk;
+    const int64_t ke = min(q, kb + kchunk);
+    Y += (int64_t)blockIdx.z * zstride;
     Acc acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -79,14 +87,14 @@ __global__ __launch_bounds__(256) void project_kernel(int64_t l, int64_t q, int6
             const int idx = tid + e * 256;
             const int r = idx / PBK, c = idx % PBK;
             const int64_t gr = row0 + r, gc = k0 + c;
-            gv[e] = (gr < l && gc < q) ? G[gr * q + gc] : (T)0;
+            gv[e] = (gr < l && gc < ke) ? G[gr * q + gc] : (T)0;
         }
 #pragma unroll
         for (int e = 0; e < NBA; ++e) {
             const int idx = tid + e * 256;
             const int r = BCOL ? idx % PBK : idx / PBN, c = BCOL ? idx / PBK : idx % PBN;
             const int64_t gr = k0 + r, gc = col0 + c;
-            bv[e] = (gr < q && gc < n) ? (BCOL ? Y1[gc * ld1 + gr] : Y1[gr * ld1 + gc]) : (T)0;
+            bv[e] = (gr < ke && gc < n) ? (BCOL ? Y1[gc * ld1 + gr] : Y1[gr * ld1 + gc]) : (T)0;
         }
     };
     auto store = [&]() {
@@ -104,11 +112,11 @@ __global__ __launch_bounds__(256) void project_kernel(int64_t l, int64_t q, int6
                 Bs[idx / PBN][idx % PBN] = bv[e];
         }
     };
-    load(0);
+    load(kb);
     store();
     __syncthreads();
-    for (int64_t k0 = 0; k0 < q; k0 += PBK) {
-        const bool more = k0 + PBK < q;
+    for (int64_t k0 = kb; k0 < ke; k0 += PBK) {
+        const bool more = k0 + PBK < ke;
         if (more) load(k0 + PBK);
 #pragma unroll
         for (int kk = 0; kk < PBK; kk += 4) {
@@ -140,24 +148,59 @@ __global__ __launch_bounds__(256) void project_kernel(int64_t l, int64_t q, int6
             }
 }
 
+// partials[z] (l x n, column-major, leading dimension l) summed in z order
+__global__ void project_reduce_kernel(int64_t l, int64_t n, int32_t S, const double* __restrict__ part,
+                                      double* __restrict__ Y, int64_t ldy) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= l * n) return;
+    const int64_t c = e / l, r = e - c * l;
+    double s = part[e];
+    for (int z = 1; z < S; ++z) s += part[(int64_t)z * l * n + e];
+    Y[c * ldy + r] = s;
+}
+
 ids_status project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void* G, const void* Y1, int64_t ld1,
                    void* Y, int64_t ldy, hipStream_t st, bool y1_colmajor) {
     dim3 grid((unsigned)((n + PBN - 1) / PBN), (unsigned)((l + PBM - 1) / PBM));
     if (dtype == IDS_F64) {
         if (y1_colmajor)
             hipLaunchKernelGGL((project_kernel<double, true>), grid, dim3(256), 0, st, l, q, n, (const double*)G,
-                               (const double*)Y1, ld1, (double*)Y, ldy);
+                               (const double*)Y1, ld1, (double*)Y, ldy, q, (int64_t)0);
         else
             hipLaunchKernelGGL((project_kernel<double, false>), grid, dim3(256), 0, st, l, q, n, (const double*)G,
-                               (const double*)Y1, ld1, (double*)Y, ldy);
+                               (const double*)Y1, ld1, (double*)Y, ldy, q, (int64_t)0);
     } else if (dtype == IDS_F32 && !y1_colmajor) {
         hipLaunchKernelGGL((project_kernel<float, false>), grid, dim3(256), 0, st, l, q, n, (const float*)G,
-                           (const float*)Y1, ld1, (float*)Y, ldy);
+                           (const float*)Y1, ld1, (float*)Y, ldy, q, (int64_t)0);
     } else {
         set_error("projection supports IDS_F64 and IDS_F32 (row-major sketch)");
         return IDS_EDTYPE;
     }
     return check_launch("projection");
+}
+
+int project_splits(int64_t l, int64_t q, int64_t n) {
+    const int64_t tiles = ((n + PBN - 1) / PBN) * ((l + PBM - 1) / PBM);
+    int64_t S = (512 + tiles - 1) / tiles;                         // about 512 workgroups
+    S = std::min<int64_t>(S, std::max<int64_t>(1, q / (4 * Pbk<double>::K)));  // >= 4 K slices each
+    return (int)std::max<int64_t>(1, std::min<int64_t>(S, 64));
+}
+
+ids_status project_split_f64(int64_t l, int64_t q, int64_t n, const double* G, const double* Y1, int64_t ld1,
+                             bool y1_colmajor, double* Y, int64_t ldy, int S, double* part, hipStream_t st) {
+    if (S <= 1) return project(IDS_F64, l, q, n, G, Y1, ld1, Y, ldy, st, y1_colmajor);
+    const int64_t kchunk = ((q + S - 1) / S + Pbk<double>::K - 1) / Pbk<double>::K * Pbk<double>::K;
+    const int Sz = (int)((q + kchunk - 1) / kchunk);
+    dim3 grid((unsigned)((n + PBN - 1) / PBN), (unsigned)((l + PBM - 1) / PBM), (unsigned)Sz);
+    if (y1_colmajor)
+        hipLaunchKernelGGL((project_kernel<double, true>), grid, dim3(256), 0, st, l, q, n, G, Y1, ld1, part, l,
+                           kchunk, l * n);
+    else
+        hipLaunchKernelGGL((project_kernel<double, false>), grid, dim3(256), 0, st, l, q, n, G, Y1, ld1, part, l,
+                           kchunk, l * n);
+    hipLaunchKernelGGL(project_reduce_kernel, dim3((unsigned)((l * n + 255) / 256)), dim3(256), 0, st, l, n, Sz,
+                       part, Y, ldy);
+    return check_launch("projection (split K)");
 }
 
 }  // namespace ids
