@@ -246,6 +246,48 @@ def other_workloads(ids, torch, np, steps: int = 10):
     return res
 
 
+def synth_gaussian_f32(l: int, m: int):
+    import numpy as np
+    import synth
+    return np.ascontiguousarray(synth.gaussian(l, m, seed=1).astype(np.float32))
+
+
+def gaussian_baseline(ids, torch, At, Omega, cs_ms: float, steps: int = 10):
+    """The comparison method of the paper on the same GPU and input: Gaussian
+    sketch Y = Omega A (FP32 MFMA, m split over workgroups), then the same
+    CPQR and solve."""
+    dev = At.device
+    Om = torch.from_numpy(Omega).to(dev)
+    l, m = Om.shape
+    n = At.shape[1]
+    for _ in range(2):
+        ids.gaussian_id(At, K, Om)
+    torch.cuda.synchronize()
+    ids.profile_reset()
+    ids.profile_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        ids.gaussian_id(At, K, Om)
+    e1.record()
+    torch.cuda.synchronize()
+    ids.profile_enable(False)
+    st = {}
+    for nme in ("project", "cpqr", "trsm"):
+        t, c = ids.profile_read(nme)
+        st["gaussian_sketch" if nme == "project" else nme] = t / max(c, 1)
+    ids.profile_reset()
+    ms = e0.elapsed_time(e1) / steps
+    flops = 2.0 * l * m * n
+    tf = flops / (st["gaussian_sketch"] / 1e3) / 1e12
+    return {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st,
+            "sketch_mfma": {"achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
+                            "algorithmic_flops": flops},
+            "countsketch_id_speedup": ms / cs_ms,
+            "note": f"same GPU, same CPQR and solve; FP32 Gaussian sketch Omega A with l = {l}"}
+
+
 def source_hash(path: str) -> str:
     """sha256 (16 hex digits) of the dense CountSketch kernel's source text
     (between its BEGIN / END markers), so edits elsewhere keep the counters."""
@@ -296,7 +338,8 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the residual comparison with the oracle")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched mixed-precision workload")
     ap.add_argument("--batched-steps", type=int, default=10)
-    ap.add_argument("--no-others", action="store_true", help="skip the c0 / c2 / c3 timings")
+    ap.add_argument("--no-others", action="store_true", help="skip the other workloads' timings")
+    ap.add_argument("--no-gaussian", action="store_true", help="skip the Gaussian-sketch ID baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -322,6 +365,7 @@ def main():
 
     # all inputs are generated before the GPU is touched
     A, G, l1 = workload()
+    Omega = None if args.no_gaussian else synth_gaussian_f32(K + P, A.shape[0])
     batch = None if args.no_batched else batched_workload()
 
     import torch
@@ -411,8 +455,12 @@ def main():
         res_o = oracle.residual_fro(A64, oracle_out["J"], oracle_out["P"])
         out["residual"] = {"gpu": res_g, "oracle_f64": res_o, "ratio": res_g / res_o,
                            "J_overlap": int(len(set(Jg.tolist()) & set(oracle_out["J"].tolist())))}
+    if Omega is not None:
+        print("[bench] Gaussian-sketch ID baseline on the same input", flush=True)
+        out["gaussian_baseline"] = gaussian_baseline(ids, torch, At, Omega, ms_per_step)
+        del Omega
     if not args.no_others:
-        print("[bench] other workloads (dense 2000x1000, CSR 1e6x2e4, tensor 2000^3)", flush=True)
+        print("[bench] other workloads (dense 2000x1000, CSR 1e6x2e4, tensors)", flush=True)
         out["other_workloads"] = other_workloads(ids, torch, np)
     if batch is not None:
         print("[bench] batched workload", flush=True)

@@ -116,6 +116,23 @@ ids_status id_project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void
                       const void* Y1, int64_t ld1, void* Y, int64_t ldy, void* stream);
 
 /*
+ * id_gaussian_sketch -- the Gaussian sketch Y = Omega A of a dense matrix:
+ * the sketch of the Gaussian ID the paper compares its method with (Section
+ * 1.3.1; Table 1), here as a same-GPU baseline.  Computed on the matrix cores
+ * (FP64 or FP32 MFMA) with the m dimension split over workgroups and the
+ * partial products summed in a fixed order (deterministic).
+ *   A      dense row-major m x n, IDS_F64 or IDS_F32 (A->fmt IDS_DENSE).
+ *   l      sketch rows, 1 <= l <= 4096.
+ *   Omega  l x m row-major, the dtype of A (caller-owned, e.g. N(0,1)).
+ *   Y      output, l x n column-major, leading dimension ldy >= l, the dtype
+ *          of A; feed it to id_select.
+ * Workspace: ids_gaussian_workspace_size() (may be 0).
+ */
+ids_status ids_gaussian_workspace_size(const ids_matrix* A, int64_t l, size_t* bytes);
+ids_status id_gaussian_sketch(const ids_matrix* A, int64_t l, const void* Omega, void* Y,
+                              int64_t ldy, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * id_select -- Algorithm 1 on a sketch Y (l x n): rank-k column-pivoted QR
  * (greedy largest trailing column norm, ties to the smallest column index,
  * norms recomputed in FP64 every step), J from the pivots, and

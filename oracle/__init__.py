@@ -144,6 +144,18 @@ def gemm(G, B) -> np.ndarray:
     return C
 
 
+def gaussian_id(A, k: int, Omega, blas: bool = False, trace: bool = False):
+    """The Gaussian-sketch ID the paper compares with (Section 1.3.1): Y = Omega A,
+    then Algorithm 1.  blas=True forms Y with numpy's FP64 matmul (a library
+    primitive) for inputs too large for the plain triple loop."""
+    if blas:
+        Y = np.asarray(Omega, dtype=np.float64) @ np.asarray(A, dtype=np.float64)
+    else:
+        Y = gemm(Omega, A)
+    J, P, keff, R, nu = cpqr_id(Y, k, trace=trace)
+    return dict(Y=Y, J=J, P=P, k_eff=keff, nu=nu)
+
+
 def cpqr_id(Y, k: int, trace: bool = False):
     """Algorithm 1 with column-pivoted QR.  Returns (J, P, k_eff, Rtop, nu)."""
     Y = _f64(Y)

@@ -21,7 +21,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["lib", "lib_path", "BatchedPlan", "batched_plan", "id_batched", "profile_enable", "profile_read", "profile_reset", "id_sketch", "id_project", "id_select", "matrix_id", "tensor_id",
+__all__ = ["lib", "lib_path", "BatchedPlan", "batched_plan", "id_batched", "profile_enable", "profile_read", "profile_reset", "id_sketch", "id_project", "id_select", "matrix_id", "tensor_id", "gaussian_sketch", "gaussian_id",
            "IdsError", "F64", "F32", "BF16", "HASH_FULLRANK", "EXPORTED"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,7 +31,8 @@ F64, F32, BF16 = 0, 1, 2
 DENSE, CSR = 0, 1
 HASH_FULLRANK = 1
 
-EXPORTED = ["ids_sketch_workspace_size", "id_sketch", "id_project", "ids_select_workspace_size",
+EXPORTED = ["ids_sketch_workspace_size", "id_sketch", "id_project", "ids_gaussian_workspace_size",
+            "id_gaussian_sketch", "ids_select_workspace_size",
             "id_select", "ids_tensor_workspace_size", "tensor_id", "ids_batched_plan_size", "ids_batched_plan",
             "id_batched", "ids_profile_enable", "ids_profile_read",
             "ids_profile_reset", "ids_status_string", "ids_last_error"]
@@ -72,6 +73,8 @@ def lib():
         L.ids_sketch_workspace_size.argtypes = [P(IdsMatrix), P(IdsSketchCfg), P(c_sz)]
         L.id_sketch.argtypes = [P(IdsMatrix), P(IdsSketchCfg), c_vp, c_i32, c_i64, c_vp, c_sz, c_vp]
         L.id_project.argtypes = [c_i32, c_i64, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp]
+        L.ids_gaussian_workspace_size.argtypes = [P(IdsMatrix), c_i64, P(c_sz)]
+        L.id_gaussian_sketch.argtypes = [P(IdsMatrix), c_i64, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp]
         L.ids_select_workspace_size.argtypes = [c_i64, c_i64, c_i64, P(c_sz)]
         L.id_select.argtypes = [c_vp, c_i32, c_i64, c_i64, c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]
         L.ids_tensor_workspace_size.argtypes = [c_i32, c_vp, c_i64, c_i64, c_i64, c_i64, P(c_sz)]
@@ -217,6 +220,34 @@ def id_project(G, Y1, stream=None):
     _check(lib().id_project(_dt(G), l, q, n, c_vp(G.data_ptr()), c_vp(Y1.data_ptr()), Y1.stride(0),
                             c_vp(Yb.data_ptr()), l, _stream(torch, stream)), "id_project")
     return Yb.t()
+
+
+def gaussian_sketch(A, Omega, stream=None):
+    """Y = Omega A for a dense row-major A (m x n) and Omega (l x m, row-major,
+    the dtype of A): the Gaussian sketch of the comparison method, returned as
+    an l x n view of a column-major buffer."""
+    torch = _torch()
+    desc, dev = _matrix_desc(A)
+    if isinstance(A, tuple):
+        raise IdsError("the Gaussian sketch takes a dense A")
+    l, m = Omega.shape
+    if m != desc.m or _dt(Omega) != desc.dtype or not Omega.is_contiguous():
+        raise IdsError("Omega must be a contiguous l x m tensor of the dtype of A")
+    nbytes = c_sz(0)
+    _check(lib().ids_gaussian_workspace_size(ctypes.byref(desc), l, ctypes.byref(nbytes)),
+           "ids_gaussian_workspace_size")
+    ws, wsb = _workspace(torch, nbytes.value, dev, stream)
+    Yb = torch.empty((desc.n, l), dtype=A.dtype, device=dev)
+    _check(lib().id_gaussian_sketch(ctypes.byref(desc), l, c_vp(Omega.data_ptr()), c_vp(Yb.data_ptr()), l,
+                                    c_vp(ws[1]) if ws else None, wsb, _stream(torch, stream)), "id_gaussian_sketch")
+    return Yb.t()
+
+
+def gaussian_id(A, k: int, Omega, stream=None):
+    """The Gaussian-sketch ID (comparison method): Y = Omega A, then Algorithm 1."""
+    Y = gaussian_sketch(A, Omega, stream=stream)
+    J, P, keff = id_select(Y, k, stream=stream)
+    return dict(Y=Y, J=J, P=P, k_eff=keff)
 
 
 def id_select(Y, k: int, stream=None):

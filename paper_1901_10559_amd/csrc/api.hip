@@ -270,6 +270,47 @@ ids_status id_project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void
 }
 
 // ---------------------------------------------------------------------------
+// Gaussian sketch (the comparison method)
+// ---------------------------------------------------------------------------
+static ids_status validate_gaussian(const ids_matrix* A, int64_t l) {
+    if (!A) return fail(IDS_EINVAL, "A must be non-NULL");
+    if (A->fmt != IDS_DENSE) return fail(IDS_EINVAL, "the Gaussian sketch takes a dense A");
+    if (A->m < 1 || A->n < 1) return fail(IDS_EINVAL, "matrix must be at least 1 x 1");
+    if (!A->val) return fail(IDS_EINVAL, "dense A: val is NULL");
+    if (A->ld < A->n) return fail(IDS_EINVAL, "dense A: ld < n");
+    if (A->dtype != IDS_F64 && A->dtype != IDS_F32) return fail(IDS_EDTYPE, "dtype must be IDS_F64 or IDS_F32");
+    if (l < 1 || l > 4096) return fail(IDS_EINVAL, "l must be in [1, 4096]");
+    return IDS_OK;
+}
+
+static int gaussian_splits(const ids_matrix* A, int64_t l) { return project_splits(l, A->m, A->n, 2048); }
+
+ids_status ids_gaussian_workspace_size(const ids_matrix* A, int64_t l, size_t* bytes) {
+    g_err.clear();
+    if (!bytes) return fail(IDS_EINVAL, "bytes is NULL");
+    ids_status s = validate_gaussian(A, l);
+    if (s) return s;
+    const int S = gaussian_splits(A, l);
+    *bytes = S > 1 ? align256(esize(A->dtype) * (size_t)S * l * A->n) : 0;
+    return IDS_OK;
+}
+
+ids_status id_gaussian_sketch(const ids_matrix* A, int64_t l, const void* Omega, void* Y, int64_t ldy, void* ws,
+                              size_t ws_bytes, void* stream) {
+    g_err.clear();
+    ids_status s = validate_gaussian(A, l);
+    if (s) return s;
+    if (!Omega || !Y) return fail(IDS_EINVAL, "Omega and Y must be non-NULL");
+    if (ldy < l) return fail(IDS_EINVAL, "ldy < l");
+    const int S = gaussian_splits(A, l);
+    const size_t need = S > 1 ? align256(esize(A->dtype) * (size_t)S * l * A->n) : 0;
+    if ((s = check_ws(ws, ws_bytes, need))) return s;
+    hipStream_t st = (hipStream_t)stream;
+    ProfScope ps(PK_PROJ, st);
+    return project_split(A->dtype, l, A->m, A->n, Omega, A->val, A->ld, false, Y, ldy, S, ws, st);
+}
+
+// ---------------------------------------------------------------------------
 // select
 // ---------------------------------------------------------------------------
 static ids_status validate_select(int64_t l, int64_t n, int64_t k) {
@@ -337,7 +378,7 @@ static ids_status tensor_layout(int32_t N, const int64_t* dims, int64_t R, int64
     T.tw = align256(sizeof(double2) * (size_t)Jlen);
     T.y = align256(sizeof(double) * (size_t)Jlen * R);
     T.yp = l ? align256(sizeof(double) * (size_t)l * R) : 0;
-    T.splits = l ? project_splits(l, Jlen, R) : 1;
+    T.splits = l ? project_splits(l, Jlen, R, 512) : 1;
     T.part = T.splits > 1 ? align256(sizeof(double) * (size_t)T.splits * l * R) : 0;
     ids_status s = select_plan(l ? l : Jlen, R, k, T.sp);
     if (s) return s;
@@ -404,7 +445,7 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
     if (l) {
         // Gaussian second stage: Yp (l x R, column-major) = G (l x Jlen) T M
         ProfScope ps(PK_PROJ, st);
-        if ((s = project_split_f64(l, Jlen, R, G, Yout, Jlen, true, Yp, l, T.splits, part, st))) return s;
+        if ((s = project_split(IDS_F64, l, Jlen, R, G, Yout, Jlen, true, Yp, l, T.splits, part, st))) return s;
     }
     if ((s = select_run(T.sp, l ? Yp : Yout, IDS_F64, 1, l ? l : Jlen, J, P, k_eff, sel, st))) return s;
     ProfScope ps(PK_LHAT, st);

@@ -55,11 +55,12 @@ ids_status cs_csr(const int64_t* rowptr, const int32_t* colind, const double* va
 // ---- projection GEMM (MFMA): Y(col-major, ldy) = G (l x q) * Y1 (q x n, ld1) --
 ids_status project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void* G, const void* Y1, int64_t ld1,
                    void* Y, int64_t ldy, hipStream_t st, bool y1_colmajor = false);
-// FP64 projection with K split over S chunks (S from project_splits; partial
-// products in `part`, S x l x n doubles, then summed in chunk order)
-int project_splits(int64_t l, int64_t q, int64_t n);
-ids_status project_split_f64(int64_t l, int64_t q, int64_t n, const double* G, const double* Y1, int64_t ld1,
-                             bool y1_colmajor, double* Y, int64_t ldy, int S, double* part, hipStream_t st);
+// projection with K split over S chunks (S from project_splits for about
+// target_wgs workgroups; partial products in `part`, S x l x n elements of the
+// dtype, then summed in chunk order)
+int project_splits(int64_t l, int64_t q, int64_t n, int64_t target_wgs);
+ids_status project_split(int32_t dtype, int64_t l, int64_t q, int64_t n, const void* G, const void* Y1, int64_t ld1,
+                         bool y1_colmajor, void* Y, int64_t ldy, int S, void* part, hipStream_t st);
 
 // ---- CPQR + interpolation matrix --------------------------------------------
 struct SelectPlan {

@@ -149,12 +149,13 @@ __global__ __launch_bounds__(256) void project_kernel(int64_t l, int64_t q, int6
 }
 
 // partials[z] (l x n, column-major, leading dimension l) summed in z order
-__global__ void project_reduce_kernel(int64_t l, int64_t n, int32_t S, const double* __restrict__ part,
-                                      double* __restrict__ Y, int64_t ldy) {
+template <typename T>
+__global__ void project_reduce_kernel(int64_t l, int64_t n, int32_t S, const T* __restrict__ part,
+                                      T* __restrict__ Y, int64_t ldy) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= l * n) return;
     const int64_t c = e / l, r = e - c * l;
-    double s = part[e];
+    T s = part[e];
     for (int z = 1; z < S; ++z) s += part[(int64_t)z * l * n + e];
     Y[c * ldy + r] = s;
 }
@@ -179,28 +180,42 @@ ids_status project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void* G
     return check_launch("projection");
 }
 
-int project_splits(int64_t l, int64_t q, int64_t n) {
+int project_splits(int64_t l, int64_t q, int64_t n, int64_t target_wgs) {
     const int64_t tiles = ((n + PBN - 1) / PBN) * ((l + PBM - 1) / PBM);
-    int64_t S = (512 + tiles - 1) / tiles;                         // about 512 workgroups
+    int64_t S = (target_wgs + tiles - 1) / tiles;
     S = std::min<int64_t>(S, std::max<int64_t>(1, q / (4 * Pbk<double>::K)));  // >= 4 K slices each
-    return (int)std::max<int64_t>(1, std::min<int64_t>(S, 64));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(S, 256));
 }
 
-ids_status project_split_f64(int64_t l, int64_t q, int64_t n, const double* G, const double* Y1, int64_t ld1,
-                             bool y1_colmajor, double* Y, int64_t ldy, int S, double* part, hipStream_t st) {
-    if (S <= 1) return project(IDS_F64, l, q, n, G, Y1, ld1, Y, ldy, st, y1_colmajor);
-    const int64_t kchunk = ((q + S - 1) / S + Pbk<double>::K - 1) / Pbk<double>::K * Pbk<double>::K;
+template <typename T>
+static ids_status split_run(int64_t l, int64_t q, int64_t n, const T* G, const T* Y1, int64_t ld1, bool y1_colmajor,
+                            T* Y, int64_t ldy, int S, T* part, hipStream_t st) {
+    constexpr int K = Pbk<T>::K;
+    const int64_t kchunk = ((q + S - 1) / S + K - 1) / K * K;
     const int Sz = (int)((q + kchunk - 1) / kchunk);
     dim3 grid((unsigned)((n + PBN - 1) / PBN), (unsigned)((l + PBM - 1) / PBM), (unsigned)Sz);
     if (y1_colmajor)
-        hipLaunchKernelGGL((project_kernel<double, true>), grid, dim3(256), 0, st, l, q, n, G, Y1, ld1, part, l,
-                           kchunk, l * n);
+        hipLaunchKernelGGL((project_kernel<T, true>), grid, dim3(256), 0, st, l, q, n, G, Y1, ld1, part, l, kchunk,
+                           l * n);
     else
-        hipLaunchKernelGGL((project_kernel<double, false>), grid, dim3(256), 0, st, l, q, n, G, Y1, ld1, part, l,
-                           kchunk, l * n);
-    hipLaunchKernelGGL(project_reduce_kernel, dim3((unsigned)((l * n + 255) / 256)), dim3(256), 0, st, l, n, Sz,
+        hipLaunchKernelGGL((project_kernel<T, false>), grid, dim3(256), 0, st, l, q, n, G, Y1, ld1, part, l, kchunk,
+                           l * n);
+    hipLaunchKernelGGL(project_reduce_kernel<T>, dim3((unsigned)((l * n + 255) / 256)), dim3(256), 0, st, l, n, Sz,
                        part, Y, ldy);
     return check_launch("projection (split K)");
+}
+
+ids_status project_split(int32_t dtype, int64_t l, int64_t q, int64_t n, const void* G, const void* Y1, int64_t ld1,
+                         bool y1_colmajor, void* Y, int64_t ldy, int S, void* part, hipStream_t st) {
+    if (S <= 1) return project(dtype, l, q, n, G, Y1, ld1, Y, ldy, st, y1_colmajor);
+    if (dtype == IDS_F64)
+        return split_run<double>(l, q, n, (const double*)G, (const double*)Y1, ld1, y1_colmajor, (double*)Y, ldy, S,
+                                 (double*)part, st);
+    if (dtype == IDS_F32 && !y1_colmajor)
+        return split_run<float>(l, q, n, (const float*)G, (const float*)Y1, ld1, false, (float*)Y, ldy, S,
+                                (float*)part, st);
+    set_error("projection supports IDS_F64 and IDS_F32 (row-major sketch)");
+    return IDS_EDTYPE;
 }
 
 }  // namespace ids
