@@ -118,6 +118,21 @@ def run_batched(ids, torch, np, m, n, Abits, Gb, steps: int, check: bool):
                                "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                                "frac": sk_bytes / (st["sketch_project"] / 1e3) / 1e9 / HBM_PEAK_GBPS,
                                "algorithmic_bytes": sk_bytes}}
+    # fixed-accuracy variant (same inputs): every problem stops at |r_tt| <= 1e-2 |r_11|
+    tol = 1e-2
+    for _ in range(2):
+        outa = ids.id_batched(plan, At, Gt, seed=0, tol=tol)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        outa = ids.id_batched(plan, At, Gt, seed=0, tol=tol)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_a = e0.elapsed_time(e1) / steps
+    ka = outa["k_eff"].cpu().numpy()
+    res["fixed_accuracy"] = {"tol": tol, "value": NB / (ms_a / 1e3), "unit": "IDs/s", "ms_per_batch": ms_a,
+                             "rank_mean": float(ka.mean()), "rank_min": int(ka.min()), "rank_max": int(ka.max()),
+                             "note": "problem p stops at the first step with |r_tt| <= tol |r_11| (k_eff_p = its rank)"}
     # plain per-problem FP64 on the same GPU: the single-problem FP64 path, one
     # problem after another, on the first 128 problems (inputs resident)
     nfp = 128

@@ -197,7 +197,11 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
  *                     ids_batched_plan_size() bytes; synchronises `stream`
  *                     once; returns the workspace size id_batched needs.
  *                     m, n are HOST arrays.
- *   id_batched        asynchronous; J int64[nprob*k] (J_p at p*k, -1 past
+ *   id_batched        asynchronous; tol = 0: rank k for every problem; 0 < tol
+ *                     < 1: fixed accuracy (the natural rank-revealing stop of
+ *                     Algorithm 1's pivoted QR): problem p stops at the first
+ *                     step t with |r_tt| <= tol |r_11| and k_eff_p = t <= k.
+ *                     J int64[nprob*k] (J_p at p*k, -1 past
  *                     k_eff_p), P double[k * sum n_p] (P_p, k x n_p row-major,
  *                     at k * sum_{q<p} n_q), k_eff int64[nprob].  The plan, m
  *                     and n must be the ones the plan was built from.
@@ -207,7 +211,7 @@ ids_status ids_batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, i
                             int64_t l1max, void* plan, size_t plan_bytes, size_t* ws_bytes,
                             void* stream);
 ids_status id_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* plan, int64_t k,
-                      int64_t l, int64_t l1max, uint64_t seed, const void* A, const void* G,
+                      int64_t l, int64_t l1max, uint64_t seed, double tol, const void* A, const void* G,
                       int64_t* J, double* P, int64_t* k_eff, void* ws, size_t ws_bytes, void* stream);
 
 /*

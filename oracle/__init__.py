@@ -238,6 +238,26 @@ def matrix_id(A=None, *, csr=None, n=None, k: int, l1: int, seed: int, tag: int 
     return dict(Y1=Y1, Y=Y, J=J, P=P, k_eff=keff, R=R, nu=nu)
 
 
+def adaptive_rank(R, J, keff: int, tol: float) -> int:
+    """Fixed-accuracy stop of Algorithm 1's pivoted QR: the first step t >= 1
+    with |r_tt| <= tol |r_11| (r_tt = R[t, J[t]]); keff when no step meets it."""
+    d = np.abs(R[np.arange(keff), np.asarray(J[:keff])])
+    for t in range(1, keff):
+        if d[t] <= tol * d[0]:
+            return t
+    return keff
+
+
+def matrix_id_adaptive(A, *, kmax: int, tol: float, l1: int, seed: int, tag: int = 0, G=None):
+    """Fixed-accuracy ID: the rank-kmax factorisation decides the rank t by
+    adaptive_rank, then the ID of rank t (the first t pivots are the same)."""
+    Y1, Y = matrix_sketch(A, l1=l1, seed=seed, tag=tag, G=G)
+    J, P, keff, R, nu = cpqr_id(Y, kmax)
+    t = adaptive_rank(R, J, keff, tol)
+    J2, P2, keff2, R2, _ = cpqr_id(Y, t)
+    return dict(Y=Y, J=J2, P=P2, k_eff=keff2, rank=t, J_kmax=J, R_kmax=R)
+
+
 def tensor_maps(seed: int, dims, Jlen: int):
     """Independent per-mode maps h_n, s_n: stream tag n+1 for mode n."""
     return [hash_maps(seed, n + 1, int(d), Jlen) for n, d in enumerate(dims)]

@@ -82,7 +82,7 @@ def lib():
                                 c_vp, c_vp, c_vp, c_sz, c_vp]
         L.ids_batched_plan_size.argtypes = [c_i64, P(c_sz)]
         L.ids_batched_plan.argtypes = [c_i64, c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_sz, P(c_sz), c_vp]
-        L.id_batched.argtypes = [c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_u64, c_vp, c_vp, c_vp, c_vp, c_vp,
+        L.id_batched.argtypes = [c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_u64, ctypes.c_double, c_vp, c_vp, c_vp, c_vp, c_vp,
                                  c_vp, c_sz, c_vp]
         for fn in ("ids_batched_plan_size", "ids_batched_plan", "id_batched"):
             getattr(L, fn).restype = c_i32
@@ -345,11 +345,12 @@ def batched_plan(m, n, k: int, l: int, l1max: int, device="cuda:0", stream=None)
     return BatchedPlan(m, n, k, l, l1max, buf, wsb.value)
 
 
-def id_batched(plan: BatchedPlan, A, G, seed: int = 0, stream=None, return_Y: bool = False):
+def id_batched(plan: BatchedPlan, A, G, seed: int = 0, tol: float = 0.0, stream=None, return_Y: bool = False):
     """Batched mixed-precision ID.  A: flat bfloat16 device tensor of all A_p
     (row-major, back to back); G: l x l1max bfloat16.  Returns dict with J
     (nprob x k), P (flat float64, P_p = P[p_off[p]:p_off[p+1]].view(k, n_p)),
-    k_eff (nprob) and, if asked, Y (flat float32, Y_p column-major l x n_p)."""
+    k_eff (nprob) and, if asked, Y (flat float32, Y_p column-major l x n_p).
+    tol > 0: fixed accuracy, problem p stops once |r_tt| <= tol |r_11|."""
     torch = _torch()
     if A.dtype != torch.bfloat16 or G.dtype != torch.bfloat16:
         raise IdsError("A and G must be bfloat16")
@@ -363,7 +364,8 @@ def id_batched(plan: BatchedPlan, A, G, seed: int = 0, stream=None, return_Y: bo
     P = torch.empty(int(plan.p_off[-1]), dtype=torch.float64, device=dev)
     keff = torch.empty(plan.nprob, dtype=torch.int64, device=dev)
     _check(lib().id_batched(plan.nprob, c_vp(plan.m.ctypes.data), c_vp(plan.n.ctypes.data),
-                            c_vp(plan.buf.data_ptr()), plan.k, plan.l, plan.l1max, seed, c_vp(A.data_ptr()),
+                            c_vp(plan.buf.data_ptr()), plan.k, plan.l, plan.l1max, seed, float(tol),
+                            c_vp(A.data_ptr()),
                             c_vp(G.data_ptr()), c_vp(J.data_ptr()), c_vp(P.data_ptr()), c_vp(keff.data_ptr()),
                             c_vp(ws[1]), wsb, _stream(torch, stream)), "id_batched")
     out = dict(J=J, P=P, k_eff=keff)

@@ -488,11 +488,12 @@ ids_status ids_batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, i
 }
 
 ids_status id_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* plan, int64_t k, int64_t l,
-                      int64_t l1max, uint64_t seed, const void* A, const void* G, int64_t* J, double* P,
+                      int64_t l1max, uint64_t seed, double tol, const void* A, const void* G, int64_t* J, double* P,
                       int64_t* k_eff, void* ws, size_t ws_bytes, void* stream) {
     g_err.clear();
     ids_status s = validate_batched(nprob, m, n, k, l, l1max);
     if (s) return s;
+    if (!(tol >= 0.0 && tol < 1.0)) return fail(IDS_EINVAL, "tol must be in [0, 1)");
     if (!plan || !A || !G || !J || !P || !k_eff) return fail(IDS_EINVAL, "plan, A, G, J, P and k_eff required");
     int64_t y_elems = 0, r_elems = 0;
     for (int64_t q = 0; q < nprob; ++q) {
@@ -502,7 +503,7 @@ ids_status id_batched(int64_t nprob, const int64_t* m, const int64_t* n, const v
     const size_t need = align256(sizeof(float) * (size_t)y_elems) + align256(sizeof(double) * (size_t)r_elems * k) +
                         align256(sizeof(int32_t) * (size_t)r_elems) + align256(sizeof(double) * (size_t)nprob * k);
     if ((s = check_ws(ws, ws_bytes, need))) return s;
-    return batched_run(nprob, plan, k, l, l1max, seed, A, G, J, P, k_eff, ws, ws_bytes, y_elems, r_elems,
+    return batched_run(nprob, plan, k, l, l1max, seed, tol, A, G, J, P, k_eff, ws, ws_bytes, y_elems, r_elems,
                        (hipStream_t)stream);
 }
 

@@ -11,6 +11,8 @@
 //       threads by n_p): column j of Y_p in lane j (rows 0..RL-1 in LDS, rows
 //       RL.. in registers), FP32 data and Householder updates, trailing norms
 //       recomputed in FP64 each step.
+//   With tol > 0 (fixed-accuracy ID) problem p stops at the first step t with
+//   |r_tt| <= tol |r_11| and returns k_eff_p = t (its adaptive rank).
 //   batched_trsm_kernel    one workgroup per problem: R11 in LDS, FP64
 //       axpy back-substitution, up to 4 lanes per column; writes P_p.
 // Problem p draws its CountSketch from the stream (seed, tag = p) and uses
@@ -65,6 +67,7 @@ struct BatchArgs {
     const int32_t* order;
     int64_t nprob, k, l, l1max;
     uint64_t seed;
+    double tol2;        // fixed-accuracy stop: |r_tt|^2 <= tol2 |r_11|^2 (0: fixed rank k)
     const uint16_t* A;
     const uint16_t* G;  // l x l1max BF16
     int32_t g_vec;      // G rows 16-byte aligned (l1max % 8 == 0, G aligned)
@@ -426,6 +429,7 @@ __global__ __launch_bounds__(NT) void batched_cpqr_kernel(BatchArgs a, int nt_mi
     };
     double nu = wave_live ? norm_from(0) : 0.0;
     int keff = k;
+    double nu0 = 0.0;  // |r_11|^2
     const int64_t roff = pr.r_off;
     if (alive) a.pos[roff + j] = -1;
 
@@ -450,7 +454,10 @@ __global__ __launch_bounds__(NT) void batched_cpqr_kernel(BatchArgs a, int nt_mi
             wnu = m2;
             wj = q2;
         }
-        if (wj == INT32_MAX || !(wnu > 0.0)) {
+        if (t == 0) nu0 = wnu;
+        // stop at rank deficiency, or (fixed accuracy) once the pivot's trailing
+        // norm |r_tt| = sqrt(wnu) is at most tol |r_11|
+        if (wj == INT32_MAX || !(wnu > 0.0) || (t > 0 && wnu <= a.tol2 * nu0)) {
             keff = t;
             break;
         }
@@ -661,7 +668,7 @@ ids_status batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, int64
 }
 
 ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, int64_t l1max, uint64_t seed,
-                       const void* A, const void* G, int64_t* J, double* P, int64_t* keff, void* ws,
+                       double tol, const void* A, const void* G, int64_t* J, double* P, int64_t* keff, void* ws,
                        size_t ws_bytes, int64_t y_elems, int64_t r_elems, hipStream_t st) {
     size_t op, o1, o2;
     plan_layout(nprob, &op, &o1, &o2);
@@ -672,6 +679,7 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
     a.l = l;
     a.l1max = l1max;
     a.seed = seed;
+    a.tol2 = tol * tol;
     a.A = (const uint16_t*)A;
     a.G = (const uint16_t*)G;
     a.g_vec = (l1max % 8 == 0) && (((uintptr_t)G & 15) == 0);

@@ -82,3 +82,33 @@ def test_batched_rejects_out_of_range():
         ids.batched_plan([500], [2000], 111, 121, 496)        # n > 1024
     with pytest.raises(ids.IdsError):
         ids.batched_plan([500], [300], 111, 121, 600)         # l1max > 512
+
+
+def test_batched_fixed_accuracy_rank_and_residual():
+    # fixed-accuracy batched ID: problem p stops at |r_tt| <= tol |r_11|; the
+    # rank matches the oracle's fixed-accuracy stop on the same BF16 input up
+    # to one step (the two sides' norms differ at rounding level near the
+    # threshold), and the ID of that rank is as accurate as the oracle's
+    nprob, k, l, l1max, tol = 48, 111, 121, 496, 1e-2
+    m, n, flat = synth.batched_inputs(nprob, seed=7)
+    Gb = synth.bf16_bits(synth.gaussian(l, l1max, seed=7))
+    plan = ids.batched_plan(m, n, k, l, l1max)
+    At = torch.from_numpy(flat.view(np.int16)).to(DEV).view(torch.bfloat16)
+    Gt = torch.from_numpy(Gb.view(np.int16)).to(DEV).view(torch.bfloat16)
+    out = ids.id_batched(plan, At, Gt, seed=7, tol=tol)
+    keff = out["k_eff"].cpu().numpy()
+    J = out["J"].cpu().numpy()
+    P = out["P"].cpu().numpy()
+    assert np.all((keff >= 1) & (keff < k))
+    G64 = synth.bf16_to_f64(Gb)
+    for p in range(0, nprob, 6):
+        A64 = synth.bf16_to_f64(flat[plan.a_off[p]:plan.a_off[p + 1]]).reshape(m[p], n[p])
+        l1 = min(int(m[p]), l1max)
+        o = oracle.matrix_id_adaptive(A64, kmax=k, tol=tol, l1=l1, seed=7, tag=p, G=G64[:, :l1])
+        r = int(keff[p])
+        assert abs(r - o["rank"]) <= 1, (p, r, o["rank"])
+        Pp = P[plan.p_off[p]:plan.p_off[p + 1]].reshape(k, n[p])
+        assert np.all(J[p, r:] == -1) and np.all(Pp[r:] == 0.0)
+        assert np.array_equal(Pp[:r][:, J[p, :r]], np.eye(r))
+        of = oracle.matrix_id(A64, k=r, l1=l1, seed=7, tag=p, G=G64[:, :l1])
+        assert oracle.residual_fro(A64, J[p, :r], Pp[:r]) <= 2.0 * oracle.residual_fro(A64, of["J"], of["P"])

@@ -168,3 +168,32 @@ def test_fact1_residual_bound_holds_for_sketched_id():
     r = oracle.matrix_id(A, k=k, l1=64, seed=2, G=G)
     err = np.linalg.norm(A - A[:, r["J"]] @ r["P"], 2)
     assert err <= 1e-6 * np.sqrt(4 * k * (n - k) + 1)
+
+
+def test_adaptive_rank_clear_gap_and_consistency():
+    # sigma = 1 for i <= 10, 1e-6 after: at tol = 1e-3 the fixed-accuracy stop
+    # is rank 10; the adaptive ID is the fixed-rank ID of that rank
+    g = np.random.default_rng(31)
+    m, n = 300, 120
+    U, _ = np.linalg.qr(g.standard_normal((m, n)))
+    V, _ = np.linalg.qr(g.standard_normal((n, n)))
+    s = np.where(np.arange(n) < 10, 1.0, 1e-6)
+    A = (U * s) @ V.T
+    G = g.standard_normal((40, 128))
+    o = oracle.matrix_id_adaptive(A, kmax=30, tol=1e-3, l1=128, seed=1, G=G)
+    assert o["rank"] == 10 and o["k_eff"] == 10
+    f = oracle.matrix_id(A, k=10, l1=128, seed=1, G=G)
+    assert np.array_equal(o["J"], f["J"]) and np.array_equal(o["P"], f["P"])
+    assert np.array_equal(o["J"], o["J_kmax"][:10])
+    # |r_tt| of column-pivoted QR never increases, so the first step below the
+    # threshold is also the count of diagonal entries above it
+    d = np.abs(o["R_kmax"][np.arange(30), o["J_kmax"]])
+    assert np.all(d[1:] <= d[:-1] * (1 + 1e-12))
+    assert int(np.sum(d > 1e-3 * d[0])) == 10
+
+
+def test_adaptive_rank_tol_zero_is_fixed_rank():
+    g = np.random.default_rng(32)
+    A = g.standard_normal((200, 80))
+    o = oracle.matrix_id_adaptive(A, kmax=25, tol=0.0, l1=64, seed=2, G=g.standard_normal((30, 64)))
+    assert o["rank"] == 25
