@@ -189,6 +189,67 @@ __device__ __forceinline__ void vote_hdr(const SelArgs& a, const double* reg, in
     wave_argmax(wnu, wj);
 }
 
+// Vote and winner column in one wave (speculative slots, nh <= 64 headers):
+// lane q polls header q; every poll round also (re)loads the rows of the
+// column of the best candidate seen so far, so when the last header arrives
+// the winner's column is usually complete already (one round trip instead of
+// two after the last publication).  Lane holds rows lane + 64 u, u < U.
+// Returns with the winner in (wnu, wj) and its rows in xv (0 past l), all
+// lanes agreeing; on timeout the flag is raised and the values may be NaN.
+template <int U>
+__device__ __forceinline__ void vote_prefetch(const SelArgs& a, const double* reg, int cols_per_blk, int l,
+                                              double& wnu, int& wj, uint64_t (&xv)[U]) {
+    const int lane = threadIdx.x & 63;
+    const bool mine = lane < a.nh;
+    const double* hd = reg + (size_t)(mine ? lane : 0) * a.S;
+    uint64_t hn = 0, hj = 0;
+    bool have = !mine;
+    int cand = -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = MB_SENT;
+    for (uint32_t spin = 0;; ++spin) {
+        if (!have) {
+            hn = mb_load(hd);
+            hj = mb_load(hd + 1);
+        }
+        if (cand >= 0) {
+            const double* col = reg + (size_t)(cand / cols_per_blk) * a.S + 2;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = lane + 64 * u;
+                if (xv[u] == MB_SENT) xv[u] = (i < l) ? mb_load(col + i) : 0ull;
+            }
+        }
+        if (!have) have = (hn != MB_SENT) && (hj != MB_SENT);
+        bool col_pend = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) col_pend = col_pend || (xv[u] == MB_SENT);
+        const bool col_ok = cand >= 0 && !__any(col_pend);
+        double bn = -1.0;
+        int bj = INT32_MAX;
+        if (mine && have) take(hn, hj, bn, bj);
+        wave_argmax(bn, bj);
+        const bool all = !__any(!have);
+        if (all && (bj == INT32_MAX || (bj == cand && col_ok))) {
+            wnu = bn;
+            wj = bj;
+            return;
+        }
+        if (bj != INT32_MAX && bj != cand) {
+            cand = bj;
+#pragma unroll
+            for (int u = 0; u < U; ++u) xv[u] = MB_SENT;
+        }
+        if (spin >= SPIN_LIMIT ||
+            ((spin & 63) == 63 && __hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+            if (lane == 0) __hip_atomic_store(a.flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            wnu = bn;
+            wj = bj;
+            return;
+        }
+    }
+}
+
 // l published values at src -> LDS dst, zeros up to lpad (all threads), then a
 // workgroup barrier.  Row i is stored at i + (i >> PSH): one pad slot per
 // 2^PSH rows, so lane parts that read rows 2^PSH apart hit different banks.
@@ -340,13 +401,38 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
         // ---- vote, winner column -> LDS
         double wnu;
         int wj;
-        vote_hdr<NW>(a, reg, MODE == MB_OWNER ? 2 : S, s_vn[par], s_vj[par], wnu, wj);
+        double* xb = sm + par * LB;
+        const bool one_wave_vote = MODE == MB_SPEC && a.nh <= 64;  // uniform
+        if (one_wave_vote) {
+            constexpr int UP = (LP + 63) / 64;
+            if (w == 0) {
+                uint64_t xv[UP];
+                double vn;
+                int vj;
+                vote_prefetch<UP>(a, reg, NW * CPWV, l, vn, vj, xv);
+#pragma unroll
+                for (int u = 0; u < UP; ++u) {
+                    const int i = lane + 64 * u;
+                    if (i < LP) xb[i + (i >> PSH)] = mb_val(xv[u]);
+                }
+                if (lane == 0) {
+                    s_vn[par][0] = vn;
+                    s_vj[par][0] = vj;
+                }
+            }
+            __syncthreads();
+            wnu = s_vn[par][0];
+            wj = s_vj[par][0];
+        } else {
+            vote_hdr<NW>(a, reg, MODE == MB_OWNER ? 2 : S, s_vn[par], s_vj[par], wnu, wj);
+        }
         if (wj == INT32_MAX || !(wnu > 0.0)) {
             keff = t;
             break;
         }
-        double* xb = sm + par * LB;
-        if (MODE == MB_SPEC) {
+        if (one_wave_vote) {
+            // the winner's rows are in LDS already
+        } else if (MODE == MB_SPEC) {
             fetch_col_lds<NT, PSH>(a, reg + (size_t)(wj / (NW * CPWV)) * S + 2, l, LP, xb);
         } else {
             double* cb = reg + a.H0;
