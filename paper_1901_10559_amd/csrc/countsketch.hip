@@ -507,10 +507,29 @@ ids_status cs_dense(int32_t dtype, int32_t acc, const void* A, int64_t lda, int6
 // CSR scatter (FP64)
 // ---------------------------------------------------------------------------
 constexpr int CSR_THREADS = 1024;
-constexpr int CSR_GROUP = 8;  // lanes per row
+constexpr int CSR_GROUP = 8;  // lanes per row (global-atomic variant)
+constexpr int CSR_U = 8;      // 64-entry chunks in flight per wave
+
+// inclusive prefix sum over the 64 lanes of a wave
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int64_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
 
 // LDS-privatised variant: the whole bucket row of Y1 (n <= CSR_LDS_MAX) lives in
-// LDS; a workgroup handles rows [p0, p1) of the bucket's list.
+// LDS; a workgroup handles positions [p0, p1) of the bucket's row list.
+// Entry-parallel: a wave takes a batch of 64 consecutive rows of the list
+// (batches are handed out through an LDS counter), scans their lengths, and
+// then walks the batch's entries 64 at a time, lane q taking the q-th entry of
+// the chunk, so the loads of val / colind are coalesced whatever the row
+// lengths are.  The row of an entry is the last row whose start is <= it,
+// found by a binary search over the batch's starts held one per lane.  CSR_U
+// chunks are loaded before their LDS adds, so that many loads are in flight.
 __global__ __launch_bounds__(CSR_THREADS) void cs_csr_lds_kernel(const int64_t* __restrict__ rowptr,
                                                                   const int32_t* __restrict__ colind,
                                                                   const double* __restrict__ val, int64_t n,
@@ -519,46 +538,95 @@ __global__ __launch_bounds__(CSR_THREADS) void cs_csr_lds_kernel(const int64_t* 
                                                                   double* __restrict__ Y, int64_t rs, int64_t cs,
                                                                   int use_atomic) {
     extern __shared__ double ybuf[];
+    __shared__ int s_next;
     const int b = blockIdx.x / nchunk;
     const int ch = blockIdx.x % nchunk;
     for (int64_t j = threadIdx.x; j < n; j += CSR_THREADS) ybuf[j] = 0.0;
+    if (threadIdx.x == 0) s_next = 0;
     __syncthreads();
     const int beg = off[b], end = off[b + 1];
     const int64_t cnt = end - beg;
     const int p0 = beg + (int)(cnt * ch / nchunk);
     const int p1 = beg + (int)(cnt * (ch + 1) / nchunk);
-    // Each group of CSR_GROUP lanes takes CSR_GROUP consecutive rows of the
-    // list at a time: lane q fetches row q's code and extent (independent loads
-    // in flight), then the group walks the rows' entries together.
-    const int g = threadIdx.x / CSR_GROUP;
-    const int gl = threadIdx.x % CSR_GROUP;
-    constexpr int NG = CSR_THREADS / CSR_GROUP;
-    for (int pb = p0 + g * CSR_GROUP; pb < p1; pb += NG * CSR_GROUP) {
-        const int pq = pb + gl;
-        int32_t code = 0;
-        int64_t e0 = 0, e1 = 0;
-        if (pq < p1) {
-            code = rows[pq];
+    const int nbat = (p1 - p0 + 63) / 64;
+    const int lane = threadIdx.x & 63;
+
+    auto grab = [&]() -> int {
+        int bi = 0;
+        if (lane == 0) bi = atomicAdd(&s_next, 1);
+        return __shfl(bi, 0, 64);
+    };
+    int bi = grab();
+    int32_t code = 0;
+    bool have = false;
+    if (bi < nbat) {
+        const int p = p0 + bi * 64 + lane;
+        have = p < p1;
+        code = have ? rows[p] : 0;
+    }
+    while (bi < nbat) {
+        // this batch: one row per lane
+        int64_t e0 = 0, len = 0;
+        if (have) {
             const int64_t i = code >= 0 ? code : -(int64_t)code - 1;
             e0 = rowptr[i];
-            e1 = rowptr[i + 1];
+            len = rowptr[i + 1] - e0;
         }
+        const bool neg = code < 0;
+        // next batch's row codes load while this one is summed
+        const int bn = grab();
+        bool have_n = false;
+        int32_t code_n = 0;
+        if (bn < nbat) {
+            const int p = p0 + bn * 64 + lane;
+            have_n = p < p1;
+            code_n = have_n ? rows[p] : 0;
+        }
+        const int64_t inc = wave_incl_scan(len);
+        const int64_t T = __shfl(inc, 63, 64);
+        const int64_t pre = inc - len;  // start of this lane's row in the batch's entry sequence
+        // entry q of the batch is element (e0 - pre) + q of val / colind; the
+        // row's sign rides in the low bit
+        const int64_t base2 = 2 * (e0 - pre) + (neg ? 1 : 0);
+        // an entry every lane may load: the first entry of the batch
+        const uint64_t nz = __ballot(len > 0);
+        const int64_t e_any = nz ? __shfl(e0, __ffsll((unsigned long long)nz) - 1, 64) : 0;
+        for (int64_t B = 0; B < T; B += 64 * CSR_U) {
+            // (1) entry index of every chunk (branch-free, so the searches of
+            //     the chunks interleave); lanes past the end load e_any
+            int64_t e[CSR_U];
+            bool ok[CSR_U], sg[CSR_U];
 #pragma unroll
-        for (int q = 0; q < CSR_GROUP; ++q) {
-            const int64_t b0 = __shfl(e0, q, CSR_GROUP), b1 = __shfl(e1, q, CSR_GROUP);
-            const bool neg = __shfl(code, q, CSR_GROUP) < 0;
-            int64_t e = b0 + gl;
-            for (; e + CSR_GROUP < b1; e += 2 * CSR_GROUP) {  // two entries per lane in flight
-                const double v0 = val[e], v1 = val[e + CSR_GROUP];
-                const int c0 = colind[e], c1 = colind[e + CSR_GROUP];
-                atomicAdd(&ybuf[c0], neg ? -v0 : v0);
-                atomicAdd(&ybuf[c1], neg ? -v1 : v1);
+            for (int u = 0; u < CSR_U; ++u) {
+                const int64_t Bu = B + 64 * u;
+                // batch-relative start of this lane's row, clamped to [-1, 64]
+                const int rel = (int)max((int64_t)-1, min(pre - Bu, (int64_t)64));
+                int r = 0;
+#pragma unroll
+                for (int st = 32; st >= 1; st >>= 1)
+                    if (__shfl(rel, r + st, 64) <= lane) r += st;
+                const int64_t bb = __shfl(base2, r, 64);
+                const int64_t q = Bu + lane;
+                ok[u] = q < T;
+                sg[u] = bb & 1;
+                e[u] = ok[u] ? (bb >> 1) + q : e_any;
             }
-            if (e < b1) {
-                const double v = val[e];
-                atomicAdd(&ybuf[colind[e]], neg ? -v : v);
+            // (2) all loads in flight
+            double v[CSR_U];
+            int32_t c[CSR_U];
+#pragma unroll
+            for (int u = 0; u < CSR_U; ++u) {
+                v[u] = val[e[u]];
+                c[u] = colind[e[u]];
             }
+            // (3) signed adds into the LDS row
+#pragma unroll
+            for (int u = 0; u < CSR_U; ++u)
+                if (ok[u]) atomicAdd(&ybuf[c[u]], sg[u] ? -v[u] : v[u]);
         }
+        bi = bn;
+        code = code_n;
+        have = have_n;
     }
     __syncthreads();
     for (int64_t j = threadIdx.x; j < n; j += CSR_THREADS) {
@@ -607,9 +675,10 @@ ids_status cs_csr(const int64_t* rowptr, const int32_t* colind, const double* va
                   const PlanBufs& pb, int64_t L, double* Y, int64_t rs, int64_t cs, int32_t* scratch_bop,
                   hipStream_t st) {
     const size_t lds = sizeof(double) * (size_t)n;
-    if (lds <= CSR_LDS_MAX_BYTES) {
-        // enough workgroups to cover the chip twice, at most one per 256 rows
-        int nchunk = (int)((2 * 256 + L - 1) / L);
+    if (lds + 256 <= CSR_LDS_MAX_BYTES) {  // + the static batch counter
+        // about one workgroup per compute unit (one fits, the LDS row is large);
+        // several per bucket only when there are fewer buckets than units
+        int nchunk = (int)(256 / L);
         int64_t rows_per_bucket = (m + L - 1) / L;
         int64_t maxch = rows_per_bucket / 256;
         if (nchunk > maxch) nchunk = (int)(maxch > 1 ? maxch : 1);

@@ -111,6 +111,28 @@ def test_countsketch_csr(m, n, L):
     assert np.all(np.abs(Y - Yo) <= 64 * 2.0 ** -52 * absum + 1e-300)
 
 
+def test_countsketch_csr_empty_and_long_rows():
+    # empty rows, one full row, a band of long rows and single entries: the
+    # entry-parallel walk must map every entry to its own row
+    import scipy.sparse as sp
+    m, n, L = 5000, 3000, 37
+    g = np.random.default_rng(11)
+    cnt = np.where(g.random(m) < 0.3, 0, g.integers(1, 4, m))
+    cnt[17] = n
+    cnt[100:140] = 700
+    cnt[4999] = 1
+    rows = np.repeat(np.arange(m), cnt)
+    cols = np.concatenate([g.choice(n, c, replace=False) for c in cnt])
+    A = sp.csr_matrix((g.standard_normal(rows.size), (rows, cols)), shape=(m, n))
+    A.sort_indices()
+    rp, ci, v = A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data.astype(np.float64)
+    Y = ids.id_sketch((dev(rp), dev(ci), dev(v), n), L, seed=9).cpu().numpy()
+    b, s = oracle.hash_maps(9, 0, m, L)
+    Yo = oracle.countsketch_csr(rp, ci, v, n, b, s, L)
+    absum = oracle.countsketch_csr(rp, ci, np.abs(v), n, b, np.ones_like(s), L)
+    assert np.all(np.abs(Y - Yo) <= 64 * 2.0 ** -52 * absum + 1e-300)
+
+
 # ---------------------------------------------------------------------------
 # projection
 # ---------------------------------------------------------------------------
