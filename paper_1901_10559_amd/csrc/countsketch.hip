@@ -521,19 +521,35 @@ __device__ __forceinline__ int64_t wave_incl_scan(int64_t x) {
     return x;
 }
 
+// inclusive max-scan over the wave of values >= 0: row_shr 1, 2, 4, 8 inside
+// each row of 16 lanes (lanes shifted in from outside the row read 0), then
+// row_bcast15 / row_bcast31 carry the row maxima into the later rows
+__device__ __forceinline__ int wave_max_scan(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false));
+    return x;
+}
+
 // LDS-privatised variant: the whole bucket row of Y1 (n <= CSR_LDS_MAX) lives in
 // LDS; a workgroup handles positions [p0, p1) of the bucket's row list.
 // Entry-parallel: a wave takes a batch of 64 consecutive rows of the list
 // (batches are handed out through an LDS counter), scans their lengths, and
 // then walks the batch's entries 64 at a time, lane q taking the q-th entry of
 // the chunk, so the loads of val / colind are coalesced whatever the row
-// lengths are.  The row of an entry is the last row whose start is <= it,
-// found by a binary search over the batch's starts held one per lane.  CSR_U
-// chunks are loaded before their LDS adds, so that many loads are in flight.
+// lengths are.  The row of an entry is the last row whose start is <= it: the
+// row running into the chunk comes from one ballot (rows are in start order),
+// each row starting inside the chunk announces its index at its start lane
+// with one forward permute, and a max-scan over the lanes hands every lane its
+// row.  CSR_U chunks are loaded before their LDS adds, so that many loads are
+// in flight.
 __global__ __launch_bounds__(CSR_THREADS) void cs_csr_lds_kernel(const int64_t* __restrict__ rowptr,
                                                                   const int32_t* __restrict__ colind,
-                                                                  const double* __restrict__ val, int64_t n,
-                                                                  const int32_t* __restrict__ off,
+                                                                  const double* __restrict__ val, int64_t m,
+                                                                  int64_t n, const int32_t* __restrict__ off,
                                                                   const int32_t* __restrict__ rows, int nchunk,
                                                                   double* __restrict__ Y, int64_t rs, int64_t cs,
                                                                   int use_atomic) {
@@ -550,6 +566,7 @@ __global__ __launch_bounds__(CSR_THREADS) void cs_csr_lds_kernel(const int64_t* 
     const int p1 = beg + (int)(cnt * (ch + 1) / nchunk);
     const int nbat = (p1 - p0 + 63) / 64;
     const int lane = threadIdx.x & 63;
+    const int64_t nnz = rowptr[m];  // entry indices are clamped into [0, nnz)
 
     auto grab = [&]() -> int {
         int bi = 0;
@@ -590,7 +607,7 @@ __global__ __launch_bounds__(CSR_THREADS) void cs_csr_lds_kernel(const int64_t* 
         const int64_t base2 = 2 * (e0 - pre) + (neg ? 1 : 0);
         // an entry every lane may load: the first entry of the batch
         const uint64_t nz = __ballot(len > 0);
-        const int64_t e_any = nz ? __shfl(e0, __ffsll((unsigned long long)nz) - 1, 64) : 0;
+        const int64_t e_any = nz ? min(__shfl(e0, __ffsll((unsigned long long)nz) - 1, 64), nnz - 1) : 0;
         for (int64_t B = 0; B < T; B += 64 * CSR_U) {
             // (1) entry index of every chunk (branch-free, so the searches of
             //     the chunks interleave); lanes past the end load e_any
@@ -599,17 +616,18 @@ __global__ __launch_bounds__(CSR_THREADS) void cs_csr_lds_kernel(const int64_t* 
 #pragma unroll
             for (int u = 0; u < CSR_U; ++u) {
                 const int64_t Bu = B + 64 * u;
-                // batch-relative start of this lane's row, clamped to [-1, 64]
-                const int rel = (int)max((int64_t)-1, min(pre - Bu, (int64_t)64));
-                int r = 0;
-#pragma unroll
-                for (int st = 32; st >= 1; st >>= 1)
-                    if (__shfl(rel, r + st, 64) <= lane) r += st;
+                // the row holding entry Bu: the last row with start <= Bu
+                const int rc = __popcll(__ballot(pre <= Bu)) - 1;
+                // rows starting at Bu + d, 0 < d < 64, post index + 1 at lane d
+                const int64_t d = pre - Bu;
+                const bool in = len > 0 && d > 0 && d < 64;
+                const int post = __builtin_amdgcn_ds_permute(in ? (int)d * 4 : 0, in ? lane + 1 : 0);
+                const int r = min(63, max(rc, wave_max_scan(post) - 1));
                 const int64_t bb = __shfl(base2, r, 64);
                 const int64_t q = Bu + lane;
                 ok[u] = q < T;
                 sg[u] = bb & 1;
-                e[u] = ok[u] ? (bb >> 1) + q : e_any;
+                e[u] = ok[u] ? max((int64_t)0, min((bb >> 1) + q, nnz - 1)) : e_any;
             }
             // (2) all loads in flight
             double v[CSR_U];
@@ -690,7 +708,7 @@ ids_status cs_csr(const int64_t* rowptr, const int32_t* colind, const double* va
                                rs, cs);
         }
         hipLaunchKernelGGL(cs_csr_lds_kernel, dim3((unsigned)(L * nchunk)), dim3(CSR_THREADS), lds, st, rowptr,
-                           colind, val, n, (const int32_t*)pb.off, (const int32_t*)pb.rows, nchunk, Y, rs, cs,
+                           colind, val, m, n, (const int32_t*)pb.off, (const int32_t*)pb.rows, nchunk, Y, rs, cs,
                            use_atomic);
     } else {
         int64_t tot = L * n;
