@@ -431,16 +431,16 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
     p += T.part;
     char* sel = p;
     double* Yout = Y ? Y : Yw;
+    uint64_t keys[8];
+    for (int n = 0; n < N; ++n) keys[n] = stream_key(seed, (uint64_t)n + 1);
     {
         ProfScope ps(PK_PLAN, st);
-        uint64_t keys[8];
-        for (int n = 0; n < N; ++n) keys[n] = stream_key(seed, (uint64_t)n + 1);
         if ((s = plan_build_many(N, T.ps, keys, pb, st))) return s;
         if ((s = twiddles(Jlen, tw, st))) return s;
     }
     {
         ProfScope ps(PK_TS, st);
-        if ((s = tensorsketch(N, dims, R, factors, ld, lambda, Jlen, pb, tw, Yout, st))) return s;
+        if ((s = tensorsketch(N, dims, R, factors, ld, lambda, Jlen, pb, keys, tw, Yout, st))) return s;
     }
     if (l) {
         // Gaussian second stage: Yp (l x R, column-major) = G (l x Jlen) T M

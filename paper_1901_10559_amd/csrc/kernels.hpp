@@ -89,7 +89,7 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
 // ---- TensorSketch -------------------------------------------------------------
 ids_status tensorsketch(int32_t N, const int64_t* dims, int64_t R, const double* const* factors,
                         const int64_t* ld, const double* lambda, int64_t Jlen, const PlanBufs* plans,
-                        const double2* twiddle, double* Y, hipStream_t st);
+                        const uint64_t* keys, const double2* twiddle, double* Y, hipStream_t st);
 ids_status twiddles(int64_t Jlen, double2* tw, hipStream_t st);
 size_t ts_lds_bytes(int64_t J);
 

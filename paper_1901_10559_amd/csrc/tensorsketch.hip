@@ -6,8 +6,7 @@
 //
 // One 256-thread workgroup sketches two columns (r, r+1) at once:
 //   * per mode: the two real CountSketches are packed as c(r) + i c(r+1) into
-//     an LDS buffer (each bucket summed by one thread from the mode's sorted
-//     plan, so the result is deterministic), transformed by a radix-16
+//     an LDS buffer, transformed by a radix-16
 //     Stockham FFT in LDS, and split into the two half spectra
 //     (Z[k] + conj Z[-k]) / 2 and (Z[k] - conj Z[-k]) / 2i, which are
 //     multiplied into two running products (k = 0..J/2);
@@ -16,6 +15,15 @@
 // LDS: the padded complex work buffer (J * 17/16); the two half-spectrum
 // products stay in registers (each thread owns up to 9 frequencies), so two
 // workgroups share a CU.
+//
+// Mode CountSketch: thread t owns the contiguous bucket range
+// [t J / 256, (t+1) J / 256), hence the contiguous stretch of the mode's plan
+// (rows grouped by bucket, ascending row index inside a bucket).  It loads the
+// stretch's row codes and factor entries TS_CB at a time (independent loads),
+// recomputes each row's bucket from the hash, and adds the entries into a
+// running bucket sum that it writes out when the bucket changes.  Every bucket
+// is summed by one thread, from 0, in ascending row order: the result does not
+// depend on scheduling.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -129,7 +137,10 @@ struct TsArgs {
     const double* lambda;
     const double2* tw;
     double* Y;  // J x R column-major
+    uint64_t key[8];  // hash key of each mode's plan
 };
+
+constexpr int TS_CB = 8;  // plan positions loaded together
 
 // frequencies k = tid + 256 q (q < TS_NK) of the half spectrum 0..J/2 are owned
 // by thread tid, which keeps their running products in registers
@@ -150,21 +161,49 @@ __global__ __launch_bounds__(256) void tensorsketch_kernel(TsArgs a) {
         const int32_t* off = a.off[md];
         const int32_t* rows = a.rows[md];
         // mode-n CountSketch of columns r0, r0+1 packed as re + i im
-        for (int b = tid; b < J; b += 256) {
+        {
+            const int bA = (int)(((int64_t)tid * J) >> 8), bB = (int)(((int64_t)(tid + 1) * J) >> 8);
+            const int pA = off[bA], pB = off[bB];
+            const uint64_t key = a.key[md];
             double s0 = 0.0, s1 = 0.0;
-            for (int p = off[b]; p < off[b + 1]; ++p) {
-                const int32_t code = rows[p];
-                const int64_t i = code >= 0 ? code : -(int64_t)code - 1;
-                const double x0 = f0[i], x1 = f1[i];
-                if (code < 0) {
-                    s0 -= x0;
-                    s1 -= x1;
-                } else {
-                    s0 += x0;
-                    s1 += x1;
+            int bcur = bA;
+            for (int pb = pA; pb < pB; pb += TS_CB) {
+                int32_t code[TS_CB];
+#pragma unroll
+                for (int u = 0; u < TS_CB; ++u) code[u] = (pb + u < pB) ? rows[pb + u] : 0;
+                double x0[TS_CB], x1[TS_CB];
+#pragma unroll
+                for (int u = 0; u < TS_CB; ++u) {
+                    const int64_t i = code[u] >= 0 ? code[u] : -(int64_t)code[u] - 1;
+                    x0[u] = (pb + u < pB) ? f0[i] : 0.0;
+                    x1[u] = (pb + u < pB) ? f1[i] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < TS_CB; ++u) {
+                    if (pb + u < pB) {
+                        const int64_t i = code[u] >= 0 ? code[u] : -(int64_t)code[u] - 1;
+                        uint32_t bk;
+                        bool ng;
+                        hash_row(key, i, (uint32_t)J, bk, ng);
+                        while (bcur < (int)bk) {
+                            buf[padi(bcur)] = make_double2(s0, two ? s1 : 0.0);
+                            s0 = s1 = 0.0;
+                            ++bcur;
+                        }
+                        if (code[u] < 0) {
+                            s0 -= x0[u];
+                            s1 -= x1[u];
+                        } else {
+                            s0 += x0[u];
+                            s1 += x1[u];
+                        }
+                    }
                 }
             }
-            buf[padi(b)] = make_double2(s0, two ? s1 : 0.0);
+            for (; bcur < bB; ++bcur) {
+                buf[padi(bcur)] = make_double2(s0, two ? s1 : 0.0);
+                s0 = s1 = 0.0;
+            }
         }
         __syncthreads();
         fft_lds(buf, J, a.tw);
@@ -230,8 +269,8 @@ ids_status twiddles(int64_t Jlen, double2* tw, hipStream_t st) {
 size_t ts_lds_bytes(int64_t J) { return sizeof(double2) * (size_t)(J + J / 16); }
 
 ids_status tensorsketch(int32_t N, const int64_t* dims, int64_t R, const double* const* factors, const int64_t* ld,
-                        const double* lambda, int64_t Jlen, const PlanBufs* plans, const double2* tw, double* Y,
-                        hipStream_t st) {
+                        const double* lambda, int64_t Jlen, const PlanBufs* plans, const uint64_t* keys,
+                        const double2* tw, double* Y, hipStream_t st) {
     (void)dims;
     TsArgs a;
     a.N = N;
@@ -242,6 +281,7 @@ ids_status tensorsketch(int32_t N, const int64_t* dims, int64_t R, const double*
         a.ld[n] = ld[n];
         a.off[n] = plans[n].off;
         a.rows[n] = plans[n].rows;
+        a.key[n] = keys[n];
     }
     a.lambda = lambda;
     a.tw = tw;
