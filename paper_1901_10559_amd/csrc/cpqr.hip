@@ -26,12 +26,14 @@
 // a value that is not the sentinel is the value: there is no barrier counter,
 // fence or flag per step, and a reader waits only for the data it needs.
 // Data whose bits equal MB_SENT are stored as the canonical quiet NaN.
+// A step region starts with the headers, packed (publisher q at 2 q, 2 q + 1)
+// so that the vote polls a few cache lines only, followed by column space.
 // Two ways to move the winner's column (chosen on the host by size):
-//   MB_SPEC  every publisher also writes its best column speculatively next
-//            to its header; after the vote everyone reads the winner's copy;
+//   MB_SPEC  every publisher also writes its best column speculatively into
+//            its own column slot; after the vote everyone reads the winner's;
 //   MB_OWNER headers only; after the vote the owner of the winner publishes
-//            its column into the step's column box (long sketches and long
-//            factorisations, where the speculative copies would dominate).
+//            its column into the step's one column box (when the slots of all
+//            steps would make the region, filled before every call, large).
 // The reflector norm is the winner's published trailing norm:
 // ||x_{t..l-1}||^2 = nu_winner, so beta = -sign(alpha) sqrt(nu_winner) and no
 // workgroup re-sums the column.  (nu_winner <= alpha^2 means the entries
@@ -60,8 +62,8 @@ struct SelArgs {
     double* mb;       // k step regions of RS doubles each, sentinel-filled
     uint32_t* flag;   // [0] timeout flag
     int32_t nh;       // publishers (headers per step)
-    int32_t S;        // MB_SPEC: slot stride ([0] norm, [1] index, [2..2+l) column)
-    int32_t H0;       // MB_OWNER: offset of the column box (headers at 2 q)
+    int32_t S;        // MB_SPEC: stride of the publishers' column slots
+    int32_t H0;       // offset of the column area (header q at 2 q, 2 q + 1)
     int64_t RS;       // doubles per step region
 };
 
@@ -201,7 +203,7 @@ __device__ __forceinline__ void vote_prefetch(const SelArgs& a, const double* re
                                               double& wnu, int& wj, uint64_t (&xv)[U]) {
     const int lane = threadIdx.x & 63;
     const bool mine = lane < a.nh;
-    const double* hd = reg + (size_t)(mine ? lane : 0) * a.S;
+    const double* hd = reg + 2 * (mine ? lane : 0);
     uint64_t hn = 0, hj = 0;
     bool have = !mine;
     int cand = -1;
@@ -213,7 +215,7 @@ __device__ __forceinline__ void vote_prefetch(const SelArgs& a, const double* re
             hj = mb_load(hd + 1);
         }
         if (cand >= 0) {
-            const double* col = reg + (size_t)(cand / cols_per_blk) * a.S + 2;
+            const double* col = reg + a.H0 + (size_t)(cand / cols_per_blk) * a.S;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int i = lane + 64 * u;
@@ -388,7 +390,8 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
         double bn = (lane < NW) ? s_nu[par][lane] : -1.0;
         int bj = (lane < NW) ? s_j[par][lane] : INT32_MAX;
         wave_argmax(bn, bj);
-        double* hd = (MODE == MB_OWNER) ? reg + 2 * blockIdx.x : reg + (size_t)blockIdx.x * S;
+        double* hd = reg + 2 * blockIdx.x;
+        double* sc = reg + a.H0 + (size_t)blockIdx.x * S;  // MB_SPEC: this workgroup's column slot
         if (threadIdx.x == 0) {
             mb_put(hd, bn);
             mb_put(hd + 1, idx_bits(bj == INT32_MAX ? -1 : bj));
@@ -396,7 +399,7 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
         if (MODE == MB_SPEC && j == bj) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (row0 + r < l) mb_put(hd + 2 + row0 + r, y[r]);
+                if (row0 + r < l) mb_put(sc + row0 + r, y[r]);
         }
         // ---- vote, winner column -> LDS
         double wnu;
@@ -424,7 +427,7 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
             wnu = s_vn[par][0];
             wj = s_vj[par][0];
         } else {
-            vote_hdr<NW>(a, reg, MODE == MB_OWNER ? 2 : S, s_vn[par], s_vj[par], wnu, wj);
+            vote_hdr<NW>(a, reg, 2, s_vn[par], s_vj[par], wnu, wj);
         }
         if (wj == INT32_MAX || !(wnu > 0.0)) {
             keff = t;
@@ -433,7 +436,7 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
         if (one_wave_vote) {
             // the winner's rows are in LDS already
         } else if (MODE == MB_SPEC) {
-            fetch_col_lds<NT, PSH>(a, reg + (size_t)(wj / (NW * CPWV)) * S + 2, l, LP, xb);
+            fetch_col_lds<NT, PSH>(a, reg + a.H0 + (size_t)(wj / (NW * CPWV)) * S, l, LP, xb);
         } else {
             double* cb = reg + a.H0;
             if (j == wj) {
@@ -614,7 +617,8 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
                 bn = nu[c];
                 bc = c;
             }
-        double* hd = (MODE == MB_OWNER) ? reg + 2 * blockIdx.x : reg + (size_t)blockIdx.x * a.S;
+        double* hd = reg + 2 * blockIdx.x;
+        double* sc = reg + a.H0 + (size_t)blockIdx.x * a.S;  // MB_SPEC: this workgroup's column slot
         if (threadIdx.x == 0) {
             mb_put(hd, bn);
             mb_put(hd + 1, idx_bits(bc >= 0 ? col0 + bc : -1));
@@ -623,12 +627,12 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const int i = rb0 + 64 * r;
-                if (i < l) mb_put(hd + 2 + i, ysel(y, bc, r));
+                if (i < l) mb_put(sc + i, ysel(y, bc, r));
             }
         }
         double wnu;
         int wj;
-        vote_hdr<NW>(a, reg, MODE == MB_OWNER ? 2 : a.S, s_vn[par], s_vj[par], wnu, wj);
+        vote_hdr<NW>(a, reg, 2, s_vn[par], s_vj[par], wnu, wj);
         if (wj == INT32_MAX || !(wnu > 0.0)) {
             keff = t;
             break;
@@ -646,7 +650,7 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
             }
             src = cb;
         } else {
-            src = reg + (size_t)wblk * a.S + 2;
+            src = reg + a.H0 + (size_t)wblk * a.S;
         }
         double x[RB];
         {
@@ -970,18 +974,18 @@ static bool pick(int64_t l, Inst& in) {
 }
 
 static int64_t round32(int64_t x) { return (x + 31) / 32 * 32; }
-constexpr int SPEC_PUBS_MAX = 128;            // beyond: the speculative stores slow the vote
-constexpr size_t SPEC_STEP_MAX = 1u << 20;    // speculative columns of one step
-constexpr size_t SPEC_TOTAL_MAX = 64u << 20;  // speculative regions of all steps
+constexpr int SPEC_PUBS_MAX = 256;            // candidate columns stored per step
+constexpr size_t SPEC_TOTAL_MAX = 64u << 20;  // regions of all steps (each is filled with the sentinel)
 
 // mailbox mode and geometry (sp.l, sp.k, sp.nh set)
 static void mb_layout(SelectPlan& sp) {
-    sp.S = (int)round32(sp.l + 2);
-    const size_t step = sizeof(double) * (size_t)sp.S * sp.nh;
-    sp.mode = (sp.nh <= SPEC_PUBS_MAX && step <= SPEC_STEP_MAX && step * sp.k <= SPEC_TOTAL_MAX) ? MB_SPEC
-                                                                                                : MB_OWNER;
+    // headers packed at the start of each step region (one or a few cache
+    // lines for the vote to poll), column slots after them
     sp.H0 = (int)round32(2 * (int64_t)sp.nh);
-    sp.RS = (sp.mode == MB_OWNER) ? sp.H0 + round32(sp.l) : (int64_t)sp.S * sp.nh;
+    sp.S = (int)round32(sp.l);
+    const size_t step = sizeof(double) * ((size_t)sp.H0 + (size_t)sp.S * sp.nh);
+    sp.mode = (sp.nh <= SPEC_PUBS_MAX && step * sp.k <= SPEC_TOTAL_MAX) ? MB_SPEC : MB_OWNER;
+    sp.RS = (sp.mode == MB_OWNER) ? sp.H0 + round32(sp.l) : sp.H0 + (int64_t)sp.S * sp.nh;
 }
 
 static size_t cpqr_lds(const SelectPlan& sp, const Inst& in) {
