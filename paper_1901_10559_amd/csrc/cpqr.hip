@@ -85,8 +85,10 @@ __device__ __forceinline__ double idx_bits(int j) { return __longlong_as_double(
 // U values per lane from addr(u) (nullptr: unused, reads as 0).  Sentinel
 // entries are reloaded until every lane of the wave has final values; the
 // loop is wave-uniform.  On timeout the flag is raised and the remaining
-// entries keep the sentinel (a NaN).
-template <int U, class F>
+// entries keep the sentinel (a NaN).  SLEEP: pause about 64 clocks between
+// polls (less polling traffic on the lines being published; used where the
+// awaited data is normally on its way already).
+template <int U, bool SLEEP = false, class F>
 __device__ __forceinline__ void mb_read(uint64_t (&v)[U], F addr, uint32_t* flag) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -94,6 +96,7 @@ __device__ __forceinline__ void mb_read(uint64_t (&v)[U], F addr, uint32_t* flag
         v[u] = p ? mb_load(p) : 0ull;
     }
     for (uint32_t spin = 0;; ++spin) {
+        if (SLEEP && spin) __builtin_amdgcn_s_sleep(1);
         bool pend = false;
 #pragma unroll
         for (int u = 0; u < U; ++u) pend = pend || (v[u] == MB_SENT);
@@ -116,7 +119,9 @@ __global__ void mb_fill_kernel(uint64_t* mb, int64_t count, uint32_t* flag) {
 }
 
 // argmax over the wave of (nu, j): largest nu, then smallest j; j < 2^31.
-// DPP max / min trees fold into lane 63, which is broadcast.
+// DPP max / min trees fold into lane 63, which is broadcast.  With SKIP = s,
+// aligned groups of 2^s lanes hold identical pairs and the first s steps
+// (which only combine lanes inside such a group) are left out.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ double dpp_keep_f64(double v) {
     const int lo = __builtin_amdgcn_update_dpp(__double2loint(v), __double2loint(v), CTRL, ROW_MASK, 0xf, false);
@@ -127,24 +132,45 @@ template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ int dpp_keep_i32(int v) {
     return __builtin_amdgcn_update_dpp(v, v, CTRL, ROW_MASK, 0xf, false);
 }
+template <int SKIP = 0>
 __device__ __forceinline__ void wave_argmax(double& nu, int& j) {
     double m = nu;
-    m = fmax(m, dpp_keep_f64<0xB1, 0xf>(m));
-    m = fmax(m, dpp_keep_f64<0x4E, 0xf>(m));
-    m = fmax(m, dpp_keep_f64<0x141, 0xf>(m));
-    m = fmax(m, dpp_keep_f64<0x140, 0xf>(m));
+    if (SKIP < 1) m = fmax(m, dpp_keep_f64<0xB1, 0xf>(m));
+    if (SKIP < 2) m = fmax(m, dpp_keep_f64<0x4E, 0xf>(m));
+    if (SKIP < 3) m = fmax(m, dpp_keep_f64<0x141, 0xf>(m));
+    if (SKIP < 4) m = fmax(m, dpp_keep_f64<0x140, 0xf>(m));
     m = fmax(m, dpp_keep_f64<0x142, 0xa>(m));
     m = fmax(m, dpp_keep_f64<0x143, 0xc>(m));
     m = lane63_f64(m);
     int q = (nu == m) ? j : INT32_MAX;
-    q = min(q, dpp_keep_i32<0xB1, 0xf>(q));
-    q = min(q, dpp_keep_i32<0x4E, 0xf>(q));
-    q = min(q, dpp_keep_i32<0x141, 0xf>(q));
-    q = min(q, dpp_keep_i32<0x140, 0xf>(q));
+    if (SKIP < 1) q = min(q, dpp_keep_i32<0xB1, 0xf>(q));
+    if (SKIP < 2) q = min(q, dpp_keep_i32<0x4E, 0xf>(q));
+    if (SKIP < 3) q = min(q, dpp_keep_i32<0x141, 0xf>(q));
+    if (SKIP < 4) q = min(q, dpp_keep_i32<0x140, 0xf>(q));
     q = min(q, dpp_keep_i32<0x142, 0xa>(q));
     q = min(q, dpp_keep_i32<0x143, 0xc>(q));
     nu = m;
     j = __builtin_amdgcn_readlane(q, 63);
+}
+
+// the same over lanes 0..NL-1 only (NL = 2, 4, 8, 16), broadcast from lane 0
+template <int NL>
+__device__ __forceinline__ void wave_argmax_lo(double& nu, int& j) {
+    static_assert(NL == 2 || NL == 4 || NL == 8 || NL == 16, "NL must be 2, 4, 8 or 16");
+    double m = nu;
+    m = fmax(m, dpp_keep_f64<0xB1, 0xf>(m));
+    if (NL >= 4) m = fmax(m, dpp_keep_f64<0x4E, 0xf>(m));
+    if (NL >= 8) m = fmax(m, dpp_keep_f64<0x141, 0xf>(m));
+    if (NL >= 16) m = fmax(m, dpp_keep_f64<0x140, 0xf>(m));
+    m = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(m), 0),
+                         __builtin_amdgcn_readlane(__double2loint(m), 0));
+    int q = (nu == m) ? j : INT32_MAX;
+    q = min(q, dpp_keep_i32<0xB1, 0xf>(q));
+    if (NL >= 4) q = min(q, dpp_keep_i32<0x4E, 0xf>(q));
+    if (NL >= 8) q = min(q, dpp_keep_i32<0x141, 0xf>(q));
+    if (NL >= 16) q = min(q, dpp_keep_i32<0x140, 0xf>(q));
+    nu = m;
+    j = __builtin_amdgcn_readlane(q, 0);
 }
 
 // fold one published header into a running (norm, index) best
@@ -161,13 +187,13 @@ __device__ __forceinline__ void take(uint64_t nb_bits, uint64_t j_bits, double& 
 // by all threads of the workgroup (up to 4 each), reduced per wave, then over
 // the waves through LDS; every wave returns the same winner.
 constexpr int VOTE_PER_THREAD = 4;
-template <int NW>
+template <int NW, bool SLEEP>
 __device__ __forceinline__ void vote_hdr(const SelArgs& a, const double* reg, int hs, double* s_vn, int* s_vj,
                                          double& wnu, int& wj) {
     constexpr int NT = NW * 64;
     constexpr int UH = VOTE_PER_THREAD;
     uint64_t hv[2 * UH];
-    mb_read<2 * UH>(
+    mb_read<2 * UH, SLEEP>(
         hv,
         [&](int u) -> const double* {
             const int q = (int)threadIdx.x + NT * (u >> 1);
@@ -188,7 +214,7 @@ __device__ __forceinline__ void vote_hdr(const SelArgs& a, const double* reg, in
     __syncthreads();
     wnu = (lane < NW) ? s_vn[lane] : -1.0;
     wj = (lane < NW) ? s_vj[lane] : INT32_MAX;
-    wave_argmax(wnu, wj);
+    wave_argmax_lo<NW>(wnu, wj);
 }
 
 // Vote and winner column in one wave (speculative slots, nh <= 64 headers):
@@ -210,6 +236,7 @@ __device__ __forceinline__ void vote_prefetch(const SelArgs& a, const double* re
 #pragma unroll
     for (int u = 0; u < U; ++u) xv[u] = MB_SENT;
     for (uint32_t spin = 0;; ++spin) {
+        if (spin) __builtin_amdgcn_s_sleep(1);  // about 64 clocks between polls
         if (!have) {
             hn = mb_load(hd);
             hj = mb_load(hd + 1);
@@ -255,12 +282,12 @@ __device__ __forceinline__ void vote_prefetch(const SelArgs& a, const double* re
 // l published values at src -> LDS dst, zeros up to lpad (all threads), then a
 // workgroup barrier.  Row i is stored at i + (i >> PSH): one pad slot per
 // 2^PSH rows, so lane parts that read rows 2^PSH apart hit different banks.
-template <int NT, int PSH>
+template <int NT, int PSH, bool SLEEP>
 __device__ __forceinline__ void fetch_col_lds(const SelArgs& a, const double* src, int l, int lpad, double* dst) {
     for (int i = l + (int)threadIdx.x; i < lpad; i += NT) dst[i + (i >> PSH)] = 0.0;
     for (int i0 = 0; i0 < l; i0 += NT * 8) {
         uint64_t v[8];
-        mb_read<8>(
+        mb_read<8, SLEEP>(
             v,
             [&](int u) -> const double* {
                 const int i = i0 + u * NT + (int)threadIdx.x;
@@ -343,24 +370,22 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
     bool alive = j < n;
     int tsel = -1;  // step at which this column was chosen
     {
+        // every lane loads all R rows (addresses clamped into Y), then masks:
+        // the barrier keeps the compiler from turning the mask into a branch
+        // around each load, which would serialise the loads
         const int64_t jc = min(j, n - 1);
         if (a.ydt == IDS_F64) {
             const double* Yp = (const double*)a.Y;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = row0 + r;
-                const double v = Yp[(int64_t)min(i, l - 1) * a.rs + jc * a.cs];
-                y[r] = (alive && i < l) ? v : 0.0;
-            }
+            for (int r = 0; r < R; ++r) y[r] = Yp[(int64_t)min(row0 + r, l - 1) * a.rs + jc * a.cs];
         } else {
             const float* Yp = (const float*)a.Y;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = row0 + r;
-                const double v = (double)Yp[(int64_t)min(i, l - 1) * a.rs + jc * a.cs];
-                y[r] = (alive && i < l) ? v : 0.0;
-            }
+            for (int r = 0; r < R; ++r) y[r] = (double)Yp[(int64_t)min(row0 + r, l - 1) * a.rs + jc * a.cs];
         }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int r = 0; r < R; ++r) y[r] = (alive && row0 + r < l) ? y[r] : 0.0;
     }
     if (alive && p == 0) a.pos[j] = -1;
     double nu;
@@ -380,7 +405,7 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
         {
             double wn = alive ? nu : -1.0;
             int wjw = alive ? j : INT32_MAX;
-            wave_argmax(wn, wjw);
+            wave_argmax<ilog2(G)>(wn, wjw);  // the G lanes of a column agree
             if (lane == 0) {
                 s_nu[par][w] = wn;
                 s_j[par][w] = wjw;
@@ -389,13 +414,14 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
         __syncthreads();
         double bn = (lane < NW) ? s_nu[par][lane] : -1.0;
         int bj = (lane < NW) ? s_j[par][lane] : INT32_MAX;
-        wave_argmax(bn, bj);
+        wave_argmax_lo<NW>(bn, bj);
         double* hd = reg + 2 * blockIdx.x;
         double* sc = reg + a.H0 + (size_t)blockIdx.x * S;  // MB_SPEC: this workgroup's column slot
         if (threadIdx.x == 0) {
             mb_put(hd, bn);
             mb_put(hd + 1, idx_bits(bj == INT32_MAX ? -1 : bj));
         }
+        const bool one_wave_vote = MODE == MB_SPEC && a.nh <= 64;  // uniform
         if (MODE == MB_SPEC && j == bj) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
@@ -405,7 +431,6 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
         double wnu;
         int wj;
         double* xb = sm + par * LB;
-        const bool one_wave_vote = MODE == MB_SPEC && a.nh <= 64;  // uniform
         if (one_wave_vote) {
             constexpr int UP = (LP + 63) / 64;
             if (w == 0) {
@@ -427,7 +452,7 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
             wnu = s_vn[par][0];
             wj = s_vj[par][0];
         } else {
-            vote_hdr<NW>(a, reg, 2, s_vn[par], s_vj[par], wnu, wj);
+            vote_hdr<NW, MODE == MB_SPEC>(a, reg, 2, s_vn[par], s_vj[par], wnu, wj);
         }
         if (wj == INT32_MAX || !(wnu > 0.0)) {
             keff = t;
@@ -436,7 +461,7 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
         if (one_wave_vote) {
             // the winner's rows are in LDS already
         } else if (MODE == MB_SPEC) {
-            fetch_col_lds<NT, PSH>(a, reg + a.H0 + (size_t)(wj / (NW * CPWV)) * S, l, LP, xb);
+            fetch_col_lds<NT, PSH, true>(a, reg + a.H0 + (size_t)(wj / (NW * CPWV)) * S, l, LP, xb);
         } else {
             double* cb = reg + a.H0;
             if (j == wj) {
@@ -444,7 +469,7 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
                 for (int r = 0; r < R; ++r)
                     if (row0 + r < l) mb_put(cb + row0 + r, y[r]);
             }
-            fetch_col_lds<NT, PSH>(a, cb, l, LP, xb);
+            fetch_col_lds<NT, PSH, false>(a, cb, l, LP, xb);
         }
         // ---- Householder reflector (every wave, same bits)
         double tau, beta, scal;
@@ -579,19 +604,37 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
     double y[NC][RB];
     bool alive[NC];
     int tsel[NC];  // step at which column c was chosen (uniform)
+    // every load is issued before any value is used (FP32 data waits in the
+    // low word of y until then), so the loads overlap
+    const bool f64 = a.ydt == IDS_F64;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const int64_t jc = min(col0 + c, n - 1);
         alive[c] = col0 + c < n;
         tsel[c] = -1;
+    }
+    if (f64) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                y[c][r] = ((const double*)a.Y)[(int64_t)min(rb0 + 64 * r, l - 1) * a.rs +
+                                               (int64_t)min(col0 + c, n - 1) * a.cs];
+    } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                y[c][r] = __hiloint2double(0, __float_as_int(((const float*)a.Y)[(int64_t)min(rb0 + 64 * r, l - 1) * a.rs +
+                                                                                 (int64_t)min(col0 + c, n - 1) * a.cs]));
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const int i = rb0 + 64 * r;
-            const int64_t off = (int64_t)min(i, l - 1) * a.rs + jc * a.cs;
-            const double v = (a.ydt == IDS_F64) ? ((const double*)a.Y)[off] : (double)((const float*)a.Y)[off];
-            y[c][r] = (alive[c] && i < l) ? v : 0.0;
+            const double v = f64 ? y[c][r] : (double)__int_as_float(__double2loint(y[c][r]));
+            y[c][r] = (alive[c] && rb0 + 64 * r < l) ? v : 0.0;
         }
-    }
     if (w == 0 && lane < NC && col0 + lane < n) a.pos[col0 + lane] = -1;
     double nu[NC];
 #pragma unroll
@@ -632,7 +675,7 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
         }
         double wnu;
         int wj;
-        vote_hdr<NW>(a, reg, 2, s_vn[par], s_vj[par], wnu, wj);
+        vote_hdr<NW, MODE == MB_SPEC>(a, reg, 2, s_vn[par], s_vj[par], wnu, wj);
         if (wj == INT32_MAX || !(wnu > 0.0)) {
             keff = t;
             break;
@@ -655,7 +698,7 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
         double x[RB];
         {
             uint64_t xv[RB];
-            mb_read<RB>(
+            mb_read<RB, MODE == MB_SPEC>(
                 xv,
                 [&](int r) -> const double* {
                     const int i = rb0 + 64 * r;
