@@ -27,13 +27,19 @@
 // fence or flag per step, and a reader waits only for the data it needs.
 // Data whose bits equal MB_SENT are stored as the canonical quiet NaN.
 // A step region starts with the headers, packed (publisher q at 2 q, 2 q + 1)
-// so that the vote polls a few cache lines only, followed by column space.
-// Two ways to move the winner's column (chosen on the host by size):
+// so that the vote polls a few cache lines only.  Two ways to move the
+// winner's column (chosen on the host by size):
 //   MB_SPEC  every publisher also writes its best column speculatively into
-//            its own column slot; after the vote everyone reads the winner's;
+//            its own column slot; after the vote everyone reads the winner's.
+//            The slots form two sets used by alternate steps: once the vote
+//            of step t is complete every workgroup has finished step t - 1,
+//            so each workgroup resets its own slot of that set to the
+//            sentinel for step t + 1, and waits for those stores to complete
+//            before the barrier that precedes its next publication (the one
+//            place where a location is written twice: sentinel, then value);
 //   MB_OWNER headers only; after the vote the owner of the winner publishes
-//            its column into the step's one column box (when the slots of all
-//            steps would make the region, filled before every call, large).
+//            its column into the step's column box, which follows the
+//            headers (many publishers or very long columns).
 // The reflector norm is the winner's published trailing norm:
 // ||x_{t..l-1}||^2 = nu_winner, so beta = -sign(alpha) sqrt(nu_winner) and no
 // workgroup re-sums the column.  (nu_winner <= alpha^2 means the entries
@@ -63,13 +69,23 @@ struct SelArgs {
     uint32_t* flag;   // [0] timeout flag
     int32_t nh;       // publishers (headers per step)
     int32_t S;        // MB_SPEC: stride of the publishers' column slots
-    int32_t H0;       // offset of the column area (header q at 2 q, 2 q + 1)
+    int32_t H0;       // header q at 2 q, 2 q + 1 of a step region; MB_OWNER: column box at H0
     int64_t RS;       // doubles per step region
+    double* ring;     // MB_SPEC: two sets of column slots (step t uses set t & 1)
+    int64_t CS;       // MB_SPEC: doubles per set (nh slots of S)
 };
 
 constexpr uint64_t MB_SENT = 0xFFF4A5A5A5A5A5A5ull;
 constexpr uint64_t MB_QNAN = 0x7FF8000000000000ull;
 constexpr uint32_t SPIN_LIMIT = 1u << 20;
+
+// MB_SPEC column slots of step t
+__device__ __forceinline__ double* spec_slots(const SelArgs& a, int t) { return a.ring + (size_t)(t & 1) * a.CS; }
+
+// back to the sentinel (a slot reused two steps later)
+__device__ __forceinline__ void mb_clear(double* p) {
+    __hip_atomic_store((uint64_t*)p, MB_SENT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ void mb_put(double* p, double v) {
     uint64_t b = (uint64_t)__double_as_longlong(v);
@@ -225,8 +241,8 @@ __device__ __forceinline__ void vote_hdr(const SelArgs& a, const double* reg, in
 // Returns with the winner in (wnu, wj) and its rows in xv (0 past l), all
 // lanes agreeing; on timeout the flag is raised and the values may be NaN.
 template <int U>
-__device__ __forceinline__ void vote_prefetch(const SelArgs& a, const double* reg, int cols_per_blk, int l,
-                                              double& wnu, int& wj, uint64_t (&xv)[U]) {
+__device__ __forceinline__ void vote_prefetch(const SelArgs& a, const double* reg, const double* slots,
+                                              int cols_per_blk, int l, double& wnu, int& wj, uint64_t (&xv)[U]) {
     const int lane = threadIdx.x & 63;
     const bool mine = lane < a.nh;
     const double* hd = reg + 2 * (mine ? lane : 0);
@@ -242,7 +258,7 @@ __device__ __forceinline__ void vote_prefetch(const SelArgs& a, const double* re
             hj = mb_load(hd + 1);
         }
         if (cand >= 0) {
-            const double* col = reg + a.H0 + (size_t)(cand / cols_per_blk) * a.S;
+            const double* col = slots + (size_t)(cand / cols_per_blk) * a.S;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int i = lane + 64 * u;
@@ -411,12 +427,17 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
                 s_j[par][w] = wjw;
             }
         }
+        // the previous step's sentinel stores into this step's column slot are
+        // complete (globally visible) before the barrier, hence before this
+        // workgroup's header and column of this step
+        if (MODE == MB_SPEC) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         double bn = (lane < NW) ? s_nu[par][lane] : -1.0;
         int bj = (lane < NW) ? s_j[par][lane] : INT32_MAX;
         wave_argmax_lo<NW>(bn, bj);
         double* hd = reg + 2 * blockIdx.x;
-        double* sc = reg + a.H0 + (size_t)blockIdx.x * S;  // MB_SPEC: this workgroup's column slot
+        double* slots = (MODE == MB_SPEC) ? spec_slots(a, t) : nullptr;
+        double* sc = slots + (size_t)blockIdx.x * S;  // MB_SPEC: this workgroup's column slot
         if (threadIdx.x == 0) {
             mb_put(hd, bn);
             mb_put(hd + 1, idx_bits(bj == INT32_MAX ? -1 : bj));
@@ -437,7 +458,7 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
                 uint64_t xv[UP];
                 double vn;
                 int vj;
-                vote_prefetch<UP>(a, reg, NW * CPWV, l, vn, vj, xv);
+                vote_prefetch<UP>(a, reg, slots, NW * CPWV, l, vn, vj, xv);
 #pragma unroll
                 for (int u = 0; u < UP; ++u) {
                     const int i = lane + 64 * u;
@@ -458,10 +479,17 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
             keff = t;
             break;
         }
+        if (MODE == MB_SPEC && t >= 1 && t + 1 < k) {
+            // every workgroup has published step t, so none still reads the
+            // column slots of step t - 1: this workgroup's slot there is
+            // reset for step t + 1 (same slot set)
+            double* nsc = spec_slots(a, t + 1) + (size_t)blockIdx.x * S;
+            for (int i = threadIdx.x; i < l; i += NT) mb_clear(nsc + i);
+        }
         if (one_wave_vote) {
             // the winner's rows are in LDS already
         } else if (MODE == MB_SPEC) {
-            fetch_col_lds<NT, PSH, true>(a, reg + a.H0 + (size_t)(wj / (NW * CPWV)) * S, l, LP, xb);
+            fetch_col_lds<NT, PSH, true>(a, slots + (size_t)(wj / (NW * CPWV)) * S, l, LP, xb);
         } else {
             double* cb = reg + a.H0;
             if (j == wj) {
@@ -661,7 +689,8 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
                 bc = c;
             }
         double* hd = reg + 2 * blockIdx.x;
-        double* sc = reg + a.H0 + (size_t)blockIdx.x * a.S;  // MB_SPEC: this workgroup's column slot
+        double* slots = (MODE == MB_SPEC) ? spec_slots(a, t) : nullptr;
+        double* sc = slots + (size_t)blockIdx.x * a.S;  // MB_SPEC: this workgroup's column slot
         if (threadIdx.x == 0) {
             mb_put(hd, bn);
             mb_put(hd + 1, idx_bits(bc >= 0 ? col0 + bc : -1));
@@ -693,7 +722,7 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
             }
             src = cb;
         } else {
-            src = reg + a.H0 + (size_t)wblk * a.S;
+            src = slots + (size_t)wblk * a.S;
         }
         double x[RB];
         {
@@ -707,6 +736,15 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
                 a.flag);
 #pragma unroll
             for (int r = 0; r < RB; ++r) x[r] = (rb0 + 64 * r < l) ? mb_val(xv[r]) : 0.0;
+        }
+        if (MODE == MB_SPEC && t >= 1 && t + 1 < k) {
+            // every workgroup has published step t, so none still reads the
+            // column slots of step t - 1: this workgroup's slot there is reset
+            // for step t + 1 (each thread its own rows, as it writes them)
+            double* nsc = spec_slots(a, t + 1) + (size_t)blockIdx.x * a.S;
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+                if (rb0 + 64 * r < l) mb_clear(nsc + rb0 + 64 * r);
         }
         // ---- dot products with the rows below t
         double pa[NC];
@@ -779,6 +817,9 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
                 nu[c] = s;
             }
         }
+        // the sentinel stores are complete (globally visible) before the
+        // barriers below, hence before the next step's header
+        if (MODE == MB_SPEC) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         wg_sum_t<NC, NW>(nu, red, res);
         if (blockIdx.x == 0 && threadIdx.x == 0) a.J[t] = wj;
     }
@@ -1018,7 +1059,7 @@ static bool pick(int64_t l, Inst& in) {
 
 static int64_t round32(int64_t x) { return (x + 31) / 32 * 32; }
 constexpr int SPEC_PUBS_MAX = 256;            // candidate columns stored per step
-constexpr size_t SPEC_TOTAL_MAX = 64u << 20;  // regions of all steps (each is filled with the sentinel)
+constexpr size_t SPEC_RING_MAX = 64u << 20;   // the two sets of column slots
 
 // mailbox mode and geometry (sp.l, sp.k, sp.nh set)
 static void mb_layout(SelectPlan& sp) {
@@ -1026,9 +1067,10 @@ static void mb_layout(SelectPlan& sp) {
     // lines for the vote to poll), column slots after them
     sp.H0 = (int)round32(2 * (int64_t)sp.nh);
     sp.S = (int)round32(sp.l);
-    const size_t step = sizeof(double) * ((size_t)sp.H0 + (size_t)sp.S * sp.nh);
-    sp.mode = (sp.nh <= SPEC_PUBS_MAX && step * sp.k <= SPEC_TOTAL_MAX) ? MB_SPEC : MB_OWNER;
-    sp.RS = (sp.mode == MB_OWNER) ? sp.H0 + round32(sp.l) : sp.H0 + (int64_t)sp.S * sp.nh;
+    const size_t ring = 2 * sizeof(double) * (size_t)sp.S * sp.nh;  // two sets of column slots
+    sp.mode = (sp.nh <= SPEC_PUBS_MAX && ring <= SPEC_RING_MAX) ? MB_SPEC : MB_OWNER;
+    sp.RS = (sp.mode == MB_OWNER) ? sp.H0 + round32(sp.l) : sp.H0;
+    sp.CS = (sp.mode == MB_OWNER) ? 0 : (int64_t)sp.S * sp.nh;
 }
 
 static size_t cpqr_lds(const SelectPlan& sp, const Inst& in) {
@@ -1072,8 +1114,10 @@ ids_status select_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp) {
     return IDS_OK;
 }
 
+static size_t mb_doubles(const SelectPlan& sp) { return (size_t)sp.k * sp.RS + 2 * (size_t)sp.CS; }
+
 size_t select_bytes(const SelectPlan& sp) {
-    return align256(sizeof(double) * (size_t)sp.k * sp.RS) + align256(sizeof(uint32_t) * 2) +
+    return align256(sizeof(double) * mb_doubles(sp)) + align256(sizeof(uint32_t) * 2) +
            align256(sizeof(double) * (size_t)sp.n * sp.k) + align256(sizeof(double) * (size_t)sp.k * sp.k) +
            align256(sizeof(int32_t) * (size_t)sp.n);
 }
@@ -1094,9 +1138,11 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
     a.S = sp.S;
     a.H0 = sp.H0;
     a.RS = sp.RS;
+    a.CS = sp.CS;
     char* p = ws;
     a.mb = (double*)p;
-    p += align256(sizeof(double) * (size_t)sp.k * sp.RS);
+    a.ring = a.mb + (size_t)sp.k * sp.RS;
+    p += align256(sizeof(double) * mb_doubles(sp));
     a.flag = (uint32_t*)p;
     p += align256(sizeof(uint32_t) * 2);
     a.Rt = (double*)p;
@@ -1107,7 +1153,7 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
 
     Inst in;
     pick(sp.l, in);
-    const int64_t cnt = sp.k * sp.RS;
+    const int64_t cnt = (int64_t)mb_doubles(sp);
     const unsigned fg = (unsigned)std::min<int64_t>((cnt + 255) / 256, 4096);
     hipLaunchKernelGGL(mb_fill_kernel, dim3(fg), dim3(256), 0, st, (uint64_t*)a.mb, cnt, a.flag);
     void* args[] = {&a};

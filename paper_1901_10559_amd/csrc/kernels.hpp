@@ -69,6 +69,7 @@ struct SelectPlan {
     int nh;                 // candidate publishers per step
     int mode, S, H0;        // mailbox exchange: mode, slot stride, column box offset
     int64_t RS;             // mailbox doubles per factorisation step
+    int64_t CS;             // speculative mode: doubles per set of column slots (two sets)
 };
 ids_status select_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp);
 size_t select_bytes(const SelectPlan& sp);
