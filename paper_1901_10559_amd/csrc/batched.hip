@@ -367,7 +367,7 @@ __device__ __forceinline__ double tree_sum_d(double (&s)[N]) {
 // (n_p <= NT for the smallest NT), so small problems share a CU and hide each
 // other's per-step latency.
 template <int NT>
-__global__ __launch_bounds__(NT) void batched_cpqr_kernel(BatchArgs a, int nt_min) {
+__global__ __launch_bounds__(NT, 4) void batched_cpqr_kernel(BatchArgs a, int nt_min) {  // 4 waves per SIMD
     extern __shared__ float ylds[];           // BC_RL x NT
     __shared__ __attribute__((aligned(16))) float xf[BS_LMAX];  // pivot column (FP32)
     __shared__ __attribute__((aligned(16))) float vb[BS_LMAX];  // reflector (FP32)
@@ -387,18 +387,21 @@ __global__ __launch_bounds__(NT) void batched_cpqr_kernel(BatchArgs a, int nt_mi
 
     float y[BC_RR];
     {
-        const int jc = min(j, n - 1);
+        // column j of Y_p (clamped addresses, so every load is unconditional
+        // and all are in flight together; masked after compiler barriers):
+        // the LDS rows travel through y first, then the register rows
+        static_assert(BC_RL <= BC_RR, "LDS rows are staged in y");
+        const float* colp = Yp + (int64_t)min(j, n - 1) * l;
 #pragma unroll
-        for (int r = 0; r < BC_RL; ++r) {
-            const float v = Yp[(int64_t)jc * l + min(r, l - 1)];
-            ylds[r * NT + j] = (alive && r < l) ? v : 0.f;
-        }
+        for (int r = 0; r < BC_RL; ++r) y[r] = colp[min(r, l - 1)];
+        asm volatile("" ::: "memory");
 #pragma unroll
-        for (int r = 0; r < BC_RR; ++r) {
-            const int i = BC_RL + r;
-            const float v = Yp[(int64_t)jc * l + min(i, l - 1)];
-            y[r] = (alive && i < l) ? v : 0.f;
-        }
+        for (int r = 0; r < BC_RL; ++r) ylds[r * NT + j] = (alive && r < l) ? y[r] : 0.f;
+#pragma unroll
+        for (int r = 0; r < BC_RR; ++r) y[r] = colp[min(BC_RL + r, l - 1)];
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int r = 0; r < BC_RR; ++r) y[r] = (alive && BC_RL + r < l) ? y[r] : 0.f;
     }
     // sum of squares over rows i >= t0: squares summed in FP32 over chunks of 8
     // rows, the chunk sums accumulated in FP64 (relative error <= 8 * 2^-24,
