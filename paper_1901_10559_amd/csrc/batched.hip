@@ -575,9 +575,12 @@ __global__ __launch_bounds__(BT_THREADS) void batched_trsm_kernel(BatchArgs a) {
         keff * LDK, NT,
         [&](int e) {
             const int r = e / LDK, c = e % LDK;
-            return (c < r) ? Rt[(int64_t)Js[r] * k + c] : 0.0;
+            return Rt[(int64_t)Js[r] * k + min(c, k - 1)];
         },
-        [&](int e, double v) { R11T[e] = v; });
+        [&](int e, double v) {
+            const int r = e / LDK, c = e % LDK;
+            R11T[e] = (c < r) ? v : 0.0;
+        });
     copy_batched<1>(keff, NT, [&](int r) { return bt[r]; }, [&](int r, double v) { rd[r] = 1.0 / v; });
     __syncthreads();
     const int q = tid % GQ;

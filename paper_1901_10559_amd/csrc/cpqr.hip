@@ -847,9 +847,12 @@ __device__ __forceinline__ void stage_r11(double* R11s, const double* __restrict
         keff * keff, nthreads,
         [&](int e) {
             const int r = e / keff, c = e - r * keff;
-            return (r <= c) ? R11c[(int64_t)c * k + r] : 0.0;
+            return R11c[(int64_t)c * k + r];
         },
-        [&](int e, double v) { R11s[e] = v; });
+        [&](int e, double v) {
+            const int r = e / keff, c = e - r * keff;
+            R11s[e] = (r <= c) ? v : 0.0;
+        });
 }
 
 // P[:, j]: e_t for a chosen column, R11^{-1} R[0:keff, j] otherwise, by
@@ -971,9 +974,12 @@ __global__ __launch_bounds__(256) void trsm_axpy_kernel(int64_t n, int64_t k, co
         keff * LDK, 256,
         [&](int e) {
             const int r = e / LDK, c = e % LDK;
-            return (c < r) ? R11c[(int64_t)r * k + c] : 0.0;
+            return R11c[(int64_t)r * k + min(c, (int)k - 1)];
         },
-        [&](int e, double v) { R11T[e] = v; });
+        [&](int e, double v) {
+            const int r = e / LDK, c = e % LDK;
+            R11T[e] = (c < r) ? v : 0.0;
+        });
     copy_batched<1>(
         keff, 256, [&](int r) { return R11c[(int64_t)r * k + r]; }, [&](int r, double v) { rd[r] = 1.0 / v; });
     __syncthreads();

@@ -52,16 +52,17 @@ __device__ __forceinline__ void axpy_solve(double (&b)[TRSM_AX_KS], const double
 }
 
 // count elements e -> LDS through registers, U independent loads in flight per
-// thread (a plain loop would wait for each load before issuing the next)
+// thread.  ld must be valid for every e < count and free of branches around
+// its load (select after loading instead); slots past count load element
+// count - 1 and are not stored, so no load sits behind a branch and the U
+// loads are issued together.
 template <int U, class Ld, class St>
 __device__ __forceinline__ void copy_batched(int count, int nthreads, Ld ld, St st) {
     for (int e0 = threadIdx.x; e0 < count; e0 += U * nthreads) {
         double v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * nthreads;
-            v[u] = (e < count) ? ld(e) : 0.0;
-        }
+        for (int u = 0; u < U; ++u) v[u] = ld(min(e0 + u * nthreads, count - 1));
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = e0 + u * nthreads;
