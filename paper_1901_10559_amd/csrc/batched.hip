@@ -553,8 +553,8 @@ __global__ __launch_bounds__(NT, 4) void batched_cpqr_kernel(BatchArgs a, int nt
 constexpr int BT_THREADS = 512;  // 32 right-hand-side slots per lane need up to 256 VGPRs
 template <int GQ>
 __global__ __launch_bounds__(BT_THREADS) void batched_trsm_kernel(BatchArgs a) {
-    constexpr int KS = TRSM_AX_KS, LDK = GQ * KS, NT = BT_THREADS;
-    extern __shared__ double sm3[];
+    constexpr int KS = TRSM_AX_KS, LDK = trsm_ax_ldk<GQ>(), NT = BT_THREADS;
+    extern __shared__ __attribute__((aligned(16))) double sm3[];
     __shared__ int32_t Js[BS_LMAX];
     const int p = blockIdx.x;
     const BProb pr = a.prob[p];
@@ -574,12 +574,14 @@ __global__ __launch_bounds__(BT_THREADS) void batched_trsm_kernel(BatchArgs a) {
     copy_batched<8>(
         keff * LDK, NT,
         [&](int e) {
-            const int r = e / LDK, c = e % LDK;
-            return Rt[(int64_t)Js[r] * k + min(c, k - 1)];
+            int r, c;
+            trsm_ax_slot<GQ>(e, r, c);
+            return Rt[(int64_t)Js[r] * k + min(max(c, 0), k - 1)];
         },
         [&](int e, double v) {
-            const int r = e / LDK, c = e % LDK;
-            R11T[e] = (c < r) ? v : 0.0;
+            int r, c;
+            trsm_ax_slot<GQ>(e, r, c);
+            R11T[e] = (c >= 0 && c < r) ? v : 0.0;
         });
     copy_batched<1>(keff, NT, [&](int r) { return bt[r]; }, [&](int r, double v) { rd[r] = 1.0 / v; });
     __syncthreads();
@@ -719,7 +721,7 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
     {
         ProfScope ps(PK_TRSM, st);
         const int gq = k <= 32 ? 1 : (k <= 64 ? 2 : 4);
-        const size_t lds = sizeof(double) * (size_t)k * (gq * TRSM_AX_KS + 1);
+        const size_t lds = sizeof(double) * (size_t)k * (gq * TRSM_AX_SQ + 1);
         if (gq == 1)
             hipLaunchKernelGGL(batched_trsm_kernel<1>, dim3((unsigned)nprob), dim3(BT_THREADS), lds, st, a);
         else if (gq == 2)

@@ -962,8 +962,8 @@ __global__ __launch_bounds__(256) void trsm_axpy_kernel(int64_t n, int64_t k, co
                                                         const double* __restrict__ R11c,
                                                         const int32_t* __restrict__ pos,
                                                         const int64_t* __restrict__ keffp, double* P) {
-    constexpr int KS = TRSM_AX_KS, LDK = GQ * KS;
-    extern __shared__ double sm[];
+    constexpr int KS = TRSM_AX_KS, LDK = trsm_ax_ldk<GQ>();
+    extern __shared__ __attribute__((aligned(16))) double sm[];
     const int64_t keff64 = *keffp;
     if (keff64 < 0) return;
     const int keff = (int)keff64;
@@ -973,12 +973,14 @@ __global__ __launch_bounds__(256) void trsm_axpy_kernel(int64_t n, int64_t k, co
     copy_batched<16>(
         keff * LDK, 256,
         [&](int e) {
-            const int r = e / LDK, c = e % LDK;
-            return R11c[(int64_t)r * k + min(c, (int)k - 1)];
+            int r, c;
+            trsm_ax_slot<GQ>(e, r, c);
+            return R11c[(int64_t)r * k + min(max(c, 0), (int)k - 1)];
         },
         [&](int e, double v) {
-            const int r = e / LDK, c = e % LDK;
-            R11T[e] = (c < r) ? v : 0.0;
+            int r, c;
+            trsm_ax_slot<GQ>(e, r, c);
+            R11T[e] = (c >= 0 && c < r) ? v : 0.0;
         });
     copy_batched<1>(
         keff, 256, [&](int r) { return R11c[(int64_t)r * k + r]; }, [&](int r, double v) { rd[r] = 1.0 / v; });
@@ -1183,7 +1185,7 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
     const unsigned g16 = (unsigned)((sp.n + 15) / 16);
 #define IDS_TRSM_AXPY(GQ)                                                                                          \
     hipLaunchKernelGGL((trsm_axpy_kernel<GQ>), dim3((unsigned)((sp.n + 256 / GQ - 1) / (256 / GQ))), dim3(256),     \
-                       sizeof(double) * (size_t)sp.k * (GQ * TRSM_AX_KS + 1), st, sp.n, sp.k, Rt, R11c, pos,       \
+                       sizeof(double) * (size_t)sp.k * (trsm_ax_ldk<GQ>() + 1), st, sp.n, sp.k, Rt, R11c, pos,     \
                        (const int64_t*)keff, P)
 #define IDS_TRSM_GROUP(KS)                                                                                         \
     do {                                                                                                           \
@@ -1194,7 +1196,7 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
             hipLaunchKernelGGL((trsm_group_kernel<KS, false>), dim3(g16), dim3(256), 0, st, sp.n, sp.k, Rt,        \
                                R11c, pos, (const int64_t*)keff, P);                                   \
     } while (0)
-    const size_t ax = sizeof(double) * (size_t)sp.k * (4 * TRSM_AX_KS + 1);
+    const size_t ax = sizeof(double) * (size_t)sp.k * (trsm_ax_ldk<4>() + 1);
     if (sp.k <= 32)
         IDS_TRSM_AXPY(1);
     else if (sp.k <= 64)

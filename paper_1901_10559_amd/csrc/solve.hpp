@@ -7,14 +7,30 @@
 // (reciprocal staged in LDS), x_r reaches the GQ lanes of the column by a DPP
 // quad permutation, and every row c < r takes b_c -= R11[c][r] x_r with
 // independent FMAs; the serial chain per step is one multiply, one lane
-// exchange and one FMA.  R11 is staged transposed (row r = column r of R11,
-// zero on and below the diagonal and in the padding up to GQ * TRSM_AX_KS).
+// exchange and one FMA.  R11 is staged transposed: row r holds column r of
+// R11, as GQ lane segments of TRSM_AX_SQ doubles (segment q, slot s =
+// R11[GQ s + q][r], zero on and below the diagonal and past the slots), so a
+// lane reads its slots two at a time; the two padding slots put the GQ
+// segments of a row in different LDS banks.
 #pragma once
 #include "common.hpp"
 
 namespace ids {
 
 constexpr int TRSM_AX_KS = 32;
+constexpr int TRSM_AX_SQ = TRSM_AX_KS + 2;
+// doubles per staged row of R11 for GQ lanes per column
+template <int GQ>
+constexpr int trsm_ax_ldk() { return GQ * TRSM_AX_SQ; }
+// staged value of element e of the transposed R11 (row r = e / LDK): the
+// entry's (row of R11, column of R11), or c = -1 for a zero
+template <int GQ>
+__device__ __forceinline__ void trsm_ax_slot(int e, int& r, int& c) {
+    constexpr int LDK = trsm_ax_ldk<GQ>();
+    r = e / LDK;
+    const int rem = e - r * LDK, q = rem / TRSM_AX_SQ, sl = rem - q * TRSM_AX_SQ;
+    c = (sl < TRSM_AX_KS) ? GQ * sl + q : -1;
+}
 
 template <int GQ>
 __device__ __forceinline__ double quad_bcast(double v, int qo) {
@@ -29,24 +45,30 @@ __device__ __forceinline__ double quad_bcast(double v, int qo) {
 }
 
 // b (this lane's rows of the right-hand side) -> x in place.  R11T: keff rows
-// of GQ * TRSM_AX_KS doubles; rd: keff reciprocal diagonals.  The GQ lanes of a
-// column must be active together.
+// of trsm_ax_ldk<GQ>() doubles (16-byte aligned); rd: keff reciprocal
+// diagonals.  The GQ lanes of a column must be active together.
 template <int GQ>
 __device__ __forceinline__ void axpy_solve(double (&b)[TRSM_AX_KS], const double* R11T, const double* rd, int keff,
                                            int q) {
-    constexpr int KS = TRSM_AX_KS, LDK = GQ * KS;
-    // slot so of the owner is a compile-time index: the outer loop is unrolled
+    constexpr int KS = TRSM_AX_KS, SQ = TRSM_AX_SQ, LDK = trsm_ax_ldk<GQ>();
+    // slot so and owner qo are compile-time indices: both loops are unrolled
 #pragma unroll
     for (int so = KS - 1; so >= 0; --so) {
         if (GQ * so >= keff) continue;
+#pragma unroll
         for (int qo = GQ - 1; qo >= 0; --qo) {
             const int r = GQ * so + qo;
             if (r >= keff) continue;
             const double xr = quad_bcast<GQ>(b[so] * rd[r], qo);
-            const double* row = R11T + r * LDK + q;
+            const double* row = R11T + r * LDK + q * SQ;
 #pragma unroll
-            for (int sl = 0; sl < so; ++sl) b[sl] = fma(-row[GQ * sl], xr, b[sl]);
-            b[so] = (q == qo) ? xr : fma(-row[GQ * so], xr, b[so]);
+            for (int sl = 0; sl + 1 < so; sl += 2) {
+                const double2 v = *reinterpret_cast<const double2*>(row + sl);
+                b[sl] = fma(-v.x, xr, b[sl]);
+                b[sl + 1] = fma(-v.y, xr, b[sl + 1]);
+            }
+            if (so & 1) b[so - 1] = fma(-row[so - 1], xr, b[so - 1]);
+            b[so] = (q == qo) ? xr : fma(-row[so], xr, b[so]);
         }
     }
 }
