@@ -233,30 +233,39 @@ __device__ __forceinline__ void vote_hdr(const SelArgs& a, const double* reg, in
     wave_argmax_lo<NW>(wnu, wj);
 }
 
-// Vote and winner column in one wave (speculative slots, nh <= 64 headers):
-// lane q polls header q; every poll round also (re)loads the rows of the
-// column of the best candidate seen so far, so when the last header arrives
+// Vote and winner column in one wave (speculative slots, nh <= 64 HPL headers):
+// lane q polls headers q + 64 h (h < HPL); every poll round also (re)loads
+// the rows of the column of the best candidate seen so far, so when the last header arrives
 // the winner's column is usually complete already (one round trip instead of
 // two after the last publication).  Lane holds rows lane + 64 u, u < U.
 // Returns with the winner in (wnu, wj) and its rows in xv (0 past l), all
 // lanes agreeing; on timeout the flag is raised and the values may be NaN.
-template <int U>
+template <int U, int HPL>
 __device__ __forceinline__ void vote_prefetch(const SelArgs& a, const double* reg, const double* slots,
                                               int cols_per_blk, int l, double& wnu, int& wj, uint64_t (&xv)[U]) {
     const int lane = threadIdx.x & 63;
-    const bool mine = lane < a.nh;
-    const double* hd = reg + 2 * (mine ? lane : 0);
-    uint64_t hn = 0, hj = 0;
-    bool have = !mine;
+    bool mine[HPL], have[HPL];
+    const double* hd[HPL];
+    uint64_t hn[HPL], hj[HPL];
+#pragma unroll
+    for (int h = 0; h < HPL; ++h) {
+        const int q = lane + 64 * h;  // headers q = lane + 64 h of this lane
+        mine[h] = q < a.nh;
+        hd[h] = reg + 2 * (mine[h] ? q : 0);
+        have[h] = !mine[h];
+        hn[h] = hj[h] = 0;
+    }
     int cand = -1;
 #pragma unroll
     for (int u = 0; u < U; ++u) xv[u] = MB_SENT;
     for (uint32_t spin = 0;; ++spin) {
         if (spin) __builtin_amdgcn_s_sleep(1);  // about 64 clocks between polls
-        if (!have) {
-            hn = mb_load(hd);
-            hj = mb_load(hd + 1);
-        }
+#pragma unroll
+        for (int h = 0; h < HPL; ++h)
+            if (!have[h]) {
+                hn[h] = mb_load(hd[h]);
+                hj[h] = mb_load(hd[h] + 1);
+            }
         if (cand >= 0) {
             const double* col = slots + (size_t)(cand / cols_per_blk) * a.S;
 #pragma unroll
@@ -265,16 +274,23 @@ __device__ __forceinline__ void vote_prefetch(const SelArgs& a, const double* re
                 if (xv[u] == MB_SENT) xv[u] = (i < l) ? mb_load(col + i) : 0ull;
             }
         }
-        if (!have) have = (hn != MB_SENT) && (hj != MB_SENT);
+        bool missing = false;
+#pragma unroll
+        for (int h = 0; h < HPL; ++h) {
+            if (!have[h]) have[h] = (hn[h] != MB_SENT) && (hj[h] != MB_SENT);
+            missing = missing || !have[h];
+        }
         bool col_pend = false;
 #pragma unroll
         for (int u = 0; u < U; ++u) col_pend = col_pend || (xv[u] == MB_SENT);
         const bool col_ok = cand >= 0 && !__any(col_pend);
         double bn = -1.0;
         int bj = INT32_MAX;
-        if (mine && have) take(hn, hj, bn, bj);
+#pragma unroll
+        for (int h = 0; h < HPL; ++h)
+            if (mine[h] && have[h]) take(hn[h], hj[h], bn, bj);
         wave_argmax(bn, bj);
-        const bool all = !__any(!have);
+        const bool all = !__any(missing);
         if (all && (bj == INT32_MAX || (bj == cand && col_ok))) {
             wnu = bn;
             wj = bj;
@@ -442,7 +458,7 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
             mb_put(hd, bn);
             mb_put(hd + 1, idx_bits(bj == INT32_MAX ? -1 : bj));
         }
-        const bool one_wave_vote = MODE == MB_SPEC && a.nh <= 64;  // uniform
+        const bool one_wave_vote = MODE == MB_SPEC && a.nh <= 256;  // uniform
         if (MODE == MB_SPEC && j == bj) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
@@ -458,7 +474,10 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
                 uint64_t xv[UP];
                 double vn;
                 int vj;
-                vote_prefetch<UP>(a, reg, slots, NW * CPWV, l, vn, vj, xv);
+                if (a.nh <= 64)
+                    vote_prefetch<UP, 1>(a, reg, slots, NW * CPWV, l, vn, vj, xv);
+                else
+                    vote_prefetch<UP, 4>(a, reg, slots, NW * CPWV, l, vn, vj, xv);
 #pragma unroll
                 for (int u = 0; u < UP; ++u) {
                     const int i = lane + 64 * u;
