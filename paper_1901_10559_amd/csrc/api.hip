@@ -495,16 +495,17 @@ ids_status id_batched(int64_t nprob, const int64_t* m, const int64_t* n, const v
     if (s) return s;
     if (!(tol >= 0.0 && tol < 1.0)) return fail(IDS_EINVAL, "tol must be in [0, 1)");
     if (!plan || !A || !G || !J || !P || !k_eff) return fail(IDS_EINVAL, "plan, A, G, J, P and k_eff required");
-    int64_t y_elems = 0, r_elems = 0;
+    int64_t a_elems = 0, y_elems = 0, r_elems = 0;
     for (int64_t q = 0; q < nprob; ++q) {
+        a_elems += m[q] * n[q];
         y_elems += l * n[q];
         r_elems += n[q];
     }
     const size_t need = align256(sizeof(float) * (size_t)y_elems) + align256(sizeof(double) * (size_t)r_elems * k) +
                         align256(sizeof(int32_t) * (size_t)r_elems) + align256(sizeof(double) * (size_t)nprob * k);
     if ((s = check_ws(ws, ws_bytes, need))) return s;
-    return batched_run(nprob, plan, k, l, l1max, seed, tol, A, G, J, P, k_eff, ws, ws_bytes, y_elems, r_elems,
-                       (hipStream_t)stream);
+    return batched_run(nprob, plan, k, l, l1max, seed, tol, A, G, J, P, k_eff, ws, ws_bytes, a_elems, y_elems,
+                       r_elems, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -69,6 +69,8 @@ struct BatchArgs {
     uint64_t seed;
     double tol2;        // fixed-accuracy stop: |r_tt|^2 <= tol2 |r_11|^2 (0: fixed rank k)
     const uint16_t* A;
+    int64_t a_elems;    // elements of A (all problems)
+    int32_t a_al16;     // A is 16-byte aligned
     const uint16_t* G;  // l x l1max BF16
     int32_t g_vec;      // G rows 16-byte aligned (l1max % 8 == 0, G aligned)
     float* Y;
@@ -217,7 +219,10 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
             // added in increasing row order
             {
                 const int cc = c0 + 8 * ch;
-                const bool full = cc + 8 <= n && (n % 8) == 0 && (pr.a_off % 8) == 0;
+                // rows 16-byte aligned (n % 8 == 0 and A_p aligned): one load per
+                // chunk; otherwise a chunk spans two aligned 16-byte blocks and
+                // is shifted out of them (uniform per problem)
+                const bool vec = a.a_al16 && (n % 8) == 0 && (pr.a_off % 8) == 0;
                 int qb[2], qn[2];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
@@ -231,39 +236,86 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
                     for (int e = 0; e < 8; ++e) s[h][e] = 0.f;
-                for (int q0 = 0; q0 < max(qn[0], qn[1]); q0 += BS_RIF) {
-                    uint32_t raw[2][BS_RIF][4];
-                    int32_t code[2][BS_RIF];
+                // one chunk (8 BF16 in 4 words) into the bucket sums
+                auto add = [&](int h, int32_t code, const uint32_t (&w4)[4]) {
 #pragma unroll
-                    for (int h = 0; h < 2; ++h)
+                    for (int e = 0; e < 8; ++e) {
+                        const float xe = (cc + e < n) ? bf16_to_f32((uint16_t)(w4[e >> 1] >> (16 * (e & 1)))) : 0.f;
+                        s[h][e] = code < 0 ? s[h][e] - xe : s[h][e] + xe;
+                    }
+                };
+                if (vec) {
+                    for (int q0 = 0; q0 < max(qn[0], qn[1]); q0 += BS_RIF) {
+                        uint32_t raw[2][BS_RIF][4];
+                        int32_t code[2][BS_RIF];
+                        // all loads issued before any is used (a slot past its
+                        // bucket's rows loads row 0 and is skipped)
 #pragma unroll
-                        for (int u = 0; u < BS_RIF; ++u) {
-                            const bool in = q0 + u < qn[h];
-                            code[h][u] = in ? rows[qb[h] + q0 + u] : 0;
-                            const int64_t i = code[h][u] >= 0 ? code[h][u] : -(int64_t)code[h][u] - 1;
-                            const uint16_t* rowp = Ap + i * n + cc;
-                            if (in && full) {
-                                const uint4 v = load_nt16(rowp);
+                        for (int h = 0; h < 2; ++h)
+#pragma unroll
+                            for (int u = 0; u < BS_RIF; ++u) {
+                                code[h][u] = (q0 + u < qn[h]) ? rows[qb[h] + q0 + u] : 0;
+                                const int64_t i = code[h][u] >= 0 ? code[h][u] : -(int64_t)code[h][u] - 1;
+                                const uint4 v = load_nt16(Ap + i * n + (cc < n ? cc : 0));
                                 raw[h][u][0] = v.x; raw[h][u][1] = v.y; raw[h][u][2] = v.z; raw[h][u][3] = v.w;
+                            }
+                        asm volatile("" ::: "memory");
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+#pragma unroll
+                            for (int u = 0; u < BS_RIF; ++u) {
+                                if (q0 + u >= qn[h]) break;
+                                add(h, code[h][u], raw[h][u]);
+                            }
+                    }
+                } else {
+                    for (int q0 = 0; q0 < max(qn[0], qn[1]); ++q0) {
+                        uint32_t w[2][8];
+                        int32_t code[2];
+                        int sh[2];
+                        bool tail[2];
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            code[h] = (q0 < qn[h]) ? rows[qb[h] + q0] : 0;
+                            const int64_t i = code[h] >= 0 ? code[h] : -(int64_t)code[h] - 1;
+                            const int64_t e0 = pr.a_off + i * n + (cc < n ? cc : 0);  // element index in A
+                            int64_t base = e0 & ~(int64_t)7;
+                            // element loads where the second block would pass the end of
+                            // A (or A itself is not 16-byte aligned)
+                            tail[h] = !a.a_al16 || base + 16 > a.a_elems;
+                            if (tail[h]) base = 0;
+                            sh[h] = (int)(e0 - (e0 & ~(int64_t)7));
+                            const uint4 b0 = load_nt16(a.A + base), b1 = load_nt16(a.A + base + 8);
+                            w[h][0] = b0.x; w[h][1] = b0.y; w[h][2] = b0.z; w[h][3] = b0.w;
+                            w[h][4] = b1.x; w[h][5] = b1.y; w[h][6] = b1.z; w[h][7] = b1.w;
+                        }
+                        asm volatile("" ::: "memory");
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            if (q0 >= qn[h]) continue;
+                            uint32_t w4[4];
+                            if (!tail[h]) {
+                                // elements sh .. sh + 7 of the 16 loaded: words d .. d + 4
+                                // (d = sh / 2), shifted by one element when sh is odd
+                                const int d = sh[h] >> 1;
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) {
+                                    const uint32_t lo = (d == 0) ? w[h][q] : (d == 1) ? w[h][q + 1] : (d == 2) ? w[h][q + 2] : w[h][q + 3];
+                                    const uint32_t hi = (d == 0) ? w[h][q + 1] : (d == 1) ? w[h][q + 2] : (d == 2) ? w[h][q + 3] : w[h][q + 4];
+                                    w4[q] = (sh[h] & 1) ? __builtin_amdgcn_alignbyte(hi, lo, 2) : lo;
+                                }
                             } else {
+                                const int64_t i = code[h] >= 0 ? code[h] : -(int64_t)code[h] - 1;
+                                const uint16_t* rowp = Ap + i * n + cc;
                                 uint32_t hh[8];
 #pragma unroll
-                                for (int e = 0; e < 8; ++e) hh[e] = (in && cc + e < n) ? rowp[e] : 0u;
+                                for (int e = 0; e < 8; ++e) hh[e] = (cc + e < n) ? rowp[e] : 0u;
 #pragma unroll
-                                for (int e = 0; e < 4; ++e) raw[h][u][e] = hh[2 * e] | (hh[2 * e + 1] << 16);
+                                for (int e = 0; e < 4; ++e) w4[e] = hh[2 * e] | (hh[2 * e + 1] << 16);
                             }
+                            add(h, code[h], w4);
                         }
-#pragma unroll
-                    for (int h = 0; h < 2; ++h)
-#pragma unroll
-                        for (int u = 0; u < BS_RIF; ++u) {
-                            if (q0 + u >= qn[h]) break;
-#pragma unroll
-                            for (int e = 0; e < 8; ++e) {
-                                const float xe = bf16_to_f32((uint16_t)(raw[h][u][e >> 1] >> (16 * (e & 1))));
-                                s[h][e] = code[h][u] < 0 ? s[h][e] - xe : s[h][e] + xe;
-                            }
-                        }
+                    }
                 }
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
@@ -677,7 +729,7 @@ ids_status batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, int64
 
 ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, int64_t l1max, uint64_t seed,
                        double tol, const void* A, const void* G, int64_t* J, double* P, int64_t* keff, void* ws,
-                       size_t ws_bytes, int64_t y_elems, int64_t r_elems, hipStream_t st) {
+                       size_t ws_bytes, int64_t a_elems, int64_t y_elems, int64_t r_elems, hipStream_t st) {
     size_t op, o1, o2;
     plan_layout(nprob, &op, &o1, &o2);
     BatchArgs a;
@@ -689,6 +741,8 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
     a.seed = seed;
     a.tol2 = tol * tol;
     a.A = (const uint16_t*)A;
+    a.a_elems = a_elems;
+    a.a_al16 = ((uintptr_t)A & 15) == 0;
     a.G = (const uint16_t*)G;
     a.g_vec = (l1max % 8 == 0) && (((uintptr_t)G & 15) == 0);
     char* p = (char*)ws;

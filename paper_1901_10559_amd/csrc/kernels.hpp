@@ -85,7 +85,7 @@ ids_status batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, int64
                         void* plan, size_t plan_bytes, size_t* ws_bytes, hipStream_t st);
 ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, int64_t l1max, uint64_t seed,
                        double tol, const void* A, const void* G, int64_t* J, double* P, int64_t* keff, void* ws,
-                       size_t ws_bytes, int64_t y_elems, int64_t r_elems, hipStream_t st);
+                       size_t ws_bytes, int64_t a_elems, int64_t y_elems, int64_t r_elems, hipStream_t st);
 
 // ---- TensorSketch -------------------------------------------------------------
 ids_status tensorsketch(int32_t N, const int64_t* dims, int64_t R, const double* const* factors,
