@@ -75,6 +75,36 @@ def test_batched_id_residual_within_2x_of_oracle(ms, ns, k, l, l1max):
         assert rg <= 2.0 * ro, (p, rg, ro)
 
 
+def test_batched_sketch_unaligned_A_base():
+    # A starting 2 bytes past a 16-byte boundary: every chunk takes the element
+    # loads; odd n also exercises rows that straddle 16-byte blocks
+    ms, ns, k, l, l1max = [300, 129, 77], [77, 200, 33], 20, 40, 128
+    As, At = make_batch(ms, ns, 0)
+    buf = torch.zeros(At.numel() + 8, dtype=torch.bfloat16, device=DEV)
+    buf[1:1 + At.numel()] = At
+    Au = buf[1:1 + At.numel()]
+    assert Au.data_ptr() % 16 == 2
+    Gb = synth.bf16_bits(synth.gaussian(l, l1max, 0))
+    G64 = synth.bf16_to_f64(Gb)
+    Gt = torch.from_numpy(Gb.view(np.int16)).to(DEV).view(torch.bfloat16)
+    plan = ids.batched_plan(ms, ns, k, l, l1max)
+    out = ids.id_batched(plan, Au, Gt, seed=0, return_Y=True)
+    ref = ids.id_batched(plan, At, Gt, seed=0, return_Y=True)
+    torch.cuda.synchronize()
+    Y = out["Y"].cpu().numpy()
+    # same sums in the same order whatever the load path: bit-identical
+    assert np.array_equal(Y, ref["Y"].cpu().numpy())
+    for p, (A, m, n) in enumerate(zip(As, ms, ns)):
+        A64 = synth.bf16_to_f64(A).reshape(m, n)
+        l1 = min(m, l1max)
+        b, s = oracle.hash_maps(0, p, m, l1)
+        Yo = oracle.gemm(G64[:, :l1], oracle.countsketch_dense(A64, b, s, l1))
+        Yg = Y[plan.y_off[p]:plan.y_off[p + 1]].reshape(n, l).T
+        absY1 = oracle.countsketch_dense(np.abs(A64), b, np.ones_like(s), l1)
+        bound = 4 * (2.0 ** -16 + l1 * 2.0 ** -24) * (np.abs(G64[:, :l1]) @ absY1)
+        assert np.all(np.abs(Yg - Yo) <= bound + 1e-30), p
+
+
 def test_batched_rejects_out_of_range():
     with pytest.raises(ids.IdsError):
         ids.batched_plan([5000], [300], 111, 121, 496)        # m > 4096
