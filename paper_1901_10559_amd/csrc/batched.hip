@@ -97,7 +97,8 @@ constexpr int BS_YN = BS_PANEL * BS_YS + (BS_PANEL / 8) * 8;
 constexpr int BS_LMAX = 128;    // padded sketch height (l <= 128)
 constexpr int BS_MMAX = 4096;   // rows per problem
 constexpr int BS_L1MAX = 512;   // buckets per problem
-constexpr int BS_RIF = 2;       // rows in flight per bucket and gather thread (two buckets)
+constexpr int BS_IIF = 4;       // row loads in flight per gather thread (aligned rows)
+static_assert(BS_THREADS / 64 >= BS_L1MAX / BS_BG, "one wave per bucket group sorts its bucket sizes");
 
 __device__ __forceinline__ uint16_t f2bf_rne(float f) {
     uint32_t u = __float_as_uint(f);
@@ -114,6 +115,9 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
     __shared__ __attribute__((aligned(16))) uint16_t Y1h[BS_YN];
     __shared__ __attribute__((aligned(16))) uint16_t Y1l[BS_YN];
     __shared__ __attribute__((aligned(16))) uint16_t Gs[BS_LMAX][BS_YS];
+    // per bucket group: slot s < 32 -> the s-th largest bucket, slot 32 + s ->
+    // the s-th smallest (positions within the group)
+    __shared__ uint8_t pairing[BS_L1MAX];
 
     const int p = a.order[blockIdx.x];
     const BProb pr = a.prob[p];
@@ -176,6 +180,25 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
             rows[r + 1] = c;
         }
     }
+    // gather balance: a gather thread sums two buckets of a 64-bucket group,
+    // the s-th largest with the s-th smallest, so each thread reads close to
+    // the group's mean of 2 m / L1 rows instead of the largest bucket's count
+    // (one wave per group: bitonic sort of (count, position) keys)
+    {
+        const int wv = tid >> 6, ln = tid & 63, g0 = wv * BS_BG;
+        if (g0 < L1) {
+            const int b = g0 + ln;
+            uint32_t key = ((uint32_t)(b < L1 ? off[b + 1] - off[b] : 0) << 6) | (uint32_t)ln;
+#pragma unroll
+            for (int k2 = 2; k2 <= 64; k2 <<= 1)
+#pragma unroll
+                for (int j = k2 >> 1; j > 0; j >>= 1) {
+                    const uint32_t o = (uint32_t)__shfl_xor((int)key, j, 64);
+                    key = (((ln & j) == 0) == ((ln & k2) == 0)) ? min(key, o) : max(key, o);
+                }
+            pairing[g0 + (ln >= 32 ? 63 - ln : 32 + ln)] = (uint8_t)(key & 63);
+        }
+    }
     __syncthreads();
 
     const int w = tid >> 6, lane = tid & 63;
@@ -214,8 +237,9 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
                 }
                 gvals[u] = v;
             }
-            // gather: Y1[b][c0 + 8ch .. +8] for the two buckets b = g0 + bl and
-            // g0 + 32 + bl; BS_RIF rows of each in flight, each bucket's rows
+            // gather: Y1[b][c0 + 8ch .. +8] for the two buckets b = g0 + pb[h]
+            // paired for this thread's slot bl; the thread walks one stream of
+            // qn[0] + qn[1] rows (bucket 0's, then bucket 1's), each bucket's rows
             // added in increasing row order
             {
                 const int cc = c0 + 8 * ch;
@@ -223,89 +247,98 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
                 // chunk; otherwise a chunk spans two aligned 16-byte blocks and
                 // is shifted out of them (uniform per problem)
                 const bool vec = a.a_al16 && (n % 8) == 0 && (pr.a_off % 8) == 0;
-                int qb[2], qn[2];
+                int qb[2], qn[2], pb[2];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    const int b = g0 + 32 * h + bl;
+                    pb[h] = pairing[g0 + 32 * h + bl];
+                    const int b = g0 + pb[h];
                     const bool ok = b < L1 && cc < n;
                     qb[h] = ok ? off[b] : 0;
                     qn[h] = ok ? off[b + 1] - off[b] : 0;
                 }
+                const int nq = qn[0] + qn[1];
                 float s[2][8];
 #pragma unroll
                 for (int h = 0; h < 2; ++h)
 #pragma unroll
                     for (int e = 0; e < 8; ++e) s[h][e] = 0.f;
-                // one chunk (8 BF16 in 4 words) into the bucket sums
+                // item q of the stream: its bucket slot h and row code (past the
+                // stream: row 0, not added)
+                auto item = [&](int q, int& h, int32_t& code) {
+                    h = q >= qn[0] ? 1 : 0;
+                    const int r = (q < nq) ? (h ? qb[1] + q - qn[0] : qb[0] + q) : 0;
+                    code = rows[r];
+                    code = (q < nq) ? code : 0;
+                };
+                // one chunk (8 BF16 in 4 words) into the sum of bucket slot h
                 auto add = [&](int h, int32_t code, const uint32_t (&w4)[4]) {
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
                         const float xe = (cc + e < n) ? bf16_to_f32((uint16_t)(w4[e >> 1] >> (16 * (e & 1)))) : 0.f;
-                        s[h][e] = code < 0 ? s[h][e] - xe : s[h][e] + xe;
+                        const float v = h ? s[1][e] : s[0][e];
+                        const float t = code < 0 ? v - xe : v + xe;
+                        s[0][e] = h ? s[0][e] : t;
+                        s[1][e] = h ? t : s[1][e];
                     }
                 };
                 if (vec) {
-                    for (int q0 = 0; q0 < max(qn[0], qn[1]); q0 += BS_RIF) {
-                        uint32_t raw[2][BS_RIF][4];
-                        int32_t code[2][BS_RIF];
-                        // all loads issued before any is used (a slot past its
-                        // bucket's rows loads row 0 and is skipped)
+                    for (int q0 = 0; q0 < nq; q0 += BS_IIF) {
+                        uint32_t raw[BS_IIF][4];
+                        int32_t code[BS_IIF];
+                        int hs[BS_IIF];
+                        // all loads issued before any is used
 #pragma unroll
-                        for (int h = 0; h < 2; ++h)
-#pragma unroll
-                            for (int u = 0; u < BS_RIF; ++u) {
-                                code[h][u] = (q0 + u < qn[h]) ? rows[qb[h] + q0 + u] : 0;
-                                const int64_t i = code[h][u] >= 0 ? code[h][u] : -(int64_t)code[h][u] - 1;
-                                const uint4 v = load_nt16(Ap + i * n + (cc < n ? cc : 0));
-                                raw[h][u][0] = v.x; raw[h][u][1] = v.y; raw[h][u][2] = v.z; raw[h][u][3] = v.w;
-                            }
-                        asm volatile("" ::: "memory");
-#pragma unroll
-                        for (int h = 0; h < 2; ++h)
-#pragma unroll
-                            for (int u = 0; u < BS_RIF; ++u) {
-                                if (q0 + u >= qn[h]) break;
-                                add(h, code[h][u], raw[h][u]);
-                            }
-                    }
-                } else {
-                    for (int q0 = 0; q0 < max(qn[0], qn[1]); ++q0) {
-                        uint32_t w[2][8];
-                        int32_t code[2];
-                        int sh[2];
-                        bool tail[2];
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            code[h] = (q0 < qn[h]) ? rows[qb[h] + q0] : 0;
-                            const int64_t i = code[h] >= 0 ? code[h] : -(int64_t)code[h] - 1;
-                            const int64_t e0 = pr.a_off + i * n + (cc < n ? cc : 0);  // element index in A
-                            int64_t base = e0 & ~(int64_t)7;
-                            // element loads where the second block would pass the end of
-                            // A (or A itself is not 16-byte aligned)
-                            tail[h] = !a.a_al16 || base + 16 > a.a_elems;
-                            if (tail[h]) base = 0;
-                            sh[h] = (int)(e0 - (e0 & ~(int64_t)7));
-                            const uint4 b0 = load_nt16(a.A + base), b1 = load_nt16(a.A + base + 8);
-                            w[h][0] = b0.x; w[h][1] = b0.y; w[h][2] = b0.z; w[h][3] = b0.w;
-                            w[h][4] = b1.x; w[h][5] = b1.y; w[h][6] = b1.z; w[h][7] = b1.w;
+                        for (int u = 0; u < BS_IIF; ++u) {
+                            item(q0 + u, hs[u], code[u]);
+                            const int64_t i = code[u] >= 0 ? code[u] : -(int64_t)code[u] - 1;
+                            const uint4 v = load_nt16(Ap + i * n + cc);
+                            raw[u][0] = v.x; raw[u][1] = v.y; raw[u][2] = v.z; raw[u][3] = v.w;
                         }
                         asm volatile("" ::: "memory");
 #pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            if (q0 >= qn[h]) continue;
+                        for (int u = 0; u < BS_IIF; ++u) {
+                            if (q0 + u >= nq) break;
+                            add(hs[u], code[u], raw[u]);
+                        }
+                    }
+                } else {
+                    for (int q0 = 0; q0 < nq; q0 += 2) {
+                        uint32_t w[2][8];
+                        int32_t code[2];
+                        int hs[2], sh[2];
+                        bool tail[2];
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            item(q0 + u, hs[u], code[u]);
+                            const int64_t i = code[u] >= 0 ? code[u] : -(int64_t)code[u] - 1;
+                            const int64_t e0 = pr.a_off + i * n + cc;  // element index in A
+                            int64_t base = e0 & ~(int64_t)7;
+                            // element loads where the second block would pass the end of
+                            // A (or A itself is not 16-byte aligned)
+                            tail[u] = !a.a_al16 || base + 16 > a.a_elems;
+                            if (tail[u]) base = 0;
+                            sh[u] = (int)(e0 - (e0 & ~(int64_t)7));
+                            const uint4 b0 = load_nt16(a.A + base), b1 = load_nt16(a.A + base + 8);
+                            w[u][0] = b0.x; w[u][1] = b0.y; w[u][2] = b0.z; w[u][3] = b0.w;
+                            w[u][4] = b1.x; w[u][5] = b1.y; w[u][6] = b1.z; w[u][7] = b1.w;
+                        }
+                        asm volatile("" ::: "memory");
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            if (q0 + u >= nq) continue;
                             uint32_t w4[4];
-                            if (!tail[h]) {
+                            if (!tail[u]) {
                                 // elements sh .. sh + 7 of the 16 loaded: words d .. d + 4
                                 // (d = sh / 2), shifted by one element when sh is odd
-                                const int d = sh[h] >> 1;
+                                const int d = sh[u] >> 1;
 #pragma unroll
                                 for (int q = 0; q < 4; ++q) {
-                                    const uint32_t lo = (d == 0) ? w[h][q] : (d == 1) ? w[h][q + 1] : (d == 2) ? w[h][q + 2] : w[h][q + 3];
-                                    const uint32_t hi = (d == 0) ? w[h][q + 1] : (d == 1) ? w[h][q + 2] : (d == 2) ? w[h][q + 3] : w[h][q + 4];
-                                    w4[q] = (sh[h] & 1) ? __builtin_amdgcn_alignbyte(hi, lo, 2) : lo;
+                                    const uint32_t lo = (d == 0) ? w[u][q] : (d == 1) ? w[u][q + 1] : (d == 2) ? w[u][q + 2] : w[u][q + 3];
+                                    const uint32_t hi = (d == 0) ? w[u][q + 1] : (d == 1) ? w[u][q + 2] : (d == 2) ? w[u][q + 3] : w[u][q + 4];
+                                    w4[q] = (sh[u] & 1) ? __builtin_amdgcn_alignbyte(hi, lo, 2) : lo;
                                 }
                             } else {
-                                const int64_t i = code[h] >= 0 ? code[h] : -(int64_t)code[h] - 1;
+                                const int64_t i = code[u] >= 0 ? code[u] : -(int64_t)code[u] - 1;
                                 const uint16_t* rowp = Ap + i * n + cc;
                                 uint32_t hh[8];
 #pragma unroll
@@ -313,7 +346,7 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
 #pragma unroll
                                 for (int e = 0; e < 4; ++e) w4[e] = hh[2 * e] | (hh[2 * e + 1] << 16);
                             }
-                            add(h, code[h], w4);
+                            add(hs[u], code[u], w4);
                         }
                     }
                 }
@@ -323,7 +356,7 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
                     for (int e = 0; e < 8; ++e) {
                         const uint16_t hi = f2bf_rne(s[h][e]);
                         const float hf = bf16_to_f32(hi);
-                        const int o = ys_off(8 * ch + e) + 32 * h + bl;
+                        const int o = ys_off(8 * ch + e) + pb[h];
                         Y1h[o] = hi;
                         Y1l[o] = f2bf_rne(s[h][e] - hf);
                     }
