@@ -270,15 +270,20 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
                     code = rows[r];
                     code = (q < nq) ? code : 0;
                 };
-                // one chunk (8 BF16 in 4 words) into the sum of bucket slot h
+                // one chunk (8 BF16 in 4 words) into the sum of bucket slot h:
+                // fma(g, x, s) with g = +-1 (the row's sign) in slot h and +0 in
+                // the other adds exactly s +- x and s + 0 (for finite x), two
+                // FMAs per element instead of a routed add.  Elements past column
+                // n - 1 only reach discarded columns of Y.
                 auto add = [&](int h, int32_t code, const uint32_t (&w4)[4]) {
+                    const float sg = code < 0 ? -1.f : 1.f;
+                    const float g0s = h ? 0.f : sg, g1s = h ? sg : 0.f;
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
-                        const float xe = (cc + e < n) ? bf16_to_f32((uint16_t)(w4[e >> 1] >> (16 * (e & 1)))) : 0.f;
-                        const float v = h ? s[1][e] : s[0][e];
-                        const float t = code < 0 ? v - xe : v + xe;
-                        s[0][e] = h ? s[0][e] : t;
-                        s[1][e] = h ? t : s[1][e];
+                        const uint32_t wd = w4[e >> 1];
+                        const float xe = __uint_as_float((e & 1) ? (wd & 0xffff0000u) : (wd << 16));
+                        s[0][e] = fmaf(g0s, xe, s[0][e]);
+                        s[1][e] = fmaf(g1s, xe, s[1][e]);
                     }
                 };
                 if (vec) {
@@ -330,13 +335,19 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
                             if (!tail[u]) {
                                 // elements sh .. sh + 7 of the 16 loaded: words d .. d + 4
                                 // (d = sh / 2), shifted by one element when sh is odd
+                                // (words picked by the two bits of d in turn, as bit
+                                // selects: a select of array elements would become an
+                                // indexed private array)
                                 const int d = sh[u] >> 1;
+                                const uint32_t m2 = 0u - (uint32_t)((d >> 1) & 1), m1 = 0u - (uint32_t)(d & 1);
+                                uint32_t u6[6], v5[5];
 #pragma unroll
-                                for (int q = 0; q < 4; ++q) {
-                                    const uint32_t lo = (d == 0) ? w[u][q] : (d == 1) ? w[u][q + 1] : (d == 2) ? w[u][q + 2] : w[u][q + 3];
-                                    const uint32_t hi = (d == 0) ? w[u][q + 1] : (d == 1) ? w[u][q + 2] : (d == 2) ? w[u][q + 3] : w[u][q + 4];
-                                    w4[q] = (sh[u] & 1) ? __builtin_amdgcn_alignbyte(hi, lo, 2) : lo;
-                                }
+                                for (int q = 0; q < 6; ++q) u6[q] = (w[u][q + 2] & m2) | (w[u][q] & ~m2);
+#pragma unroll
+                                for (int q = 0; q < 5; ++q) v5[q] = (u6[q + 1] & m1) | (u6[q] & ~m1);
+                                const uint32_t bs = (uint32_t)(sh[u] & 1) * 2u;
+#pragma unroll
+                                for (int q = 0; q < 4; ++q) w4[q] = __builtin_amdgcn_alignbyte(v5[q + 1], v5[q], bs);
                             } else {
                                 const int64_t i = code[u] >= 0 ? code[u] : -(int64_t)code[u] - 1;
                                 const uint16_t* rowp = Ap + i * n + cc;
