@@ -202,8 +202,12 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
     __syncthreads();
 
     const int w = tid >> 6, lane = tid & 63;
-    const int rt = w;               // row tile (16 rows of Y), 8 waves = 128 rows
-    const int ct0 = 0;              // 8 column tiles = the 128-column panel
+    // MFMA phase: wave w owns row tiles rt0 .. rt0 + 3 (16 rows of Y each) and
+    // column tiles ct0, ct0 + 1 (16 columns of the panel each): 4 G and 4 Y1
+    // operand reads per 32-bucket step instead of 1 and 16 for a 16 x 128
+    // strip, so half the LDS reads and operand registers
+    const int rt0 = 4 * (w >> 2);
+    const int ct0 = 2 * (w & 3);
     const int bl = tid >> 4;        // buckets bl and 32 + bl of the group (gather phase)
     const int ch = tid & 15;        // 8-column chunk within panel (gather phase)
     const uint16_t* Ap = a.A + pr.a_off;
@@ -381,27 +385,35 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
             // Y(rows rt*16.., cols ct*16..) += G tile (16 x 64) * Y1 (64 x 16), hi and lo
 #pragma unroll
             for (int kk = 0; kk < BS_BG / 32; ++kk) {
-                const v8bf16 av = __builtin_bit_cast(
-                    v8bf16, *reinterpret_cast<const uint4*>(&Gs[rt * 16 + (lane & 15)][32 * kk + 8 * (lane >> 4)]));
+                v8bf16 av[4], bh[2], blo[2];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int o = ys_off((ct0 + q) * 16 + (lane & 15)) + 32 * kk + 8 * (lane >> 4);
-                    const v8bf16 bh = __builtin_bit_cast(v8bf16, *reinterpret_cast<const uint4*>(&Y1h[o]));
-                    const v8bf16 blo = __builtin_bit_cast(v8bf16, *reinterpret_cast<const uint4*>(&Y1l[o]));
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bh, acc[q], 0, 0, 0);
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, blo, acc[q], 0, 0, 0);
+                for (int i = 0; i < 4; ++i)
+                    av[i] = __builtin_bit_cast(v8bf16, *reinterpret_cast<const uint4*>(
+                                                           &Gs[(rt0 + i) * 16 + (lane & 15)][32 * kk + 8 * (lane >> 4)]));
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int o = ys_off((ct0 + c) * 16 + (lane & 15)) + 32 * kk + 8 * (lane >> 4);
+                    bh[c] = __builtin_bit_cast(v8bf16, *reinterpret_cast<const uint4*>(&Y1h[o]));
+                    blo[c] = __builtin_bit_cast(v8bf16, *reinterpret_cast<const uint4*>(&Y1l[o]));
                 }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        acc[2 * i + c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bh[c], acc[2 * i + c], 0, 0, 0);
+                        acc[2 * i + c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], blo[c], acc[2 * i + c], 0, 0, 0);
+                    }
             }
             __syncthreads();
         }
         // write the panel of Y_p (column-major, leading dimension l)
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int col = c0 + (ct0 + q) * 16 + (lane & 15);
+            const int col = c0 + (ct0 + (q & 1)) * 16 + (lane & 15);
             if (col >= n) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = rt * 16 + 4 * (lane >> 4) + r;
+                const int row = (rt0 + (q >> 1)) * 16 + 4 * (lane >> 4) + r;
                 if (row < l) Yp[(int64_t)col * l + row] = acc[q][r];
             }
         }
