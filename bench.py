@@ -449,6 +449,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": "cs_dense_kernel<float,float,4>", "algorithmic_bytes": cs_bytes},
+        # the other half of the step: the pivoted QR, bound by the latency of
+        # its K sequential pivot steps (one device-wide exchange each), not by
+        # bytes or flops
+        "cpqr_latency": {"bound": "latency", "steps": K, "us_per_step": stages["cpqr"] * 1e3 / K,
+                         "share_of_step": stages["cpqr"] / ms_per_step, "kernel": "cpqr_gl_kernel<8,16,8,0>"},
         "cpu_baseline": None,
     }
 
