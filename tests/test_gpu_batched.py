@@ -36,6 +36,9 @@ def run_batch(ms, ns, k, l, l1max, seed=0):
     ([300, 700, 121, 4096, 1500, 497], [130, 1024, 640, 200, 333, 257], 111, 121, 496),
     ([64, 200, 90, 1000], [50, 77, 300, 1000], 20, 40, 128),
     ([150, 333, 2000], [90, 700, 129], 50, 60, 130),   # G rows not 16-byte aligned
+    # smallest shapes: n < 8, partial 64-bucket groups, a single bucket group
+    ([4, 5, 7, 9, 64, 65, 4096], [3, 5, 8, 9, 127, 129, 1024], 2, 4, 8),
+    ([12, 20, 33, 63, 700], [4, 10, 100, 17, 1000], 3, 12, 496),
 ])
 def test_batched_sketch_matches_oracle(ms, ns, k, l, l1max):
     As, G64, plan, out = run_batch(ms, ns, k, l, l1max)
@@ -57,6 +60,8 @@ def test_batched_sketch_matches_oracle(ms, ns, k, l, l1max):
     ([300, 700, 121, 4096, 1500, 497], [130, 1024, 640, 200, 333, 257], 111, 121, 496),
     ([64, 200, 90, 1000], [50, 77, 300, 1000], 20, 40, 128),
     ([150, 333, 2000], [90, 700, 129], 50, 60, 130),
+    ([4, 5, 7, 9, 64, 65, 4096], [3, 5, 8, 9, 127, 129, 1024], 2, 4, 8),
+    ([12, 20, 33, 63, 700], [4, 10, 100, 17, 1000], 3, 12, 496),
 ])
 def test_batched_id_residual_within_2x_of_oracle(ms, ns, k, l, l1max):
     As, G64, plan, out = run_batch(ms, ns, k, l, l1max)
