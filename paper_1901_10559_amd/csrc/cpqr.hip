@@ -975,6 +975,99 @@ __global__ __launch_bounds__(256) void trsm_group_kernel(int64_t n, int64_t k, c
     for (int64_t r = keff + q; r < k; r += 16) P[r * n + j] = 0.0;
 }
 
+// The same solve where R11 does not fit in LDS (k up to 16*KS): R11 is read
+// from memory TRSM_TC steps at a time.  The workgroup (16 columns) stages the
+// entries R11[r][c] of a block of TRSM_TC consecutive steps into LDS
+// cooperatively (contiguous reads along r of the column-major R11), and the
+// next block's loads are in flight while the current block's steps run, so a
+// step waits on LDS instead of an L2 round trip.  Per column the arithmetic
+// (its order included) is that of trsm_group_kernel.
+constexpr int TRSM_TC = 16;
+template <int KS>
+__global__ __launch_bounds__(256) void trsm_chunk_kernel(int64_t n, int64_t k, const double* __restrict__ Rt,
+                                                         const double* __restrict__ R11c,
+                                                         const int32_t* __restrict__ pos,
+                                                         const int64_t* __restrict__ keffp, double* P) {
+    constexpr int KP = 16 * KS;                       // staged entries per step
+    constexpr int PER = (TRSM_TC * KP + 255) / 256;   // staged doubles per thread per block
+    static_assert(TRSM_TC * KP % 256 == 0, "whole blocks per thread");
+    __shared__ double stg[2][TRSM_TC * KP];           // [buffer][rr * KP + c] = R11[r1 - rr][c]
+    const int64_t keff64 = *keffp;
+    if (keff64 < 0) return;  // the same for the whole workgroup
+    const int keff = (int)keff64;
+    const int tid = threadIdx.x, q = tid & 15;
+    const int64_t j = (int64_t)blockIdx.x * 16 + (tid >> 4);
+    const bool inb = j < n;
+    const int32_t pj = inb ? pos[j] : 0;
+    const bool solve = inb && pj < 0;  // other lanes only help with the staging
+    if (inb && pj >= 0)
+        for (int64_t r = q; r < k; r += 16) P[r * n + j] = (r == pj) ? 1.0 : 0.0;
+    double b[KS], x[KS];
+#pragma unroll
+    for (int sl = 0; sl < KS; ++sl) {
+        const int64_t c = 16 * sl + q;
+        b[sl] = (solve && c < keff) ? Rt[j * k + c] : 0.0;
+        x[sl] = 0.0;
+    }
+    // block i holds steps r = r1 - rr, rr < TRSM_TC, r1 = keff - 1 - i TRSM_TC;
+    // element e of a block: c = e / TRSM_TC, rr = e % TRSM_TC
+    const int nblk = (keff + TRSM_TC - 1) / TRSM_TC;
+    double v[PER];
+    auto load = [&](int i) {
+        const int r1 = keff - 1 - i * TRSM_TC;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + 256 * u, c = e / TRSM_TC, r = r1 - e % TRSM_TC;
+            const bool ok = c < keff && r >= 0;
+            v[u] = R11c[ok ? (int64_t)c * k + r : 0];
+        }
+        asm volatile("" ::: "memory");
+    };
+    auto store = [&](int i) {
+        double* S = stg[i & 1];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + 256 * u, c = e / TRSM_TC, rr = e % TRSM_TC;
+            S[rr * KP + c] = v[u];
+        }
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int i = 0; i < nblk; ++i) {
+        if (i + 1 < nblk) load(i + 1);
+        const double* S = stg[i & 1];
+        const int r1 = keff - 1 - i * TRSM_TC;
+        for (int rr = 0; rr < TRSM_TC; ++rr) {
+            const int r = r1 - rr;
+            if (r < 0) break;
+            const double* row = S + rr * KP;  // row[c] = R11[r][c]
+            double part = 0.0;
+#pragma unroll
+            for (int sl = 0; sl < KS; ++sl) {
+                const int c = 16 * sl + q;
+                if (c == r) part = b[sl];
+                if (c > r && c < keff) part = fma(-row[c], x[sl], part);
+            }
+            part += dpp_f64<0xB1, 0xf>(part);
+            part += dpp_f64<0x4E, 0xf>(part);
+            part += dpp_f64<0x141, 0xf>(part);
+            part += dpp_f64<0x140, 0xf>(part);
+            const double xr = part / row[r];
+            if (q == (r & 15)) {
+#pragma unroll
+                for (int sl = 0; sl < KS; ++sl)
+                    if (sl == (r >> 4)) x[sl] = xr;
+            }
+            if (q == 0 && solve) P[(int64_t)r * n + j] = xr;
+        }
+        if (i + 1 < nblk) store(i + 1);
+        __syncthreads();
+    }
+    if (solve)
+        for (int64_t r = keff + q; r < k; r += 16) P[r * n + j] = 0.0;
+}
+
 // k <= 128: the axpy back-substitution, GQ = 1, 2, 4 lanes per column
 template <int GQ>
 __global__ __launch_bounds__(256) void trsm_axpy_kernel(int64_t n, int64_t k, const double* __restrict__ Rt,
@@ -1212,8 +1305,8 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
             hipLaunchKernelGGL((trsm_group_kernel<KS, true>), dim3(g16), dim3(256), r11, st, sp.n, sp.k, Rt,       \
                                R11c, pos, (const int64_t*)keff, P);                                   \
         else                                                                                                       \
-            hipLaunchKernelGGL((trsm_group_kernel<KS, false>), dim3(g16), dim3(256), 0, st, sp.n, sp.k, Rt,        \
-                               R11c, pos, (const int64_t*)keff, P);                                   \
+            hipLaunchKernelGGL((trsm_chunk_kernel<KS>), dim3(g16), dim3(256), 0, st, sp.n, sp.k, Rt, R11c, pos,    \
+                               (const int64_t*)keff, P);                                                           \
     } while (0)
     const size_t ax = sizeof(double) * (size_t)sp.k * (trsm_ax_ldk<4>() + 1);
     if (sp.k <= 32)

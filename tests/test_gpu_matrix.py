@@ -177,7 +177,9 @@ def test_projection_f32():
                                    (130, 700, 130), (200, 6000, 150), (300, 900, 64), (400, 3000, 120),
                                    (700, 400, 30), (800, 1200, 90), (900, 2400, 60), (1500, 600, 50),
                                    (1500, 2000, 40), (4096, 300, 30),
-                                   (3000, 500, 40), (2049, 260, 70), (4096, 2000, 12)])
+                                   (3000, 500, 40), (2049, 260, 70), (4096, 2000, 12),
+                                   # R11 staged from memory a block of steps at a time (k > 143)
+                                   (250, 800, 201), (300, 1500, 256)])
 def test_select_f64(l, n, k):
     g = np.random.default_rng(l + n + k)
     Y = g.standard_normal((l, n)) * g.uniform(0.1, 10, n)[None, :]
