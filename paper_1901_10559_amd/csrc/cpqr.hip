@@ -917,11 +917,11 @@ __global__ __launch_bounds__(TRSM_THREADS) void trsm_p_kernel(int64_t n, int64_t
     for (int64_t r = keff; r < k; ++r) P[r * n + j] = 0.0;
 }
 
-// Faster variant for k <= 16*KS: a group of 16 lanes solves one column.  Lane q
+// Faster variant for k <= 16*KS with R11 in LDS: a group of 16 lanes solves one column.  Lane q
 // of the group keeps x_c and b_c for c = 16*s + q in register slot s; at step r
 // every lane forms its part of b_r - sum_{c>r} R11[r][c] x_c, the 16 parts are
 // summed with DPP row operations, and x_r = (that sum) / R11[r][r].
-template <int KS, bool R11_LDS>
+template <int KS>
 __global__ __launch_bounds__(256) void trsm_group_kernel(int64_t n, int64_t k, const double* __restrict__ Rt,
                                                          const double* __restrict__ R11c,
                                                          const int32_t* __restrict__ pos,
@@ -929,10 +929,8 @@ __global__ __launch_bounds__(256) void trsm_group_kernel(int64_t n, int64_t k, c
     extern __shared__ double R11s[];
     const int64_t keff = *keffp;
     if (keff < 0) return;
-    if (R11_LDS) {
-        stage_r11(R11s, R11c, k, (int)keff, 256);
-        __syncthreads();
-    }
+    stage_r11(R11s, R11c, k, (int)keff, 256);
+    __syncthreads();
     const int q = threadIdx.x & 15;
     const int64_t j = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
     if (j >= n) return;
@@ -949,21 +947,24 @@ __global__ __launch_bounds__(256) void trsm_group_kernel(int64_t n, int64_t k, c
         x[sl] = 0.0;
     }
     for (int64_t r = keff - 1; r >= 0; --r) {
+        // the row's reads issued together from clamped addresses (a read
+        // behind the c > r test is compiled as a branch and a wait each)
+        double rv[KS];
+#pragma unroll
+        for (int sl = 0; sl < KS; ++sl) rv[sl] = R11s[r * keff + min<int64_t>(16 * sl + q, keff - 1)];
+        asm volatile("" ::: "memory");
         double part = 0.0;
 #pragma unroll
         for (int sl = 0; sl < KS; ++sl) {
             const int64_t c = 16 * sl + q;
-            if (c == r) part = b[sl];
-            if (c > r && c < keff) {
-                const double rc = R11_LDS ? R11s[r * keff + c] : R11c[c * k + r];
-                part = fma(-rc, x[sl], part);
-            }
+            const double f = fma(-rv[sl], x[sl], part);
+            part = (c == r) ? b[sl] : ((c > r && c < keff) ? f : part);
         }
         part += dpp_f64<0xB1, 0xf>(part);
         part += dpp_f64<0x4E, 0xf>(part);
         part += dpp_f64<0x141, 0xf>(part);
         part += dpp_f64<0x140, 0xf>(part);
-        const double d = R11_LDS ? R11s[r * keff + r] : R11c[r * k + r];
+        const double d = R11s[r * keff + r];
         const double xr = part / d;
         if (q == (int)(r & 15)) {
 #pragma unroll
@@ -980,8 +981,10 @@ __global__ __launch_bounds__(256) void trsm_group_kernel(int64_t n, int64_t k, c
 // entries R11[r][c] of a block of TRSM_TC consecutive steps into LDS
 // cooperatively (contiguous reads along r of the column-major R11), and the
 // next block's loads are in flight while the current block's steps run, so a
-// step waits on LDS instead of an L2 round trip.  Per column the arithmetic
-// (its order included) is that of trsm_group_kernel.
+// step waits on LDS instead of an L2 round trip.  Within a step each lane
+// keeps four partial sums (a chain of KS / 4 dependent FMAs instead of KS),
+// and x_r = part * (1 / R11[r][r]) with the reciprocals of a block's diagonal
+// formed at staging.
 constexpr int TRSM_TC = 16;
 template <int KS>
 __global__ __launch_bounds__(256) void trsm_chunk_kernel(int64_t n, int64_t k, const double* __restrict__ Rt,
@@ -992,6 +995,7 @@ __global__ __launch_bounds__(256) void trsm_chunk_kernel(int64_t n, int64_t k, c
     constexpr int PER = (TRSM_TC * KP + 255) / 256;   // staged doubles per thread per block
     static_assert(TRSM_TC * KP % 256 == 0, "whole blocks per thread");
     __shared__ double stg[2][TRSM_TC * KP];           // [buffer][rr * KP + c] = R11[r1 - rr][c]
+    __shared__ double rdg[2][TRSM_TC];                // [buffer][rr] = 1 / R11[r1 - rr][r1 - rr]
     const int64_t keff64 = *keffp;
     if (keff64 < 0) return;  // the same for the whole workgroup
     const int keff = (int)keff64;
@@ -1003,16 +1007,22 @@ __global__ __launch_bounds__(256) void trsm_chunk_kernel(int64_t n, int64_t k, c
     if (inb && pj >= 0)
         for (int64_t r = q; r < k; r += 16) P[r * n + j] = (r == pj) ? 1.0 : 0.0;
     double b[KS], x[KS];
+    {
+        // loads from clamped addresses, all in flight together, then masked
+        const int64_t jr = (inb ? j : 0) * k;
 #pragma unroll
-    for (int sl = 0; sl < KS; ++sl) {
-        const int64_t c = 16 * sl + q;
-        b[sl] = (solve && c < keff) ? Rt[j * k + c] : 0.0;
-        x[sl] = 0.0;
+        for (int sl = 0; sl < KS; ++sl) b[sl] = Rt[jr + min(16 * sl + q, max(keff - 1, 0))];
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int sl = 0; sl < KS; ++sl) {
+            b[sl] = (solve && 16 * sl + q < keff) ? b[sl] : 0.0;
+            x[sl] = 0.0;
+        }
     }
     // block i holds steps r = r1 - rr, rr < TRSM_TC, r1 = keff - 1 - i TRSM_TC;
     // element e of a block: c = e / TRSM_TC, rr = e % TRSM_TC
     const int nblk = (keff + TRSM_TC - 1) / TRSM_TC;
-    double v[PER];
+    double v[PER], dg = 1.0;  // dg: thread rr < TRSM_TC also loads R11[r1 - rr][r1 - rr]
     auto load = [&](int i) {
         const int r1 = keff - 1 - i * TRSM_TC;
 #pragma unroll
@@ -1021,6 +1031,8 @@ __global__ __launch_bounds__(256) void trsm_chunk_kernel(int64_t n, int64_t k, c
             const bool ok = c < keff && r >= 0;
             v[u] = R11c[ok ? (int64_t)c * k + r : 0];
         }
+        const int rd = r1 - tid;
+        dg = R11c[(tid < TRSM_TC && rd >= 0) ? (int64_t)rd * (k + 1) : 0];
         asm volatile("" ::: "memory");
     };
     auto store = [&](int i) {
@@ -1030,6 +1042,7 @@ __global__ __launch_bounds__(256) void trsm_chunk_kernel(int64_t n, int64_t k, c
             const int e = tid + 256 * u, c = e / TRSM_TC, rr = e % TRSM_TC;
             S[rr * KP + c] = v[u];
         }
+        if (tid < TRSM_TC) rdg[i & 1][tid] = 1.0 / dg;
     };
     load(0);
     store(0);
@@ -1042,18 +1055,25 @@ __global__ __launch_bounds__(256) void trsm_chunk_kernel(int64_t n, int64_t k, c
             const int r = r1 - rr;
             if (r < 0) break;
             const double* row = S + rr * KP;  // row[c] = R11[r][c]
-            double part = 0.0;
+            // all KS reads issued together (a read behind the c > r test is
+            // compiled as a branch and a wait each), then the masked FMAs
+            double rv[KS];
+#pragma unroll
+            for (int sl = 0; sl < KS; ++sl) rv[sl] = row[16 * sl + q];
+            asm volatile("" ::: "memory");
+            double ps[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int sl = 0; sl < KS; ++sl) {
                 const int c = 16 * sl + q;
-                if (c == r) part = b[sl];
-                if (c > r && c < keff) part = fma(-row[c], x[sl], part);
+                const double f = fma(-rv[sl], x[sl], ps[sl & 3]);
+                ps[sl & 3] = (c == r) ? b[sl] : ((c > r && c < keff) ? f : ps[sl & 3]);
             }
+            double part = (ps[0] + ps[1]) + (ps[2] + ps[3]);
             part += dpp_f64<0xB1, 0xf>(part);
             part += dpp_f64<0x4E, 0xf>(part);
             part += dpp_f64<0x141, 0xf>(part);
             part += dpp_f64<0x140, 0xf>(part);
-            const double xr = part / row[r];
+            const double xr = part * rdg[i & 1][rr];
             if (q == (r & 15)) {
 #pragma unroll
                 for (int sl = 0; sl < KS; ++sl)
@@ -1302,8 +1322,8 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
 #define IDS_TRSM_GROUP(KS)                                                                                         \
     do {                                                                                                           \
         if (r11 <= lim)                                                                                            \
-            hipLaunchKernelGGL((trsm_group_kernel<KS, true>), dim3(g16), dim3(256), r11, st, sp.n, sp.k, Rt,       \
-                               R11c, pos, (const int64_t*)keff, P);                                   \
+            hipLaunchKernelGGL((trsm_group_kernel<KS>), dim3(g16), dim3(256), r11, st, sp.n, sp.k, Rt, R11c, pos,  \
+                               (const int64_t*)keff, P);                                                           \
         else                                                                                                       \
             hipLaunchKernelGGL((trsm_chunk_kernel<KS>), dim3(g16), dim3(256), 0, st, sp.n, sp.k, Rt, R11c, pos,    \
                                (const int64_t*)keff, P);                                                           \

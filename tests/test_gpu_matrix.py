@@ -205,6 +205,17 @@ def test_select_column_major_f32_input():
     assert np.linalg.norm(P.cpu().numpy() - Po) <= 1e-10 * np.linalg.norm(Po)
 
 
+@pytest.mark.parametrize("l,n,k", [(30, 100, 20), (250, 800, 201)])
+def test_select_zero_matrix(l, n, k):
+    # rank 0: no pivot, k_eff = 0, J all -1 and P all zero (every solve kernel
+    # must handle keff = 0; k = 201 takes the block-staged one)
+    J, P, keff = ids.id_select(dev(np.zeros((l, n))), k)
+    Jo, Po, ko, _, _ = oracle.cpqr_id(np.zeros((l, n)), k, trace=True)
+    assert int(keff.item()) == ko == 0
+    assert np.array_equal(J.cpu().numpy(), Jo)
+    assert np.array_equal(P.cpu().numpy(), Po)
+
+
 @pytest.mark.parametrize("l,n", [(10, 40), (60, 20000), (200, 6000), (300, 900), (3000, 500)])
 def test_select_rank_deficient(l, n):
     g = np.random.default_rng(6)
