@@ -191,7 +191,8 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
  *   QR of the l x n_p projection with FP32 data and FP64 norms recomputed
  *   every step; FP64 back-substitution for P_p.
  * Limits: 1 <= k <= l <= 122, l <= l1max <= 512, l <= m_p <= 4096,
- * k < n_p <= 1024.
+ * k < n_p <= 1024.  A and G need only element (2-byte) alignment; the results
+ * do not depend on it (16-byte-aligned rows are merely read faster).
  *   ids_batched_plan  uploads per-problem descriptors (offsets, largest-first
  *                     schedule) into a caller-owned device buffer of
  *                     ids_batched_plan_size() bytes; synchronises `stream`
