@@ -3,7 +3,8 @@
 // second stage and Algorithm 1:
 //   batched_sketch_kernel  one workgroup per problem (largest first): the
 //       CountSketch plan in LDS, then per 128-column panel and per group of 64
-//       buckets, Y1 rows summed in FP32 from 16-byte BF16 loads, split into
+//       buckets (paired largest with smallest for the gather threads), Y1
+//       rows summed in FP32 from 16-byte BF16 loads, split into
 //       BF16 hi + lo, and multiplied by the BF16 Gaussian G on the matrix cores
 //       (v_mfma_f32_16x16x32_bf16, FP32 accumulation): Y_p = G (S A_p) stays in
 //       registers per panel and is written once (FP32, column-major).
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
     // strip, so half the LDS reads and operand registers
     const int rt0 = 4 * (w >> 2);
     const int ct0 = 2 * (w & 3);
-    const int bl = tid >> 4;        // buckets bl and 32 + bl of the group (gather phase)
+    const int bl = tid >> 4;        // pairing slot: buckets pairing[g0 + bl], pairing[g0 + 32 + bl] (gather)
     const int ch = tid & 15;        // 8-column chunk within panel (gather phase)
     const uint16_t* Ap = a.A + pr.a_off;
     float* Yp = a.Y + pr.y_off;
