@@ -221,9 +221,14 @@ ids_status id_batched(int64_t nprob, const int64_t* m, const int64_t* n, const v
  * "tensorsketch", "lambda_hat").  ids_profile_read waits for the recorded
  * events and returns the summed elapsed milliseconds and the number of
  * recorded launches of a stage; ids_profile_reset waits for and recycles them.
- * Intended for measurement; off by default.
+ * Intended for measurement; off by default.  Each recorded pair costs the
+ * stream a few microseconds, so ids_profile_stages restricts recording to
+ * the named stages (comma-separated, e.g. "countsketch"; NULL or "" = all,
+ * the default); an unknown name is IDS_EINVAL and leaves the selection as it
+ * was.
  */
 void ids_profile_enable(int on);
+ids_status ids_profile_stages(const char* stages);
 ids_status ids_profile_read(const char* stage, double* total_ms, int64_t* count);
 void ids_profile_reset(void);
 

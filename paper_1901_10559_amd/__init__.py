@@ -21,7 +21,7 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["lib", "lib_path", "BatchedPlan", "batched_plan", "id_batched", "profile_enable", "profile_read", "profile_reset", "id_sketch", "id_project", "id_select", "matrix_id", "tensor_id", "gaussian_sketch", "gaussian_id",
+__all__ = ["lib", "lib_path", "BatchedPlan", "batched_plan", "id_batched", "profile_enable", "profile_stages", "profile_read", "profile_reset", "id_sketch", "id_project", "id_select", "matrix_id", "tensor_id", "gaussian_sketch", "gaussian_id",
            "IdsError", "F64", "F32", "BF16", "HASH_FULLRANK", "EXPORTED"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -34,7 +34,7 @@ HASH_FULLRANK = 1
 EXPORTED = ["ids_sketch_workspace_size", "id_sketch", "id_project", "ids_gaussian_workspace_size",
             "id_gaussian_sketch", "ids_select_workspace_size",
             "id_select", "ids_tensor_workspace_size", "tensor_id", "ids_batched_plan_size", "ids_batched_plan",
-            "id_batched", "ids_profile_enable", "ids_profile_read",
+            "id_batched", "ids_profile_enable", "ids_profile_stages", "ids_profile_read",
             "ids_profile_reset", "ids_status_string", "ids_last_error"]
 
 c_i64 = ctypes.c_int64
@@ -88,6 +88,8 @@ def lib():
             getattr(L, fn).restype = c_i32
         L.ids_profile_enable.argtypes = [c_i32]
         L.ids_profile_enable.restype = None
+        L.ids_profile_stages.argtypes = [ctypes.c_char_p]
+        L.ids_profile_stages.restype = c_i32
         L.ids_profile_read.argtypes = [ctypes.c_char_p, P(ctypes.c_double), P(c_i64)]
         L.ids_profile_read.restype = c_i32
         L.ids_profile_reset.argtypes = []
@@ -166,6 +168,11 @@ def _matrix_desc(A):
 def profile_enable(on: bool = True):
     """Record HIP events around every stage of subsequent calls."""
     lib().ids_profile_enable(1 if on else 0)
+
+
+def profile_stages(stages: str | None = None):
+    """Restrict recording to the named stages (comma-separated); None: all."""
+    _check(lib().ids_profile_stages(stages.encode() if stages else None), "ids_profile_stages")
 
 
 def profile_read(stage: str):

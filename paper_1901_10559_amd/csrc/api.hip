@@ -48,6 +48,7 @@ struct ProfRec {
 };
 static std::mutex g_prof_mu;
 static bool g_prof_on = false;
+static uint32_t g_prof_mask = (1u << PK_COUNT) - 1;  // stages recorded while on
 static std::vector<ProfRec> g_recs;
 static std::vector<hipEvent_t> g_pool;
 
@@ -64,7 +65,7 @@ static hipEvent_t prof_event() {
 
 ProfScope::ProfScope(int k, hipStream_t s) : kind(k), st(s), a(nullptr), on(false) {
     std::lock_guard<std::mutex> g(g_prof_mu);
-    if (!g_prof_on) return;
+    if (!g_prof_on || !((g_prof_mask >> k) & 1u)) return;
     a = prof_event();
     if (a && hipEventRecord(a, st) == hipSuccess) on = true;
 }
@@ -169,6 +170,31 @@ const char* ids_last_error(void) { return g_err.c_str(); }
 void ids_profile_enable(int on) {
     std::lock_guard<std::mutex> g(g_prof_mu);
     g_prof_on = on != 0;
+}
+
+ids_status ids_profile_stages(const char* stages) {
+    g_err.clear();
+    uint32_t mask = 0;
+    if (!stages || !*stages) {
+        mask = (1u << PK_COUNT) - 1;
+    } else {
+        std::string all(stages);
+        size_t b = 0;
+        while (b <= all.size()) {
+            size_t e = all.find(',', b);
+            if (e == std::string::npos) e = all.size();
+            const std::string name = all.substr(b, e - b);
+            int kind = -1;
+            for (int k = 0; k < PK_COUNT; ++k)
+                if (name == kProfNames[k]) kind = k;
+            if (kind < 0) return fail(IDS_EINVAL, "unknown stage " + name);
+            mask |= 1u << kind;
+            b = e + 1;
+        }
+    }
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_mask = mask;
+    return IDS_OK;
 }
 
 ids_status ids_profile_read(const char* stage, double* total_ms, int64_t* count) {

@@ -89,3 +89,12 @@ def test_binding_refuses_without_gpu():
         pytest.skip("GPU present")
     with pytest.raises(ids.IdsError):
         ids.id_select(torch.zeros(4, 8, dtype=torch.float64), 2)
+
+
+def test_profile_stage_selection_without_gpu():
+    L = ids.lib()
+    assert L.ids_profile_stages(b"countsketch,cpqr") == 0
+    assert L.ids_profile_stages(b"countsketch,nosuch") == 1
+    assert b"unknown stage nosuch" in L.ids_last_error()
+    assert L.ids_profile_stages(None) == 0
+    assert L.ids_profile_stages(b"") == 0
