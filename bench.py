@@ -39,6 +39,35 @@ def cache_dir() -> str:
     return d
 
 
+
+def time_and_stages(ids, torch, fn, steps: int, names):
+    """Milliseconds per call of fn over `steps` timed calls (no stage events in
+    the timed region), then the per-stage averages from a separate pass of the
+    same calls with HIP events around every stage."""
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ids.profile_reset()
+    ids.profile_enable(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    ids.profile_enable(False)
+    st = {}
+    for nme in names:
+        t, c = ids.profile_read(nme)
+        st[nme] = t / max(c, 1)
+    ids.profile_reset()
+    return ms, st
+
 def workload(seed: int = 0):
     import numpy as np
 
@@ -88,25 +117,12 @@ def run_batched(ids, torch, np, m, n, Abits, Gb, steps: int, check: bool):
     At = torch.from_numpy(Abits.view(np.int16)).to(dev).view(torch.bfloat16)
     Gt = torch.from_numpy(Gb.view(np.int16)).to(dev).view(torch.bfloat16)
     plan = ids.batched_plan(m, n, KB, LB, L1B)
-    for _ in range(2):
-        out = ids.id_batched(plan, At, Gt, seed=0)
-    torch.cuda.synchronize()
-    ids.profile_reset()
-    ids.profile_enable(True)
+    ms, st0 = time_and_stages(ids, torch, lambda: ids.id_batched(plan, At, Gt, seed=0), steps,
+                              ("countsketch", "cpqr", "trsm"))
+    st = {"sketch_project": st0["countsketch"], "cpqr": st0["cpqr"], "trsm": st0["trsm"]}
+    out = ids.id_batched(plan, At, Gt, seed=0)   # result checked below
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        out = ids.id_batched(plan, At, Gt, seed=0)
-    e1.record()
-    torch.cuda.synchronize()
-    ids.profile_enable(False)
-    ms = e0.elapsed_time(e1) / steps
-    st = {}
-    for sname, key in (("countsketch", "sketch_project"), ("cpqr", "cpqr"), ("trsm", "trsm")):
-        t, c = ids.profile_read(sname)
-        st[key] = t / max(c, 1)
-    ids.profile_reset()
     sk_bytes = int((m * n).sum()) * 2 + int(n.sum()) * LB * 4      # read A (BF16), write Y (FP32)
     res = {"value": NB / (ms / 1e3), "unit": "IDs/s", "ms_per_batch": ms, "problems": NB,
            "workload": f"{NB} problems, m~logU[256,4096], n~logU[128,1024], sigma_i=exp(-i/8), "
@@ -178,25 +194,7 @@ def other_workloads(ids, torch, np, steps: int = 10):
     res = {}
 
     def timed(fn, names):
-        for _ in range(2):
-            fn()
-        torch.cuda.synchronize()
-        ids.profile_reset()
-        ids.profile_enable(True)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        ids.profile_enable(False)
-        st = {}
-        for nme in names:
-            t, c = ids.profile_read(nme)
-            st[nme] = t / max(c, 1)
-        ids.profile_reset()
-        return e0.elapsed_time(e1) / steps, st
+        return time_and_stages(ids, torch, fn, steps, names)
 
     # c0: 2000 x 1000 FP64, k = 20, p = 10, l1 = 128 (latency of one small ID)
     A0 = torch.from_numpy(synth.config0()).to(dev)
@@ -275,25 +273,8 @@ def gaussian_baseline(ids, torch, At, Omega, cs_ms: float, steps: int = 10):
     Om = torch.from_numpy(Omega).to(dev)
     l, m = Om.shape
     n = At.shape[1]
-    for _ in range(2):
-        ids.gaussian_id(At, K, Om)
-    torch.cuda.synchronize()
-    ids.profile_reset()
-    ids.profile_enable(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        ids.gaussian_id(At, K, Om)
-    e1.record()
-    torch.cuda.synchronize()
-    ids.profile_enable(False)
-    st = {}
-    for nme in ("project", "cpqr", "trsm"):
-        t, c = ids.profile_read(nme)
-        st["gaussian_sketch" if nme == "project" else nme] = t / max(c, 1)
-    ids.profile_reset()
-    ms = e0.elapsed_time(e1) / steps
+    ms, st0 = time_and_stages(ids, torch, lambda: ids.gaussian_id(At, K, Om), steps, ("project", "cpqr", "trsm"))
+    st = {("gaussian_sketch" if nme == "project" else nme): v for nme, v in st0.items()}
     flops = 2.0 * l * m * n
     tf = flops / (st["gaussian_sketch"] / 1e3) / 1e12
     return {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st,
