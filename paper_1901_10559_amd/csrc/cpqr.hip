@@ -981,10 +981,13 @@ __global__ __launch_bounds__(256) void trsm_group_kernel(int64_t n, int64_t k, c
 // entries R11[r][c] of a block of TRSM_TC consecutive steps into LDS
 // cooperatively (contiguous reads along r of the column-major R11), and the
 // next block's loads are in flight while the current block's steps run, so a
-// step waits on LDS instead of an L2 round trip.  Within a step each lane
-// keeps four partial sums (a chain of KS / 4 dependent FMAs instead of KS),
-// and x_r = part * (1 / R11[r][r]) with the reciprocals of a block's diagonal
-// formed at staging.
+// step waits on LDS instead of an L2 round trip.  A column's right-hand side
+// and solution live in LDS too (x_c = 0 until solved), so a step is plain
+// FMAs over all slots with no per-slot selects: each lane keeps four partial
+// sums, the 16 lanes are summed with DPP, x_r = (b_r + sum) / R11[r][r] (the
+// reciprocals of a block's diagonal formed at staging) and one lane stores
+// x_r for the column's later steps.  One wave per SIMD is all this solve has
+// (16 lanes per column), so instructions per step set its pace.
 constexpr int TRSM_TC = 16;
 template <int KS>
 __global__ __launch_bounds__(256) void trsm_chunk_kernel(int64_t n, int64_t k, const double* __restrict__ Rt,
@@ -996,27 +999,31 @@ __global__ __launch_bounds__(256) void trsm_chunk_kernel(int64_t n, int64_t k, c
     static_assert(TRSM_TC * KP % 256 == 0, "whole blocks per thread");
     __shared__ double stg[2][TRSM_TC * KP];           // [buffer][rr * KP + c] = R11[r1 - rr][c]
     __shared__ double rdg[2][TRSM_TC];                // [buffer][rr] = 1 / R11[r1 - rr][r1 - rr]
+    __shared__ double xs[16][KP];                     // [column][c] = x_c, 0 until solved
+    __shared__ double bs[16][KP];                     // [column][c] = b_c
     const int64_t keff64 = *keffp;
     if (keff64 < 0) return;  // the same for the whole workgroup
     const int keff = (int)keff64;
-    const int tid = threadIdx.x, q = tid & 15;
+    const int tid = threadIdx.x, q = tid & 15, col = tid >> 4;
     const int64_t j = (int64_t)blockIdx.x * 16 + (tid >> 4);
     const bool inb = j < n;
     const int32_t pj = inb ? pos[j] : 0;
     const bool solve = inb && pj < 0;  // other lanes only help with the staging
     if (inb && pj >= 0)
         for (int64_t r = q; r < k; r += 16) P[r * n + j] = (r == pj) ? 1.0 : 0.0;
-    double b[KS], x[KS];
     {
-        // loads from clamped addresses, all in flight together, then masked
+        // loads from clamped addresses, all in flight together, then masked;
+        // a column's b and x are used by its own 16 lanes only (one wave)
         const int64_t jr = (inb ? j : 0) * k;
+        double bv[KS];
 #pragma unroll
-        for (int sl = 0; sl < KS; ++sl) b[sl] = Rt[jr + min(16 * sl + q, max(keff - 1, 0))];
+        for (int sl = 0; sl < KS; ++sl) bv[sl] = Rt[jr + min(16 * sl + q, max(keff - 1, 0))];
         asm volatile("" ::: "memory");
 #pragma unroll
         for (int sl = 0; sl < KS; ++sl) {
-            b[sl] = (solve && 16 * sl + q < keff) ? b[sl] : 0.0;
-            x[sl] = 0.0;
+            const int c = 16 * sl + q;
+            bs[col][c] = (solve && c < keff) ? bv[sl] : 0.0;
+            xs[col][c] = 0.0;
         }
     }
     // block i holds steps r = r1 - rr, rr < TRSM_TC, r1 = keff - 1 - i TRSM_TC;
@@ -1055,31 +1062,28 @@ __global__ __launch_bounds__(256) void trsm_chunk_kernel(int64_t n, int64_t k, c
             const int r = r1 - rr;
             if (r < 0) break;
             const double* row = S + rr * KP;  // row[c] = R11[r][c]
-            // all KS reads issued together (a read behind the c > r test is
-            // compiled as a branch and a wait each), then the masked FMAs
-            double rv[KS];
+            const double* xc = xs[col];
+            // all reads issued together, then the FMAs (unsolved x_c are 0)
+            double rv[KS], xv[KS];
 #pragma unroll
-            for (int sl = 0; sl < KS; ++sl) rv[sl] = row[16 * sl + q];
+            for (int sl = 0; sl < KS; ++sl) {
+                rv[sl] = row[16 * sl + q];
+                xv[sl] = xc[16 * sl + q];
+            }
             asm volatile("" ::: "memory");
             double ps[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int sl = 0; sl < KS; ++sl) {
-                const int c = 16 * sl + q;
-                const double f = fma(-rv[sl], x[sl], ps[sl & 3]);
-                ps[sl & 3] = (c == r) ? b[sl] : ((c > r && c < keff) ? f : ps[sl & 3]);
-            }
+            for (int sl = 0; sl < KS; ++sl) ps[sl & 3] = fma(-rv[sl], xv[sl], ps[sl & 3]);
             double part = (ps[0] + ps[1]) + (ps[2] + ps[3]);
             part += dpp_f64<0xB1, 0xf>(part);
             part += dpp_f64<0x4E, 0xf>(part);
             part += dpp_f64<0x141, 0xf>(part);
             part += dpp_f64<0x140, 0xf>(part);
-            const double xr = part * rdg[i & 1][rr];
-            if (q == (r & 15)) {
-#pragma unroll
-                for (int sl = 0; sl < KS; ++sl)
-                    if (sl == (r >> 4)) x[sl] = xr;
+            const double xr = (bs[col][r] + part) * rdg[i & 1][rr];
+            if (q == 0) {
+                xs[col][r] = xr;
+                if (solve) P[(int64_t)r * n + j] = xr;
             }
-            if (q == 0 && solve) P[(int64_t)r * n + j] = xr;
         }
         if (i + 1 < nblk) store(i + 1);
         __syncthreads();
