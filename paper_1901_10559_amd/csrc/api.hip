@@ -134,7 +134,8 @@ static ids_status validate_sketch(const ids_matrix* A, const ids_sketch_cfg* c) 
 
 struct SketchLayout {
     PlanShape ps;
-    size_t plan, y1, bop, total;
+    size_t plan, y1, bop, part, total;
+    int splits;  // projection K split (1: one pass)
 };
 
 static SketchLayout sketch_layout(const ids_matrix* A, const ids_sketch_cfg* c) {
@@ -143,7 +144,11 @@ static SketchLayout sketch_layout(const ids_matrix* A, const ids_sketch_cfg* c) 
     L.plan = plan_bytes(L.ps);
     L.y1 = (c->l < c->l1) ? align256(esize(c->acc) * (size_t)c->l1 * A->n) : 0;
     L.bop = (A->fmt == IDS_CSR) ? align256(sizeof(int32_t) * (size_t)A->m) : 0;
-    L.total = L.plan + L.y1 + L.bop;
+    // a projection with few output tiles splits its K (the l1 sketch rows) so
+    // that about 256 workgroups share it; the partial products need l x n each
+    L.splits = (c->l < c->l1) ? project_splits(c->l, c->l1, A->n, 256) : 1;
+    L.part = (L.splits > 1) ? align256(esize(c->acc) * (size_t)L.splits * c->l * A->n) : 0;
+    L.total = L.plan + L.y1 + L.bop + L.part;
     return L;
 }
 
@@ -255,6 +260,8 @@ ids_status id_sketch(const ids_matrix* A, const ids_sketch_cfg* c, void* Y, int3
     void* Y1 = p;
     p += L.y1;
     int32_t* bop = (int32_t*)p;
+    p += L.bop;
+    void* part = p;
 
     const bool proj = c->l < c->l1;
     const uint64_t key = stream_key(c->seed, c->tag);
@@ -280,7 +287,7 @@ ids_status id_sketch(const ids_matrix* A, const ids_sketch_cfg* c, void* Y, int3
     if (s) return s;
     if (proj) {
         ProfScope ps(PK_PROJ, st);
-        s = project(c->acc, c->l, c->l1, A->n, c->G, Y1, A->n, Y, ldy, st);
+        s = project_split(c->acc, c->l, c->l1, A->n, c->G, Y1, A->n, false, Y, ldy, L.splits, part, st);
     }
     return s;
 }
