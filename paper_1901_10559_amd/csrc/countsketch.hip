@@ -122,11 +122,28 @@ __global__ __launch_bounds__(1024) void plan_offsets_kernel(PlanArgs a, const in
     if (t == 0) a.off[L] = (int32_t)a.m;
 }
 
+// Lanes of the wave holding the same bucket b (valid lanes only), found with
+// one ballot per bit of b: rank = how many of them precede this lane, same =
+// how many there are -- the stable order of a 64-row chunk inside each bucket.
+// Every lane of the wave must take part; nbits covers the largest bucket.
+__device__ __forceinline__ void wave_bucket_rank(uint32_t b, bool valid, int nbits, int& rank, int& same) {
+    uint64_t peers = __ballot(valid);
+    for (int k = 0; k < nbits; ++k) {
+        const bool bit = (b >> k) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    const int lane = threadIdx.x & 63;
+    rank = __popcll(peers & ((1ull << lane) - 1ull));
+    same = __popcll(peers);
+}
+
 // one wave per segment: stable placement (rows of a bucket in increasing order)
 __global__ __launch_bounds__(64) void plan_place_kernel(PlanArgs a) {
     extern __shared__ int32_t run[];
     const int s = blockIdx.x;
     const int lane = threadIdx.x;
+    const int nbits = (a.L > 1) ? 32 - __builtin_clz(a.L - 1) : 0;
     {
         constexpr int U = 8;  // loads in flight per lane
         for (uint32_t b0 = 0; b0 < a.L; b0 += 64 * U) {
@@ -153,14 +170,8 @@ __global__ __launch_bounds__(64) void plan_place_kernel(PlanArgs a) {
         uint32_t b = 0xffffffffu;
         bool neg = false;
         if (valid) plan_hash(a, i, b, neg);
-        int rank = 0, same = 0;
-#pragma unroll 8
-        for (int q = 0; q < 64; ++q) {
-            uint32_t bq = __shfl(b, q, 64);
-            int eq = (bq == b) ? 1 : 0;
-            rank += (q < lane) ? eq : 0;
-            same += eq;
-        }
+        int rank, same;
+        wave_bucket_rank(b, valid, nbits, rank, same);
         int32_t base = 0;
         if (valid) base = run[b];
         __syncthreads();
@@ -234,20 +245,15 @@ __global__ __launch_bounds__(64 * PS_W) void plan_small_kernel(PlanSmallArgs s) 
     // stable placement, wave w over its rows in order (no other wave touches
     // h[w][.], and the read of a bucket's start precedes its update in the wave)
     int32_t* hw = h + w * L;
+    const int nbits = (L > 1) ? 32 - __builtin_clz((uint32_t)(L - 1)) : 0;
     for (int64_t c0 = r0; c0 < r1; c0 += 64) {
         const int64_t i = c0 + lane;
         const bool valid = i < r1;
         uint32_t b = 0xffffffffu;
         bool neg = false;
         if (valid) plan_hash(a, i, b, neg);
-        int rank = 0, same = 0;
-#pragma unroll 8
-        for (int q = 0; q < 64; ++q) {
-            const uint32_t bq = __shfl(b, q, 64);
-            const int eq = (bq == b) ? 1 : 0;
-            rank += (q < lane) ? eq : 0;
-            same += eq;
-        }
+        int rank, same;
+        wave_bucket_rank(b, valid, nbits, rank, same);
         const int32_t base = valid ? hw[b] : 0;
         if (valid) {
             a.rows[base + rank] = encode_row(i, neg);
