@@ -189,7 +189,7 @@ __global__ __launch_bounds__(64) void plan_place_kernel(PlanArgs a) {
 // start offsets (bucket-major, waves in row order, so placement stays
 // stable), then each wave places its rows 64 at a time in increasing order.
 constexpr int PS_W = 4;
-constexpr int64_t PLAN_SMALL_M = 8192;
+constexpr int64_t PLAN_SMALL_M = 16384;
 constexpr int64_t PLAN_SMALL_L = 6144;  // PS_W x L int32 counters in LDS
 constexpr int PLAN_MANY = 8;
 struct PlanSmallArgs {
