@@ -680,18 +680,7 @@ __global__ __launch_bounds__(BT_THREADS) void batched_trsm_kernel(BatchArgs a) {
     double* rd = sm3 + (size_t)keff * LDK;    // keff
     if (tid < keff) Js[tid] = (int32_t)J[tid];
     __syncthreads();
-    copy_batched<8>(
-        keff * LDK, NT,
-        [&](int e) {
-            int r, c;
-            trsm_ax_slot<GQ>(e, r, c);
-            return Rt[(int64_t)Js[r] * k + min(max(c, 0), k - 1)];
-        },
-        [&](int e, double v) {
-            int r, c;
-            trsm_ax_slot<GQ>(e, r, c);
-            R11T[e] = (c >= 0 && c < r) ? v : 0.0;
-        });
+    stage_r11t<GQ, 4>(R11T, keff, k, NT, [&](int r, int c) { return Rt[(int64_t)Js[r] * k + c]; });
     copy_batched<1>(keff, NT, [&](int r) { return bt[r]; }, [&](int r, double v) { rd[r] = 1.0 / v; });
     __syncthreads();
     const int q = tid % GQ;

@@ -1106,18 +1106,7 @@ __global__ __launch_bounds__(256) void trsm_axpy_kernel(int64_t n, int64_t k, co
     double* R11T = sm;                    // keff x LDK
     double* rd = sm + (size_t)keff * LDK;  // keff reciprocal diagonals
     const int tid = threadIdx.x, lane = tid & 63;
-    copy_batched<16>(
-        keff * LDK, 256,
-        [&](int e) {
-            int r, c;
-            trsm_ax_slot<GQ>(e, r, c);
-            return R11c[(int64_t)r * k + min(max(c, 0), (int)k - 1)];
-        },
-        [&](int e, double v) {
-            int r, c;
-            trsm_ax_slot<GQ>(e, r, c);
-            R11T[e] = (c >= 0 && c < r) ? v : 0.0;
-        });
+    stage_r11t<GQ, 4>(R11T, keff, (int)k, 256, [&](int r, int c) { return R11c[(int64_t)r * k + c]; });
     copy_batched<1>(
         keff, 256, [&](int r) { return R11c[(int64_t)r * k + r]; }, [&](int r, double v) { rd[r] = 1.0 / v; });
     __syncthreads();

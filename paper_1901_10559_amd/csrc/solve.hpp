@@ -22,14 +22,42 @@ constexpr int TRSM_AX_SQ = TRSM_AX_KS + 2;
 // doubles per staged row of R11 for GQ lanes per column
 template <int GQ>
 constexpr int trsm_ax_ldk() { return GQ * TRSM_AX_SQ; }
-// staged value of element e of the transposed R11 (row r = e / LDK): the
-// entry's (row of R11, column of R11), or c = -1 for a zero
-template <int GQ>
-__device__ __forceinline__ void trsm_ax_slot(int e, int& r, int& c) {
-    constexpr int LDK = trsm_ax_ldk<GQ>();
-    r = e / LDK;
-    const int rem = e - r * LDK, q = rem / TRSM_AX_SQ, sl = rem - q * TRSM_AX_SQ;
-    c = (sl < TRSM_AX_KS) ? GQ * sl + q : -1;
+// Stages the transposed R11 for axpy_solve: row r < keff of LDK doubles,
+// segment q, slot sl = R11[GQ sl + q][r] where GQ sl + q < r, else 0.  Wave w
+// takes rows w, w + nw, ...; a lane covers the row positions u = lane + 64 i
+// (u < LDK), whose source entries it works out once, and UR rows' loads are
+// issued together.  ld(r, c) reads R11[c][r]; it must be valid for r < keff
+// and 0 <= c < cmax.
+template <int GQ, int UR, class Ld>
+__device__ __forceinline__ void stage_r11t(double* R11T, int keff, int cmax, int nthreads, Ld ld) {
+    constexpr int LDK = trsm_ax_ldk<GQ>(), NI = (LDK + 63) / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = nthreads >> 6;
+    int cu[NI];  // source entry of position u, -1 for a padding slot or u >= LDK
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int u = lane + 64 * i, q = u / TRSM_AX_SQ, sl = u - q * TRSM_AX_SQ;
+        cu[i] = (u < LDK && sl < TRSM_AX_KS) ? GQ * sl + q : -1;
+    }
+    for (int r0 = w; r0 < keff; r0 += nw * UR) {
+        double v[UR][NI];
+#pragma unroll
+        for (int ur = 0; ur < UR; ++ur) {
+            const int r = min(r0 + ur * nw, keff - 1);
+#pragma unroll
+            for (int i = 0; i < NI; ++i) v[ur][i] = ld(r, min(max(cu[i], 0), cmax - 1));
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int ur = 0; ur < UR; ++ur) {
+            const int r = r0 + ur * nw;
+            if (r >= keff) break;
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                const int u = lane + 64 * i;
+                if (u < LDK) R11T[r * LDK + u] = (cu[i] >= 0 && cu[i] < r) ? v[ur][i] : 0.0;
+            }
+        }
+    }
 }
 
 template <int GQ>
