@@ -342,8 +342,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1 "
-                                   "(the sketch is linear in the rows, sharding is described in DESIGN.md)"}))
+        print(json.dumps({"error": "bench.py measures a single GPU; run it with --gpus 1 (multi-GPU "
+                                   "sharding of the row-linear sketch is designed but not implemented)"}))
         sys.exit(2)
 
     import numpy as np
