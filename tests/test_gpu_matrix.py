@@ -287,3 +287,22 @@ def test_matrix_id_csr_small():
     assert tie_aware_J(Jg, o["J"], o["nu"])
     if np.array_equal(Jg, o["J"]):
         assert np.linalg.norm(r["P"].cpu().numpy() - o["P"]) <= 1e-10 * np.linalg.norm(o["P"])
+
+
+def test_stage_timing_restricted_to_named_stages():
+    # events are recorded only around the selected stages while enabled
+    g = np.random.default_rng(11)
+    A = dev(g.standard_normal((3000, 400)))
+    ids.profile_reset()
+    ids.profile_stages("countsketch")
+    ids.profile_enable(True)
+    try:
+        ids.matrix_id(A, 10, 64, 20, seed=1, G=dev(g.standard_normal((20, 64))))
+        torch.cuda.synchronize()
+    finally:
+        ids.profile_enable(False)
+        ids.profile_stages(None)
+    ms, cnt = ids.profile_read("countsketch")
+    assert cnt == 1 and ms > 0.0
+    assert ids.profile_read("cpqr")[1] == 0
+    ids.profile_reset()
