@@ -19,6 +19,7 @@
 // Problem p draws its CountSketch from the stream (seed, tag = p) and uses
 // the first l1_p = min(m_p, l1max) columns of the shared l x l1max G.
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -661,13 +662,14 @@ __global__ __launch_bounds__(NT, 4) void batched_cpqr_kernel(BatchArgs a, int nt
 // back-substitution (no workgroup barrier inside the solve).
 constexpr int BT_THREADS = 512;  // 32 right-hand-side slots per lane need up to 256 VGPRs
 template <int GQ>
-__global__ __launch_bounds__(BT_THREADS) void batched_trsm_kernel(BatchArgs a) {
+__global__ __launch_bounds__(BT_THREADS) void batched_trsm_kernel(BatchArgs a, int nlo, int nhi) {
     constexpr int KS = TRSM_AX_KS, LDK = trsm_ax_ldk<GQ>(), NT = BT_THREADS;
     extern __shared__ __attribute__((aligned(16))) double sm3[];
     __shared__ int32_t Js[BS_LMAX];
     const int p = blockIdx.x;
     const BProb pr = a.prob[p];
     const int n = pr.n;
+    if (n <= nlo || n > nhi) return;  // another launch owns this problem
     const int k = (int)a.k;
     const int keff = (int)a.keff[p];
     const int tid = threadIdx.x;
@@ -773,6 +775,32 @@ ids_status batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, int64
     return IDS_OK;
 }
 
+// Two extra streams per device (default priority, non-blocking) on which the
+// 512- and 256-thread CPQR launches run beside the 1024-thread one, so the
+// smaller problems fill the CUs the largest ones leave idle; created once.
+// The lock keeps one call's event records and waits together.
+struct CpqrSide {
+    hipStream_t s[2] = {nullptr, nullptr};
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    bool ok = false;
+};
+static std::mutex g_side_mu;
+static CpqrSide g_side[64];
+
+static CpqrSide* cpqr_side() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    CpqrSide& c = g_side[dev];
+    if (!c.ok) {
+        for (auto& x : c.s)
+            if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        for (auto& e : c.ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        c.ok = true;
+    }
+    return &c;
+}
+
 ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, int64_t l1max, uint64_t seed,
                        double tol, const void* A, const void* G, int64_t* J, double* P, int64_t* keff, void* ws,
                        size_t ws_bytes, int64_t a_elems, int64_t y_elems, int64_t r_elems, hipStream_t st) {
@@ -809,25 +837,56 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
         hipLaunchKernelGGL(batched_sketch_kernel, dim3((unsigned)nprob), dim3(BS_THREADS), 0, st, a);
     }
     {
+        // CPQR and solve together: the problems of each width class (n_p in
+        // (512, 1024], (256, 512], (0, 256]) go through their CPQR and then
+        // their solve on a stream of their own, so one class's solve overlaps
+        // the others' CPQR; stage timing covers both
         ProfScope ps(PK_CPQR, st);
         a.order = (const int32_t*)((const char*)plan + o2);
+        std::lock_guard<std::mutex> g(g_side_mu);
+        CpqrSide* side = cpqr_side();
+        hipStream_t s512 = st, s256 = st;
+        if (side) {  // else all on the caller's stream, one after another
+            if (hipEventRecord(side->ev[0], st) != hipSuccess ||
+                hipStreamWaitEvent(side->s[0], side->ev[0], 0) != hipSuccess ||
+                hipStreamWaitEvent(side->s[1], side->ev[0], 0) != hipSuccess) {
+                set_error("batched ID: stream ordering failed");
+                return IDS_EHIP;
+            }
+            s512 = side->s[0];
+            s256 = side->s[1];
+        }
+        const int gq = k <= 32 ? 1 : (k <= 64 ? 2 : 4);
+        const size_t lds = sizeof(double) * (size_t)k * (gq * TRSM_AX_SQ + 1);
+        auto solve = [&](hipStream_t ss, int nlo, int nhi) {
+            if (gq == 1)
+                hipLaunchKernelGGL(batched_trsm_kernel<1>, dim3((unsigned)nprob), dim3(BT_THREADS), lds, ss, a, nlo,
+                                   nhi);
+            else if (gq == 2)
+                hipLaunchKernelGGL(batched_trsm_kernel<2>, dim3((unsigned)nprob), dim3(BT_THREADS), lds, ss, a, nlo,
+                                   nhi);
+            else
+                hipLaunchKernelGGL(batched_trsm_kernel<4>, dim3((unsigned)nprob), dim3(BT_THREADS), lds, ss, a, nlo,
+                                   nhi);
+        };
         hipLaunchKernelGGL(batched_cpqr_kernel<1024>, dim3((unsigned)nprob), dim3(1024),
                            sizeof(float) * BC_RL * 1024, st, a, 512);
         hipLaunchKernelGGL(batched_cpqr_kernel<512>, dim3((unsigned)nprob), dim3(512), sizeof(float) * BC_RL * 512,
-                           st, a, 256);
+                           s512, a, 256);
         hipLaunchKernelGGL(batched_cpqr_kernel<256>, dim3((unsigned)nprob), dim3(256), sizeof(float) * BC_RL * 256,
-                           st, a, 0);
-    }
-    {
-        ProfScope ps(PK_TRSM, st);
-        const int gq = k <= 32 ? 1 : (k <= 64 ? 2 : 4);
-        const size_t lds = sizeof(double) * (size_t)k * (gq * TRSM_AX_SQ + 1);
-        if (gq == 1)
-            hipLaunchKernelGGL(batched_trsm_kernel<1>, dim3((unsigned)nprob), dim3(BT_THREADS), lds, st, a);
-        else if (gq == 2)
-            hipLaunchKernelGGL(batched_trsm_kernel<2>, dim3((unsigned)nprob), dim3(BT_THREADS), lds, st, a);
-        else
-            hipLaunchKernelGGL(batched_trsm_kernel<4>, dim3((unsigned)nprob), dim3(BT_THREADS), lds, st, a);
+                           s256, a, 0);
+        solve(st, 512, 1024);
+        solve(s512, 256, 512);
+        solve(s256, 0, 256);
+        if (side) {
+            if (hipEventRecord(side->ev[1], side->s[0]) != hipSuccess ||
+                hipEventRecord(side->ev[2], side->s[1]) != hipSuccess ||
+                hipStreamWaitEvent(st, side->ev[1], 0) != hipSuccess ||
+                hipStreamWaitEvent(st, side->ev[2], 0) != hipSuccess) {
+                set_error("batched ID: stream ordering failed");
+                return IDS_EHIP;
+            }
+        }
     }
     return check_launch("batched ID");
 }
