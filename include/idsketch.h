@@ -198,7 +198,10 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
  *                     ids_batched_plan_size() bytes; synchronises `stream`
  *                     once; returns the workspace size id_batched needs.
  *                     m, n are HOST arrays.
- *   id_batched        asynchronous; tol = 0: rank k for every problem; 0 < tol
+ *   id_batched        asynchronous on `stream` (its CPQR and solve fork onto two
+ *                     library-owned streams per device and join back through
+ *                     events before it returns, so work queued on `stream`
+ *                     afterwards sees the results); tol = 0: rank k for every problem; 0 < tol
  *                     < 1: fixed accuracy (the natural rank-revealing stop of
  *                     Algorithm 1's pivoted QR): problem p stops at the first
  *                     step t with |r_tt| <= tol |r_11| and k_eff_p = t <= k.
