@@ -138,13 +138,52 @@ __device__ __forceinline__ void wave_bucket_rank(uint32_t b, bool valid, int nbi
     same = __popcll(peers);
 }
 
-// one wave per segment: stable placement (rows of a bucket in increasing order)
-__global__ __launch_bounds__(64) void plan_place_kernel(PlanArgs a) {
+constexpr int PLAN_FUSED_L = 1024;  // up to this many buckets the placement scans the totals itself
+
+// one wave per segment: stable placement (rows of a bucket in increasing order).
+// With tot != nullptr (few buckets) the bucket offsets are not read from off[]
+// but scanned from the bucket totals by every workgroup (the first one also
+// stores them to off[]), which saves the separate offsets launch.
+__global__ __launch_bounds__(64) void plan_place_kernel(PlanArgs a, const int32_t* tot) {
     extern __shared__ int32_t run[];
     const int s = blockIdx.x;
     const int lane = threadIdx.x;
     const int nbits = (a.L > 1) ? 32 - __builtin_clz(a.L - 1) : 0;
-    {
+    if (tot) {
+        // lane: the buckets [b0, b1), at most PLAN_FUSED_L / 64 of them, all
+        // loaded together from clamped indices
+        constexpr int CBM = PLAN_FUSED_L / 64;
+        const uint32_t cb = (a.L + 63) / 64;
+        const uint32_t b0 = min(a.L, lane * cb), b1 = min(a.L, b0 + cb);
+        int32_t tv[CBM], sv[CBM];
+#pragma unroll
+        for (int u = 0; u < CBM; ++u) {
+            const uint32_t bb = min(b0 + u, a.L - 1);
+            tv[u] = tot[bb];
+            sv[u] = a.seg[(int64_t)bb * a.nseg + s];
+        }
+        asm volatile("" ::: "memory");
+        int32_t sum = 0;
+#pragma unroll
+        for (int u = 0; u < CBM; ++u) sum += (b0 + u < b1) ? tv[u] : 0;
+        int32_t x = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        int32_t base = x - sum;  // exclusive prefix of this lane's chunk
+#pragma unroll
+        for (int u = 0; u < CBM; ++u) {
+            const uint32_t b = b0 + u;
+            if (b < b1) {
+                if (s == 0) a.off[b] = base;
+                run[b] = base + sv[u];
+                base += tv[u];
+            }
+        }
+        if (s == 0 && lane == 0) a.off[a.L] = (int32_t)a.m;
+    } else {
         constexpr int U = 8;  // loads in flight per lane
         for (uint32_t b0 = 0; b0 < a.L; b0 += 64 * U) {
             int32_t o[U], c[U];
@@ -311,8 +350,12 @@ ids_status plan_build(const PlanShape& ps, uint64_t key, const int64_t* fr_pi, c
     size_t lds = sizeof(int32_t) * (size_t)ps.L;
     hipLaunchKernelGGL(plan_count_kernel, dim3(ps.nseg), dim3(64), lds, st, a);
     hipLaunchKernelGGL(plan_rowscan_kernel, dim3((unsigned)ps.L), dim3(64), 0, st, a, pb.tot);
-    hipLaunchKernelGGL(plan_offsets_kernel, dim3(1), dim3(1024), 0, st, a, (const int32_t*)pb.tot);
-    hipLaunchKernelGGL(plan_place_kernel, dim3(ps.nseg), dim3(64), lds, st, a);
+    if (ps.L <= PLAN_FUSED_L) {  // offsets scanned inside the placement
+        hipLaunchKernelGGL(plan_place_kernel, dim3(ps.nseg), dim3(64), lds, st, a, (const int32_t*)pb.tot);
+    } else {
+        hipLaunchKernelGGL(plan_offsets_kernel, dim3(1), dim3(1024), 0, st, a, (const int32_t*)pb.tot);
+        hipLaunchKernelGGL(plan_place_kernel, dim3(ps.nseg), dim3(64), lds, st, a, (const int32_t*)nullptr);
+    }
     return check_launch("countsketch plan");
 }
 
