@@ -4,12 +4,12 @@
  *
  * The method (Malik & Becker, "Fast randomized matrix and tensor
  * interpolative decomposition using CountSketch"):
- *   matrix ID  A ~= A[:, J] P      (problem statement, Section 1.3.1)
+ *   matrix ID  A ~= A[:, J] P      (problem statement, Section 1.2.1)
  *     Algorithm 2: draw a CountSketch S, form Y = S A implicitly, then run
  *     Algorithm 1 (rank-K column-pivoted QR of Y, J from the pivots,
  *     P = [I, R11^{-1} R12] Pi^T) on Y.  This library optionally inserts a
  *     Gaussian projection Y = G (S A) between the two stages.
- *   tensor ID  X_hat = sum_k lambda_hat_k X^(j_k)   (Section 1.3.2, eq. X*)
+ *   tensor ID  X_hat = sum_k lambda_hat_k X^(j_k)   (Section 1.2.2, eq. X*)
  *     Algorithm 3: TensorSketch Y = T M of the implicit matrix
  *     M = (Khatri-Rao of the factors) diag(lambda) via per-mode CountSketch,
  *     FFT, Hadamard product and inverse FFT; Algorithm 1 on Y; then
@@ -92,8 +92,8 @@ typedef struct {
 
 /*
  * id_sketch -- Algorithm 2, "draw S" and "compute Y = S A implicitly"
- * (CountSketch, Section 1.4), optionally followed by the Gaussian projection
- * of the sketch (Section 1.3.1).
+ * (CountSketch, Section 1.3), optionally followed by the Gaussian projection
+ * of the sketch (Section 1.2.1).
  *   A      matrix descriptor (device data).
  *   cfg    sketch configuration.
  *   Y      output, l x n, COLUMN-major with leading dimension ldy >= l
@@ -118,7 +118,7 @@ ids_status id_project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void
 /*
  * id_gaussian_sketch -- the Gaussian sketch Y = Omega A of a dense matrix:
  * the sketch of the Gaussian ID the paper compares its method with (Section
- * 1.3.1; Table 1), here as a same-GPU baseline.  Computed on the matrix cores
+ * 1.2.1; Table 1), here as a same-GPU baseline.  Computed on the matrix cores
  * (FP64 or FP32 MFMA) with the m dimension split over workgroups and the
  * partial products summed in a fixed order (deterministic).
  *   A      dense row-major m x n, IDS_F64 or IDS_F32 (A->fmt IDS_DENSE).
@@ -160,7 +160,7 @@ ids_status id_select(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t r
  *   Jlen     TensorSketch length L (power of two, 16 <= Jlen <= 4096).
  *   k        target rank, k < R, k <= Jlen.
  *   l, G     optional Gaussian second stage (the Gaussian sketch of Section
- *            1.3.1 applied to the TensorSketch): l = 0 factors T M itself
+ *            1.2.1 applied to the TensorSketch): l = 0 factors T M itself
  *            (Algorithm 3 as printed); k <= l <= Jlen factors G (T M), G an
  *            l x Jlen row-major FP64 device buffer (caller-owned, e.g. N(0,1)
  *            entries; NULL is an error when l > 0).

@@ -11,10 +11,10 @@ summation order).  This module loads it with ctypes, marshals numpy arrays, and
 holds the error evaluators (numpy, float64 / long double).
 
 Paper map:
-  * CountSketch S = Phi D and Y = S A ......... Section 1.4, Algorithm 2
-  * Gaussian sketch of the sketch ............. Section 1.3.1 (Gaussian ID)
+  * CountSketch S = Phi D and Y = S A ......... Section 1.3, Algorithm 2
+  * Gaussian sketch of the sketch ............. Section 1.2.1 (Gaussian ID)
   * rank-K CPQR, R11^{-1} R12, P ............... Algorithm 1 (+ CPQR remark)
-  * TensorSketch T, eq. for T A via (*) ........ Section 1.4, Algorithm 3
+  * TensorSketch T, eq. for T A via (*) ........ Section 1.3, Algorithm 3
   * lambda_hat_k = lambda_{j_k} sum_r p_kr ...... Section 4, Algorithm 3
   * modified hash h~ = f o pi .................. Remark 2, Proposition 4
 """
@@ -92,7 +92,7 @@ def stream(seed: int, tag: int, m: int) -> np.ndarray:
 
 
 def hash_maps(seed: int, tag: int, m: int, L: int):
-    """CountSketch maps (h, D) of Section 1.4 from the seeded stream."""
+    """CountSketch maps (h, D) of Section 1.3 from the seeded stream."""
     b = np.empty(m, dtype=np.int32)
     s = np.empty(m, dtype=np.int8)
     lib().orc_hash(c_u64(seed), c_u64(tag), c_i64(m), c_i64(L), _p(b), _p(s))
@@ -145,7 +145,7 @@ def gemm(G, B) -> np.ndarray:
 
 
 def gaussian_id(A, k: int, Omega, blas: bool = False, trace: bool = False):
-    """The Gaussian-sketch ID the paper compares with (Section 1.3.1): Y = Omega A,
+    """The Gaussian-sketch ID the paper compares with (Section 1.2.1): Y = Omega A,
     then Algorithm 1.  blas=True forms Y with numpy's FP64 matmul (a library
     primitive) for inputs too large for the plain triple loop."""
     if blas:
@@ -265,7 +265,7 @@ def tensor_maps(seed: int, dims, Jlen: int):
 
 def tensor_id(factors, lam, *, k: int, Jlen: int, seed: int, G=None, trace: bool = False):
     """Algorithm 3; with G (l x Jlen) the Gaussian second stage G (T M) is
-    factored instead of T M (Section 1.3.1's Gaussian sketch on the sketch)."""
+    factored instead of T M (Section 1.2.1's Gaussian sketch on the sketch)."""
     maps = tensor_maps(seed, [f.shape[0] for f in factors], Jlen)
     Y = tensorsketch(factors, lam, maps, Jlen)
     Yf = Y if G is None else gemm(G, Y)
@@ -294,9 +294,14 @@ def residual_fro(A, J, P, chunk: int = 65536) -> float:
 
 
 def residual_fro_csr(rowptr, colind, val, n, J, P) -> float:
+    """||A - A[:, J] P||_F / ||A||_F for A in CSR form, without forming the
+    m x n difference."""
     import scipy.sparse as sp
     A = sp.csr_matrix((np.asarray(val, np.float64), np.asarray(colind), np.asarray(rowptr)),
                       shape=(len(rowptr) - 1, n))
+    # a CSR matrix with repeated (row, col) entries stands for their sum (the
+    # definition CountSketch is applied to); ||A||_F needs the summed entries
+    A.sum_duplicates()
     J = np.asarray(J)
     keep = J >= 0
     AJ = A[:, J[keep]]

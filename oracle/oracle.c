@@ -23,7 +23,7 @@
 /* ------------------------------------------------------------------------
  * Counter-based hash stream (SplitMix64, Steele, Lea & Flood, OOPSLA 2014).
  * The paper only requires h(i) iid uniform on [L] and iid +-1 signs
- * (Section 1.4, CountSketch definition); the concrete generator is this
+ * (Section 1.3, CountSketch definition); the concrete generator is this
  * library's choice and is written here from the SplitMix64 publication:
  *   state_i = key + (i+1) * 0x9e3779b97f4a7c15
  *   z_i     = mix64(state_i)
@@ -50,7 +50,7 @@ void orc_stream(uint64_t seed, uint64_t tag, int64_t m, uint64_t* z) {
         z[i] = orc_mix64(key + (uint64_t)(i + 1) * 0x9e3779b97f4a7c15ULL);
 }
 
-/* The CountSketch maps h : [m] -> [L] and D = diag(+-1) (Section 1.4). */
+/* The CountSketch maps h : [m] -> [L] and D = diag(+-1) (Section 1.3). */
 void orc_hash(uint64_t seed, uint64_t tag, int64_t m, int64_t L,
               int32_t* bucket, int8_t* sign) {
     uint64_t key = orc_stream_key(seed, tag);
@@ -74,7 +74,7 @@ void orc_fullrank_hash(int64_t m, int64_t L, const int64_t* pi, const int32_t* x
 }
 
 /* ------------------------------------------------------------------------
- * CountSketch Y = S A = Phi D A (Section 1.4; Algorithm 2, step "compute
+ * CountSketch Y = S A = Phi D A (Section 1.3; Algorithm 2, step "compute
  * sketch"): every row i of A, multiplied by its sign, is added into row
  * h(i) of Y.  Rows are visited in increasing i.
  * A is m x n row-major with leading dimension lda; Y is L x n row-major.
@@ -106,7 +106,7 @@ void orc_countsketch_csr(int64_t m, int64_t n, const int64_t* rowptr,
 }
 
 /* Plain product C = G B, G l x q, B q x n, all row-major: the second-stage
- * Gaussian projection of the sketch (Section 1.3.1, Gaussian sketch). */
+ * Gaussian projection of the sketch (Section 1.2.1, Gaussian sketch). */
 void orc_gemm(int64_t l, int64_t q, int64_t n, const double* G, const double* B,
               double* C) {
     for (int64_t i = 0; i < l; ++i)
@@ -119,7 +119,7 @@ void orc_gemm(int64_t l, int64_t q, int64_t n, const double* G, const double* B,
 
 /* ------------------------------------------------------------------------
  * Matrix ID via rank-K column-pivoted QR (Algorithm 1, with column-pivoted
- * QR in place of strong RRQR as the paper does in practice, Section 1.3.1).
+ * QR in place of strong RRQR as the paper does in practice, Section 1.2.1).
  *
  * Input Y: l x n row-major.  For t = 0..k-1:
  *   nu_j = sum_{i>=t} Y[i][j]^2 for every column j not yet chosen
@@ -221,7 +221,7 @@ int64_t orc_cpqr_id(int64_t l, int64_t n, int64_t k, const double* Y,
 
 /* ------------------------------------------------------------------------
  * TensorSketch of M = (Khatri-Rao of the factor matrices) diag(lambda)
- * (eq. for M; TensorSketch definition with H and S, Section 1.4).
+ * (eq. for M; TensorSketch definition with H and S, Section 1.3).
  * Column r of T M is lambda_r * (c_1 (*) c_2 (*) ... (*) c_N), where
  * c_n = S^(n) a^(n)_r is the mode-n CountSketch of column r of factor n and
  * (*) is circular convolution of length Jlen.  The convolution is evaluated

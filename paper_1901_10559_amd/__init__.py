@@ -8,8 +8,8 @@ missing or no GPU is present, calls raise.
 
 Method (Malik & Becker, "Fast randomized matrix and tensor interpolative
 decomposition using CountSketch"):
-  * :func:`id_sketch`  -- Algorithm 2, CountSketch Y1 = S A (Section 1.4), with
-    an optional Gaussian projection Y = G Y1 (Section 1.3.1).
+  * :func:`id_sketch`  -- Algorithm 2, CountSketch Y1 = S A (Section 1.3), with
+    an optional Gaussian projection Y = G Y1 (Section 1.2.1).
   * :func:`id_select`  -- Algorithm 1 on a sketch: rank-k column-pivoted QR,
     J and P = [I, R11^{-1} R12] Pi^T.
   * :func:`matrix_id`  -- the two above in sequence.

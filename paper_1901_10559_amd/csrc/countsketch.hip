@@ -1,4 +1,4 @@
-// CountSketch Y1 = S A = Phi D A (Section 1.4; Algorithm 2, "compute the
+// CountSketch Y1 = S A = Phi D A (Section 1.3; Algorithm 2, "compute the
 // sketch implicitly") for dense row-major and CSR matrices on gfx950.
 //
 // Design (bucket owner, no atomics for dense input):

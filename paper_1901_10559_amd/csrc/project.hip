@@ -1,5 +1,5 @@
 // Second sketch stage Y = G Y1 (Gaussian projection of the CountSketch,
-// Section 1.3.1) on the matrix cores: v_mfma_f64_16x16x4f64 (FP64) and
+// Section 1.2.1) on the matrix cores: v_mfma_f64_16x16x4f64 (FP64) and
 // v_mfma_f32_16x16x4f32 (FP32).  64x64 output tile per 256-thread workgroup,
 // each wave a 32x32 quadrant of 2x2 16x16 MFMA blocks; K staged through LDS in
 // slices of 64 (FP32) or 32 (FP64), the next slice prefetched into registers.  The output is written column-major (column j of Y

@@ -1,5 +1,5 @@
 // TensorSketch of the implicit matrix M = (Khatri-Rao of the factors) diag(lambda)
-// (TensorSketch definition and the FFT formula for T A, Section 1.4;
+// (TensorSketch definition and the FFT formula for T A, Section 1.3;
 // Algorithm 3).  Column r of T M is lambda_r times the circular convolution of
 // the per-mode CountSketches c_n = S^(n) a^(n)_r, evaluated as
 // IFFT( prod_n FFT(c_n) ).

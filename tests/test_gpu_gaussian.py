@@ -1,5 +1,5 @@
 """GPU parity of the Gaussian-sketch ID (the comparison method of the paper,
-Section 1.3.1 and Table 1) built from the same CPQR: Y = Omega A on the matrix
+Section 1.2.1 and Table 1) built from the same CPQR: Y = Omega A on the matrix
 cores with the m dimension split over workgroups, against the FP64 oracle."""
 import numpy as np
 import pytest

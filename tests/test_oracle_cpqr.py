@@ -1,5 +1,5 @@
 """Pins of the oracle's rank-K column-pivoted QR and interpolation matrix
-(Algorithm 1; Fact 1; the CPQR remark in Section 1.3.1)."""
+(Algorithm 1; Fact 1; the CPQR remark in Section 1.2.1)."""
 import itertools
 
 import numpy as np

@@ -1,4 +1,4 @@
-"""Pins of the oracle's random maps (CountSketch h and D, Section 1.4; modified
+"""Pins of the oracle's random maps (CountSketch h and D, Section 1.3; modified
 hash h~, Remark 2 / Proposition 4) against published values, closed forms and
 statistics."""
 import os

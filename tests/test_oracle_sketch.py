@@ -1,4 +1,4 @@
-"""Pins of the oracle's CountSketch (Section 1.4) and of its plain product."""
+"""Pins of the oracle's CountSketch (Section 1.3) and of its plain product."""
 import numpy as np
 import pytest
 
@@ -7,7 +7,7 @@ import synth
 
 
 def explicit_S(bucket, sign, L):
-    """The CountSketch matrix S = Phi D written out (Section 1.4)."""
+    """The CountSketch matrix S = Phi D written out (Section 1.3)."""
     m = bucket.shape[0]
     S = np.zeros((L, m))
     S[bucket, np.arange(m)] = sign

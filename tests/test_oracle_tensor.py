@@ -1,4 +1,4 @@
-"""Pins of the oracle's TensorSketch (Section 1.4), s-value update
+"""Pins of the oracle's TensorSketch (Section 1.3), s-value update
 (Section 4, Algorithm 3) and tensor error evaluator (Gram identity)."""
 import itertools
 
