@@ -53,7 +53,15 @@ enum {
     IDS_EDTYPE = 2,      /* unsupported dtype combination */
     IDS_EWORKSPACE = 3,  /* workspace missing, too small or misaligned */
     IDS_EHIP = 4,        /* a HIP runtime call failed (message has details) */
-    IDS_ETIMEOUT = 5     /* a device-wide barrier gave up (never expected) */
+    /* codes written to a device status word (never returned by a call): */
+    IDS_ETIMEOUT = 5,    /* a device-wide wait of the pivoted QR gave up; k_eff = -1,
+                            J, P and lambda_hat are undefined (never expected unless
+                            forced with ids_set_wait_limit(0)) */
+    IDS_ERANKDEF = 6,    /* the pivoted QR met a zero trailing norm before step k
+                            (rank deficiency, Fact 1 needs K < rank): k_eff < k, the
+                            rank-k_eff ID is returned */
+    IDS_ENONFINITE = 7   /* a non-finite value (NaN, infinity, or a column norm that
+                            overflows) in the sketch; results are undefined */
 };
 
 /* element types */
@@ -62,6 +70,9 @@ enum { IDS_F64 = 0, IDS_F32 = 1, IDS_BF16 = 2 };
 enum { IDS_DENSE = 0, IDS_CSR = 1 };
 /* ids_sketch_cfg.flags */
 #define IDS_HASH_FULLRANK 1u /* modified map h~ = f o pi (Remark 2, Prop. 4) */
+#define IDS_CHECK_FINITE 2u  /* scan the finished sketch Y and write IDS_OK or
+                                IDS_ENONFINITE to cfg->status (a NaN or infinity
+                                anywhere in A reaches Y through its bucket) */
 
 typedef struct {
     int32_t fmt;            /* IDS_DENSE: row-major m x n, leading dim ld (elements)
@@ -88,6 +99,7 @@ typedef struct {
                             /* ignored when l == l1                                */
     const int64_t* fr_pi;   /* IDS_HASH_FULLRANK: permutation pi of [0, m)        */
     const int32_t* fr_x;    /* IDS_HASH_FULLRANK: x[q] in [0, l1) for q >= l1     */
+    int32_t* status;        /* IDS_CHECK_FINITE: device int32 status word          */
 } ids_sketch_cfg;
 
 /*
@@ -98,9 +110,12 @@ typedef struct {
  *   cfg    sketch configuration.
  *   Y      output, l x n, COLUMN-major with leading dimension ldy >= l
  *          (entry (i, j) at Y[j*ldy + i]); element type ydt = cfg->acc.
- * Workspace: ids_sketch_workspace_size().  Deterministic: the same inputs
- * give bitwise-identical Y (rows of a bucket are added in increasing row
- * order, the order of the textbook definition).
+ * Workspace: ids_sketch_workspace_size().  Dense A is deterministic: the same
+ * inputs give bitwise-identical Y (rows of a bucket are added in increasing
+ * row order, the order of the textbook definition).  CSR A is summed with
+ * atomic adds whose order is not fixed: Y can differ between runs by
+ * rounding (FP64, a few ulps of the bucket sums), and is exact whenever the
+ * sums are (e.g. integer-valued entries).
  */
 ids_status ids_sketch_workspace_size(const ids_matrix* A, const ids_sketch_cfg* cfg,
                                      size_t* bytes);
@@ -144,12 +159,36 @@ ids_status id_gaussian_sketch(const ids_matrix* A, int64_t l, const void* Omega,
  *   J      int64[k]   chosen columns (entries >= k_eff are set to -1).
  *   P      double[k*n] row-major (rows >= k_eff are zero).
  *   k_eff  int64[1]   number of pivots taken: k unless a zero trailing norm
- *          (rank deficiency) stopped the factorisation early.
+ *          (rank deficiency) stopped the factorisation early; -1 if a
+ *          device-wide wait gave up.
+ *   status int32[1] device status word or NULL: IDS_OK, IDS_ERANKDEF
+ *          (k_eff < k), IDS_ENONFINITE or IDS_ETIMEOUT (then k_eff = -1 and
+ *          J, P are undefined).  Valid once the stream has been synchronised.
  */
 ids_status ids_select_workspace_size(int64_t l, int64_t n, int64_t k, size_t* bytes);
 ids_status id_select(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t rs, int64_t cs,
-                     int64_t k, int64_t* J, double* P, int64_t* k_eff, void* ws,
+                     int64_t k, int64_t* J, double* P, int64_t* k_eff, int32_t* status, void* ws,
                      size_t ws_bytes, void* stream);
+
+/*
+ * ids_select_plan_info -- how id_select runs a shape (host only, nothing is
+ * launched): info[0] kernel family (0: grouped lanes, l <= 256; 1: row
+ * bands), info[1] candidate exchange (0: speculative column slots; 1: the
+ * owner publishes the winner's column after the vote), info[2] workgroups,
+ * info[3] candidate publishers per pivot step.  int32 info[4], host memory.
+ */
+ids_status ids_select_plan_info(int64_t l, int64_t n, int64_t k, int32_t* info);
+
+/*
+ * ids_set_wait_limit -- polls after which a device-wide wait of the pivoted
+ * QR gives up (default 2^20, far beyond any normal wait; polls < 0 restores
+ * it).  0 treats the exchange as expired from the start: every wait gives up
+ * as soon as it finds data missing and the factorisation reports
+ * IDS_ETIMEOUT, k_eff = -1 -- a host-forced test of the give-up path (the
+ * kernels still finish their bounded loops).  Applies to calls made after it,
+ * process-wide.
+ */
+void ids_set_wait_limit(int64_t polls);
 
 /*
  * tensor_id -- Algorithm 3 for an N-way CP tensor (eq. def-X-tensor) with R
@@ -166,8 +205,8 @@ ids_status id_select(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t r
  *            entries; NULL is an error when l > 0).
  *   Y        optional output (may be NULL): the sketch T M, Jlen x R
  *            column-major (leading dimension Jlen), before any projection.
- *   J, P, k_eff  as in id_select; lambda_hat double[k] (entries >= k_eff
- *            are zero).
+ *   J, P, k_eff, status  as in id_select; lambda_hat double[k] (entries >=
+ *            k_eff are zero).
  * Random maps h_n, s_n: stream (seed, tag n + 1) over [0, I_n) into Jlen.
  */
 ids_status ids_tensor_workspace_size(int32_t N, const int64_t* dims, int64_t R, int64_t k,
@@ -175,8 +214,8 @@ ids_status ids_tensor_workspace_size(int32_t N, const int64_t* dims, int64_t R, 
 ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* const* factors,
                      const int64_t* ld, const double* lambda, int64_t k, int64_t Jlen,
                      int64_t l, const double* G, uint64_t seed, double* Y, int64_t* J,
-                     double* P, double* lambda_hat, int64_t* k_eff, void* ws, size_t ws_bytes,
-                     void* stream);
+                     double* P, double* lambda_hat, int64_t* k_eff, int32_t* status, void* ws,
+                     size_t ws_bytes, void* stream);
 
 /*
  * Batched mixed-precision matrix ID (hierarchical-matrix style block
@@ -207,8 +246,11 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
  *                     step t with |r_tt| <= tol |r_11| and k_eff_p = t <= k.
  *                     J int64[nprob*k] (J_p at p*k, -1 past
  *                     k_eff_p), P double[k * sum n_p] (P_p, k x n_p row-major,
- *                     at k * sum_{q<p} n_q), k_eff int64[nprob].  The plan, m
- *                     and n must be the ones the plan was built from.
+ *                     at k * sum_{q<p} n_q), k_eff int64[nprob], status
+ *                     int32[nprob] or NULL (per problem: IDS_OK, IDS_ERANKDEF
+ *                     when a zero trailing norm stopped it before its rank,
+ *                     IDS_ENONFINITE).  The plan, m and n must be the ones the
+ *                     plan was built from.
  */
 ids_status ids_batched_plan_size(int64_t nprob, size_t* bytes);
 ids_status ids_batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, int64_t k, int64_t l,
@@ -216,7 +258,8 @@ ids_status ids_batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, i
                             void* stream);
 ids_status id_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* plan, int64_t k,
                       int64_t l, int64_t l1max, uint64_t seed, double tol, const void* A, const void* G,
-                      int64_t* J, double* P, int64_t* k_eff, void* ws, size_t ws_bytes, void* stream);
+                      int64_t* J, double* P, int64_t* k_eff, int32_t* status, void* ws, size_t ws_bytes,
+                      void* stream);
 
 /*
  * Stage timing.  While enabled, every call records a pair of HIP events on its
@@ -234,6 +277,12 @@ void ids_profile_enable(int on);
 ids_status ids_profile_stages(const char* stages);
 ids_status ids_profile_read(const char* stage, double* total_ms, int64_t* count);
 void ids_profile_reset(void);
+
+/* ids_finalize -- release what the library holds between calls (the side
+ * streams of id_batched, the stage-timing events), after the work queued on
+ * them has finished.  Optional; later calls recreate what they need.  Call it
+ * before the HIP runtime is torn down (e.g. from an atexit handler). */
+void ids_finalize(void);
 
 /* Human-readable name of a status code, and the calling thread's last error
  * message (empty string when the last call succeeded). */

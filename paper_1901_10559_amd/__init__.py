@@ -18,11 +18,15 @@ decomposition using CountSketch"):
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 
-__all__ = ["lib", "lib_path", "BatchedPlan", "batched_plan", "id_batched", "profile_enable", "profile_stages", "profile_read", "profile_reset", "id_sketch", "id_project", "id_select", "matrix_id", "tensor_id", "gaussian_sketch", "gaussian_id",
-           "IdsError", "F64", "F32", "BF16", "HASH_FULLRANK", "EXPORTED"]
+__all__ = ["lib", "lib_path", "BatchedPlan", "batched_plan", "id_batched", "profile_enable", "profile_stages",
+           "profile_read", "profile_reset", "id_sketch", "id_project", "id_select",
+           "matrix_id", "tensor_id", "gaussian_sketch", "gaussian_id", "check_status", "set_wait_limit", "select_plan_info",
+           "finalize", "IdsError", "F64", "F32", "BF16", "HASH_FULLRANK", "CHECK_FINITE", "EXPORTED",
+           "OK", "ETIMEOUT", "ERANKDEF", "ENONFINITE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libidsketch.so")
@@ -30,12 +34,15 @@ lib_path = os.path.join(_HERE, "libidsketch.so")
 F64, F32, BF16 = 0, 1, 2
 DENSE, CSR = 0, 1
 HASH_FULLRANK = 1
+CHECK_FINITE = 2
+# status codes (returned by calls: 0..4; written to device status words: 0, 5..7)
+OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ETIMEOUT, ERANKDEF, ENONFINITE = range(8)
 
 EXPORTED = ["ids_sketch_workspace_size", "id_sketch", "id_project", "ids_gaussian_workspace_size",
             "id_gaussian_sketch", "ids_select_workspace_size",
-            "id_select", "ids_tensor_workspace_size", "tensor_id", "ids_batched_plan_size", "ids_batched_plan",
-            "id_batched", "ids_profile_enable", "ids_profile_stages", "ids_profile_read",
-            "ids_profile_reset", "ids_status_string", "ids_last_error"]
+            "id_select", "ids_set_wait_limit", "ids_select_plan_info", "ids_tensor_workspace_size", "tensor_id",
+            "ids_batched_plan_size", "ids_batched_plan", "id_batched", "ids_profile_enable", "ids_profile_stages",
+            "ids_profile_read", "ids_profile_reset", "ids_finalize", "ids_status_string", "ids_last_error"]
 
 c_i64 = ctypes.c_int64
 c_i32 = ctypes.c_int32
@@ -52,7 +59,7 @@ class IdsMatrix(ctypes.Structure):
 
 class IdsSketchCfg(ctypes.Structure):
     _fields_ = [("l1", c_i64), ("l", c_i64), ("seed", c_u64), ("tag", c_u64), ("flags", c_u32),
-                ("acc", c_i32), ("proj", c_i32), ("G", c_vp), ("fr_pi", c_vp), ("fr_x", c_vp)]
+                ("acc", c_i32), ("proj", c_i32), ("G", c_vp), ("fr_pi", c_vp), ("fr_x", c_vp), ("status", c_vp)]
 
 
 class IdsError(RuntimeError):
@@ -76,14 +83,21 @@ def lib():
         L.ids_gaussian_workspace_size.argtypes = [P(IdsMatrix), c_i64, P(c_sz)]
         L.id_gaussian_sketch.argtypes = [P(IdsMatrix), c_i64, c_vp, c_vp, c_i64, c_vp, c_sz, c_vp]
         L.ids_select_workspace_size.argtypes = [c_i64, c_i64, c_i64, P(c_sz)]
-        L.id_select.argtypes = [c_vp, c_i32, c_i64, c_i64, c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]
+        L.id_select.argtypes = [c_vp, c_i32, c_i64, c_i64, c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz,
+                                c_vp]
+        L.ids_select_plan_info.argtypes = [c_i64, c_i64, c_i64, c_vp]
+        L.ids_select_plan_info.restype = c_i32
+        L.ids_set_wait_limit.argtypes = [c_i64]
+        L.ids_set_wait_limit.restype = None
+        L.ids_finalize.argtypes = []
+        L.ids_finalize.restype = None
         L.ids_tensor_workspace_size.argtypes = [c_i32, c_vp, c_i64, c_i64, c_i64, c_i64, P(c_sz)]
         L.tensor_id.argtypes = [c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_u64, c_vp, c_vp, c_vp,
-                                c_vp, c_vp, c_vp, c_sz, c_vp]
+                                c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]
         L.ids_batched_plan_size.argtypes = [c_i64, P(c_sz)]
         L.ids_batched_plan.argtypes = [c_i64, c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_sz, P(c_sz), c_vp]
-        L.id_batched.argtypes = [c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_u64, ctypes.c_double, c_vp, c_vp, c_vp, c_vp, c_vp,
-                                 c_vp, c_sz, c_vp]
+        L.id_batched.argtypes = [c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_u64, ctypes.c_double, c_vp, c_vp, c_vp,
+                                 c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]
         for fn in ("ids_batched_plan_size", "ids_batched_plan", "id_batched"):
             getattr(L, fn).restype = c_i32
         L.ids_profile_enable.argtypes = [c_i32]
@@ -102,6 +116,8 @@ def lib():
                    "id_select", "ids_tensor_workspace_size", "tensor_id"):
             getattr(L, fn).restype = c_i32
         _lib = L
+        # release the library's streams and events before the HIP runtime goes
+        atexit.register(L.ids_finalize)
     return _lib
 
 
@@ -165,6 +181,41 @@ def _matrix_desc(A):
     return d, A.device
 
 
+def check_status(status, what: str = "idsketch"):
+    """Wait for the stream and raise IdsError if a device status word (a
+    tensor of int32 codes, e.g. the "status" entry of a result) reports
+    IDS_ETIMEOUT or IDS_ENONFINITE.  IDS_ERANKDEF is not an error: k_eff
+    tells the rank reached."""
+    torch = _torch()
+    torch.cuda.synchronize(status.device)
+    codes = set(int(c) for c in status.cpu().reshape(-1).tolist())
+    for bad in (ETIMEOUT, ENONFINITE):
+        if bad in codes:
+            L = lib()
+            raise IdsError(f"{what}: device status {L.ids_status_string(bad).decode()}")
+    return codes
+
+
+def select_plan_info(l: int, n: int, k: int) -> dict:
+    """How id_select runs an l x n, rank-k shape (kernel family, candidate
+    exchange, workgroups, publishers per step); host only."""
+    info = (c_i32 * 4)()
+    _check(lib().ids_select_plan_info(l, n, k, ctypes.cast(info, c_vp)), "ids_select_plan_info")
+    return {"family": "grouped_lanes" if info[0] == 0 else "row_bands",
+            "exchange": "speculative" if info[1] == 0 else "owner", "workgroups": info[2], "publishers": info[3]}
+
+
+def set_wait_limit(polls: int | None = None):
+    """Polls before a device-wide wait of the pivoted QR gives up (None: the
+    default; 0: give up at once -- a forced test of the timeout path)."""
+    lib().ids_set_wait_limit(-1 if polls is None else int(polls))
+
+
+def finalize():
+    """Release the library's streams and events (also done at exit)."""
+    lib().ids_finalize()
+
+
 def profile_enable(on: bool = True):
     """Record HIP events around every stage of subsequent calls."""
     lib().ids_profile_enable(1 if on else 0)
@@ -188,8 +239,10 @@ def profile_reset():
 
 
 def id_sketch(A, l1: int, l: int | None = None, *, seed: int = 0, tag: int = 0, G=None, acc: int | None = None,
-              fullrank=None, stream=None):
-    """Y = (G) S A, returned as an l x n view of a column-major buffer."""
+              fullrank=None, stream=None, check_finite=None):
+    """Y = (G) S A, returned as an l x n view of a column-major buffer.
+    check_finite: an int32 device tensor that receives IDS_OK or
+    IDS_ENONFINITE from a scan of Y (flag IDS_CHECK_FINITE)."""
     torch = _torch()
     desc, dev = _matrix_desc(A)
     if l is None:
@@ -201,8 +254,11 @@ def id_sketch(A, l1: int, l: int | None = None, *, seed: int = 0, tag: int = 0, 
     if fullrank is not None:
         pi, x = fullrank
         flags |= HASH_FULLRANK
+    if check_finite is not None:
+        flags |= CHECK_FINITE
     cfg = IdsSketchCfg(l1, l, seed, tag, flags, acc, acc, c_vp(G.data_ptr()) if G is not None else None,
-                       c_vp(pi.data_ptr()) if pi is not None else None, c_vp(x.data_ptr()) if x is not None else None)
+                       c_vp(pi.data_ptr()) if pi is not None else None, c_vp(x.data_ptr()) if x is not None else None,
+                       _ptr(check_finite))
     if G is not None and l < l1:
         if _dt(G) != acc or tuple(G.shape) != (l, l1) or not G.is_contiguous():
             raise IdsError("G must be a contiguous l x l1 tensor of the accumulation dtype")
@@ -250,16 +306,27 @@ def gaussian_sketch(A, Omega, stream=None):
     return Yb.t()
 
 
+def _status(torch, device, n: int = 1):
+    return torch.full((n,), -1, dtype=torch.int32, device=device)
+
+
 def gaussian_id(A, k: int, Omega, stream=None):
     """The Gaussian-sketch ID (comparison method): Y = Omega A, then Algorithm 1."""
     Y = gaussian_sketch(A, Omega, stream=stream)
-    J, P, keff = id_select(Y, k, stream=stream)
-    return dict(Y=Y, J=J, P=P, k_eff=keff)
+    st = _status(_torch(), Y.device)
+    J, P, keff = id_select(Y, k, stream=stream, status=st)
+    return dict(Y=Y, J=J, P=P, k_eff=keff, status=st)
 
 
-def id_select(Y, k: int, stream=None):
+def _ptr(t):
+    return c_vp(t.data_ptr()) if t is not None else None
+
+
+def id_select(Y, k: int, stream=None, status=None):
     """Algorithm 1 on a sketch Y (l x n, any strides).  Returns (J, P, k_eff)
-    where J (int64[k]), P (float64 k x n) and k_eff (int64[1]) are device tensors."""
+    where J (int64[k]), P (float64 k x n) and k_eff (int64[1]) are device
+    tensors; an int32 device tensor `status` (1 element), if given, receives
+    the device status word."""
     torch = _torch()
     l, n = Y.shape
     nbytes = c_sz(0)
@@ -269,21 +336,26 @@ def id_select(Y, k: int, stream=None):
     P = torch.empty((k, n), dtype=torch.float64, device=Y.device)
     keff = torch.empty(1, dtype=torch.int64, device=Y.device)
     _check(lib().id_select(c_vp(Y.data_ptr()), _dt(Y), l, n, Y.stride(0), Y.stride(1), k, c_vp(J.data_ptr()),
-                           c_vp(P.data_ptr()), c_vp(keff.data_ptr()), c_vp(ws[1]) if ws else None, wsb,
+                           c_vp(P.data_ptr()), c_vp(keff.data_ptr()), _ptr(status), c_vp(ws[1]) if ws else None, wsb,
                            _stream(torch, stream)), "id_select")
     return J, P, keff
 
 
 def matrix_id(A, k: int, l1: int, l: int | None = None, *, seed: int = 0, tag: int = 0, G=None,
-              acc: int | None = None, fullrank=None, stream=None):
-    """Algorithm 2 (+ optional projection), then Algorithm 1.  Returns dict."""
+              acc: int | None = None, fullrank=None, stream=None, check: bool = False):
+    """Algorithm 2 (+ optional projection), then Algorithm 1.  Returns dict
+    with Y, J, P, k_eff and the device status word ("status").  check=True
+    waits for the result and raises on IDS_ETIMEOUT / IDS_ENONFINITE."""
     Y = id_sketch(A, l1, l, seed=seed, tag=tag, G=G, acc=acc, fullrank=fullrank, stream=stream)
-    J, P, keff = id_select(Y, k, stream=stream)
-    return dict(Y=Y, J=J, P=P, k_eff=keff)
+    st = _status(_torch(), Y.device)
+    J, P, keff = id_select(Y, k, stream=stream, status=st)
+    if check:
+        check_status(st, "matrix_id")
+    return dict(Y=Y, J=J, P=P, k_eff=keff, status=st)
 
 
 def tensor_id(factors, lam, k: int, Jlen: int, *, seed: int = 0, l: int = 0, G=None, return_Y: bool = False,
-              stream=None):
+              stream=None, check: bool = False):
     """Algorithm 3.  factors: list of I_n x R float64 device tensors with unit
     row stride (column-major, e.g. ``F.t().contiguous().t()``).  l > 0 with an
     l x Jlen float64 G adds the Gaussian second stage before the CPQR."""
@@ -309,12 +381,15 @@ def tensor_id(factors, lam, k: int, Jlen: int, *, seed: int = 0, l: int = 0, G=N
     P = torch.empty((k, R), dtype=torch.float64, device=dev)
     lh = torch.empty(k, dtype=torch.float64, device=dev)
     keff = torch.empty(1, dtype=torch.int64, device=dev)
+    st = _status(torch, dev)
     _check(lib().tensor_id(N, ctypes.cast(dims, c_vp), R, ctypes.cast(fptr, c_vp), ctypes.cast(ld, c_vp),
                            c_vp(lam.data_ptr()), k, Jlen, l, c_vp(G.data_ptr()) if l else None, seed,
                            c_vp(Y.data_ptr()) if Y is not None else None,
                            c_vp(J.data_ptr()), c_vp(P.data_ptr()), c_vp(lh.data_ptr()), c_vp(keff.data_ptr()),
-                           c_vp(ws[1]) if ws else None, wsb, _stream(torch, stream)), "tensor_id")
-    out = dict(J=J, P=P, lambda_hat=lh, k_eff=keff)
+                           _ptr(st), c_vp(ws[1]) if ws else None, wsb, _stream(torch, stream)), "tensor_id")
+    if check:
+        check_status(st, "tensor_id")
+    out = dict(J=J, P=P, lambda_hat=lh, k_eff=keff, status=st)
     if Y is not None:
         out["Y"] = Y.t()
     return out
@@ -370,12 +445,13 @@ def id_batched(plan: BatchedPlan, A, G, seed: int = 0, tol: float = 0.0, stream=
     J = torch.empty((plan.nprob, plan.k), dtype=torch.int64, device=dev)
     P = torch.empty(int(plan.p_off[-1]), dtype=torch.float64, device=dev)
     keff = torch.empty(plan.nprob, dtype=torch.int64, device=dev)
+    st = _status(torch, dev, plan.nprob)
     _check(lib().id_batched(plan.nprob, c_vp(plan.m.ctypes.data), c_vp(plan.n.ctypes.data),
                             c_vp(plan.buf.data_ptr()), plan.k, plan.l, plan.l1max, seed, float(tol),
                             c_vp(A.data_ptr()),
                             c_vp(G.data_ptr()), c_vp(J.data_ptr()), c_vp(P.data_ptr()), c_vp(keff.data_ptr()),
-                            c_vp(ws[1]), wsb, _stream(torch, stream)), "id_batched")
-    out = dict(J=J, P=P, k_eff=keff)
+                            _ptr(st), c_vp(ws[1]), wsb, _stream(torch, stream)), "id_batched")
+    out = dict(J=J, P=P, k_eff=keff, status=st)
     if return_Y:
         # Y is the first region of the workspace (FP32, Y_p column-major l x n_p)
         ny = int(plan.y_off[-1])

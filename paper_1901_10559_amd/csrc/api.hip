@@ -65,7 +65,7 @@ static hipEvent_t prof_event() {
 
 ProfScope::ProfScope(int k, hipStream_t s) : kind(k), st(s), a(nullptr), on(false) {
     std::lock_guard<std::mutex> g(g_prof_mu);
-    if (!g_prof_on || !((g_prof_mask >> k) & 1u)) return;
+    if (k < 0 || !g_prof_on || !((g_prof_mask >> k) & 1u)) return;
     a = prof_event();
     if (a && hipEventRecord(a, st) == hipSuccess) on = true;
 }
@@ -125,7 +125,8 @@ static ids_status validate_sketch(const ids_matrix* A, const ids_sketch_cfg* c) 
         if (c->proj != c->acc) return fail(IDS_EDTYPE, "proj must equal acc");
         if (!c->G) return fail(IDS_EINVAL, "G is required when l < l1");
     }
-    if (c->flags & ~IDS_HASH_FULLRANK) return fail(IDS_EINVAL, "unknown flag bits");
+    if (c->flags & ~(IDS_HASH_FULLRANK | IDS_CHECK_FINITE)) return fail(IDS_EINVAL, "unknown flag bits");
+    if ((c->flags & IDS_CHECK_FINITE) && !c->status) return fail(IDS_EINVAL, "IDS_CHECK_FINITE needs status");
     if ((c->flags & IDS_HASH_FULLRANK) && (!c->fr_pi || !c->fr_x))
         return fail(IDS_EINVAL, "IDS_HASH_FULLRANK needs fr_pi and fr_x");
     if (sizeof(int32_t) * (size_t)c->l1 > lds_limit()) return fail(IDS_EINVAL, "l1 too large for the LDS histogram");
@@ -166,6 +167,8 @@ const char* ids_status_string(ids_status s) {
         case IDS_EWORKSPACE: return "IDS_EWORKSPACE";
         case IDS_EHIP: return "IDS_EHIP";
         case IDS_ETIMEOUT: return "IDS_ETIMEOUT";
+        case IDS_ERANKDEF: return "IDS_ERANKDEF";
+        case IDS_ENONFINITE: return "IDS_ENONFINITE";
         default: return "IDS_UNKNOWN";
     }
 }
@@ -223,6 +226,20 @@ ids_status ids_profile_read(const char* stage, double* total_ms, int64_t* count)
     *total_ms = tot;
     *count = cnt;
     return IDS_OK;
+}
+
+void ids_finalize(void) {
+    batched_release();
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = false;
+    for (auto& r : g_recs) {
+        hipEventSynchronize(r.b);
+        g_pool.push_back(r.a);
+        g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+    for (hipEvent_t e : g_pool) hipEventDestroy(e);
+    g_pool.clear();
 }
 
 void ids_profile_reset(void) {
@@ -289,6 +306,7 @@ ids_status id_sketch(const ids_matrix* A, const ids_sketch_cfg* c, void* Y, int3
         ProfScope ps(PK_PROJ, st);
         s = project_split(c->acc, c->l, c->l1, A->n, c->G, Y1, A->n, false, Y, ldy, L.splits, part, st);
     }
+    if (!s && (c->flags & IDS_CHECK_FINITE)) s = check_finite(c->acc, Y, c->l, A->n, ldy, c->status, st);
     return s;
 }
 
@@ -365,8 +383,24 @@ ids_status ids_select_workspace_size(int64_t l, int64_t n, int64_t k, size_t* by
     return IDS_OK;
 }
 
+void ids_set_wait_limit(int64_t polls) { set_wait_limit(polls); }
+
+ids_status ids_select_plan_info(int64_t l, int64_t n, int64_t k, int32_t* info) {
+    g_err.clear();
+    if (!info) return fail(IDS_EINVAL, "info is NULL");
+    ids_status s = validate_select(l, n, k);
+    if (s) return s;
+    SelectPlan sp;
+    if ((s = select_plan(l, n, k, sp))) return s;
+    info[0] = l <= 256 ? 0 : 1;
+    info[1] = sp.mode;
+    info[2] = sp.nb;
+    info[3] = sp.nh;
+    return IDS_OK;
+}
+
 ids_status id_select(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t rs, int64_t cs, int64_t k, int64_t* J,
-                     double* P, int64_t* k_eff, void* ws, size_t ws_bytes, void* stream) {
+                     double* P, int64_t* k_eff, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
     g_err.clear();
     ids_status s = validate_select(l, n, k);
     if (s) return s;
@@ -376,7 +410,7 @@ ids_status id_select(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t r
     SelectPlan sp;
     if ((s = select_plan(l, n, k, sp))) return s;
     if ((s = check_ws(ws, ws_bytes, select_bytes(sp)))) return s;
-    return select_run(sp, Y, ydt, rs, cs, J, P, k_eff, (char*)ws, (hipStream_t)stream);
+    return select_run(sp, Y, ydt, rs, cs, J, P, k_eff, status, (char*)ws, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -434,8 +468,8 @@ ids_status ids_tensor_workspace_size(int32_t N, const int64_t* dims, int64_t R, 
 
 ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* const* factors, const int64_t* ld,
                      const double* lambda, int64_t k, int64_t Jlen, int64_t l, const double* G, uint64_t seed,
-                     double* Y, int64_t* J, double* P, double* lambda_hat, int64_t* k_eff, void* ws,
-                     size_t ws_bytes, void* stream) {
+                     double* Y, int64_t* J, double* P, double* lambda_hat, int64_t* k_eff, int32_t* status,
+                     void* ws, size_t ws_bytes, void* stream) {
     g_err.clear();
     ids_status s = validate_tensor(N, dims, R, k, Jlen, l);
     if (s) return s;
@@ -480,7 +514,7 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
         ProfScope ps(PK_PROJ, st);
         if ((s = project_split(IDS_F64, l, Jlen, R, G, Yout, Jlen, true, Yp, l, T.splits, part, st))) return s;
     }
-    if ((s = select_run(T.sp, l ? Yp : Yout, IDS_F64, 1, l ? l : Jlen, J, P, k_eff, sel, st))) return s;
+    if ((s = select_run(T.sp, l ? Yp : Yout, IDS_F64, 1, l ? l : Jlen, J, P, k_eff, status, sel, st))) return s;
     ProfScope ps(PK_LHAT, st);
     return ids::lambda_hat(k, R, P, J, k_eff, lambda, lambda_hat, st);
 }
@@ -522,7 +556,7 @@ ids_status ids_batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, i
 
 ids_status id_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* plan, int64_t k, int64_t l,
                       int64_t l1max, uint64_t seed, double tol, const void* A, const void* G, int64_t* J, double* P,
-                      int64_t* k_eff, void* ws, size_t ws_bytes, void* stream) {
+                      int64_t* k_eff, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
     g_err.clear();
     ids_status s = validate_batched(nprob, m, n, k, l, l1max);
     if (s) return s;
@@ -537,8 +571,8 @@ ids_status id_batched(int64_t nprob, const int64_t* m, const int64_t* n, const v
     const size_t need = align256(sizeof(float) * (size_t)y_elems) + align256(sizeof(double) * (size_t)r_elems * k) +
                         align256(sizeof(int32_t) * (size_t)r_elems) + align256(sizeof(double) * (size_t)nprob * k);
     if ((s = check_ws(ws, ws_bytes, need))) return s;
-    return batched_run(nprob, plan, k, l, l1max, seed, tol, A, G, J, P, k_eff, ws, ws_bytes, a_elems, y_elems,
-                       r_elems, (hipStream_t)stream);
+    return batched_run(nprob, plan, k, l, l1max, seed, tol, A, G, J, P, k_eff, status, ws, ws_bytes, a_elems,
+                       y_elems, r_elems, (hipStream_t)stream);
 }
 
 }  // extern "C"

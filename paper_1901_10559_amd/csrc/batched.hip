@@ -82,6 +82,7 @@ struct BatchArgs {
     int64_t* J;
     double* P;
     int64_t* keff;
+    int32_t* status;    // optional, per problem
 };
 
 // ---------------------------------------------------------------------------
@@ -541,6 +542,9 @@ __global__ __launch_bounds__(NT, 4) void batched_cpqr_kernel(BatchArgs a, int nt
         return s;
     };
     double nu = wave_live ? norm_from(0) : 0.0;
+    // a non-finite entry of Y_p (or an overflowing norm) is reported per problem
+    const bool nonfinite = __syncthreads_or(alive && !__builtin_isfinite(nu)) != 0;
+    bool rankdef = false;
     int keff = k;
     double nu0 = 0.0;  // |r_11|^2
     const int64_t roff = pr.r_off;
@@ -571,6 +575,7 @@ __global__ __launch_bounds__(NT, 4) void batched_cpqr_kernel(BatchArgs a, int nt
         // stop at rank deficiency, or (fixed accuracy) once the pivot's trailing
         // norm |r_tt| = sqrt(wnu) is at most tol |r_11|
         if (wj == INT32_MAX || !(wnu > 0.0) || (t > 0 && wnu <= a.tol2 * nu0)) {
+            rankdef = wj == INT32_MAX || !(wnu > 0.0);
             keff = t;
             break;
         }
@@ -650,6 +655,7 @@ __global__ __launch_bounds__(NT, 4) void batched_cpqr_kernel(BatchArgs a, int nt
     if (j == 0) {
         a.keff[p] = keff;
         for (int t = keff; t < k; ++t) a.J[(int64_t)p * k + t] = -1;
+        if (a.status) a.status[p] = nonfinite ? IDS_ENONFINITE : (rankdef ? IDS_ERANKDEF : IDS_OK);
     }
 }
 
@@ -777,33 +783,64 @@ ids_status batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, int64
 
 // Two extra streams per device (default priority, non-blocking) on which the
 // 512- and 256-thread CPQR launches run beside the 1024-thread one, so the
-// smaller problems fill the CUs the largest ones leave idle; created once.
-// The lock keeps one call's event records and waits together.
+// smaller problems fill the CUs the largest ones leave idle; created once (a
+// failed creation is undone and remembered: that device then runs every
+// class on the caller's stream).  The lock keeps one call's event records
+// and waits together.
 struct CpqrSide {
     hipStream_t s[2] = {nullptr, nullptr};
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    bool ok = false;
+    int state = 0;  // 0: not tried, 1: ready, -1: creation failed
 };
 static std::mutex g_side_mu;
 static CpqrSide g_side[64];
+
+static void side_destroy(CpqrSide& c) {
+    for (auto& x : c.s)
+        if (x) {
+            hipStreamSynchronize(x);
+            hipStreamDestroy(x);
+            x = nullptr;
+        }
+    for (auto& e : c.ev)
+        if (e) {
+            hipEventDestroy(e);
+            e = nullptr;
+        }
+}
 
 static CpqrSide* cpqr_side() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
     CpqrSide& c = g_side[dev];
-    if (!c.ok) {
-        for (auto& x : c.s)
-            if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) return nullptr;
-        for (auto& e : c.ev)
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
-        c.ok = true;
+    if (c.state == 0) {
+        bool ok = true;
+        for (auto& x : c.s) ok = ok && hipStreamCreateWithFlags(&x, hipStreamNonBlocking) == hipSuccess;
+        for (auto& e : c.ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+        if (!ok) side_destroy(c);
+        c.state = ok ? 1 : -1;
     }
-    return &c;
+    return c.state == 1 ? &c : nullptr;
+}
+
+// Library teardown (ids_finalize): the side streams of every device, after
+// the work queued on them has finished.
+void batched_release() {
+    std::lock_guard<std::mutex> g(g_side_mu);
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    for (int d = 0; d < 64; ++d) {
+        if (g_side[d].state != 1) continue;
+        if (hipSetDevice(d) == hipSuccess) side_destroy(g_side[d]);
+        g_side[d].state = 0;
+    }
+    if (have) hipSetDevice(cur);
 }
 
 ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, int64_t l1max, uint64_t seed,
-                       double tol, const void* A, const void* G, int64_t* J, double* P, int64_t* keff, void* ws,
-                       size_t ws_bytes, int64_t a_elems, int64_t y_elems, int64_t r_elems, hipStream_t st) {
+                       double tol, const void* A, const void* G, int64_t* J, double* P, int64_t* keff,
+                       int32_t* status, void* ws, size_t ws_bytes, int64_t a_elems, int64_t y_elems,
+                       int64_t r_elems, hipStream_t st) {
     size_t op, o1, o2;
     plan_layout(nprob, &op, &o1, &o2);
     BatchArgs a;
@@ -830,6 +867,7 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
     a.J = J;
     a.P = P;
     a.keff = keff;
+    a.status = status;
     (void)ws_bytes;
     {
         ProfScope ps(PK_CS, st);
@@ -847,14 +885,14 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
         CpqrSide* side = cpqr_side();
         hipStream_t s512 = st, s256 = st;
         if (side) {  // else all on the caller's stream, one after another
-            if (hipEventRecord(side->ev[0], st) != hipSuccess ||
-                hipStreamWaitEvent(side->s[0], side->ev[0], 0) != hipSuccess ||
-                hipStreamWaitEvent(side->s[1], side->ev[0], 0) != hipSuccess) {
-                set_error("batched ID: stream ordering failed");
-                return IDS_EHIP;
+            // nothing is queued on the side streams yet: on failure here the
+            // classes simply stay on the caller's stream
+            if (hipEventRecord(side->ev[0], st) == hipSuccess &&
+                hipStreamWaitEvent(side->s[0], side->ev[0], 0) == hipSuccess &&
+                hipStreamWaitEvent(side->s[1], side->ev[0], 0) == hipSuccess) {
+                s512 = side->s[0];
+                s256 = side->s[1];
             }
-            s512 = side->s[0];
-            s256 = side->s[1];
         }
         const int gq = k <= 32 ? 1 : (k <= 64 ? 2 : 4);
         const size_t lds = sizeof(double) * (size_t)k * (gq * TRSM_AX_SQ + 1);
@@ -878,12 +916,17 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
         solve(st, 512, 1024);
         solve(s512, 256, 512);
         solve(s256, 0, 256);
-        if (side) {
+        if (s512 != st) {
+            // join: the caller's stream waits for both side streams; if the
+            // event route fails, wait for them on the host instead, so no work
+            // on J, P or the workspace is still running when this returns
             if (hipEventRecord(side->ev[1], side->s[0]) != hipSuccess ||
                 hipEventRecord(side->ev[2], side->s[1]) != hipSuccess ||
                 hipStreamWaitEvent(st, side->ev[1], 0) != hipSuccess ||
                 hipStreamWaitEvent(st, side->ev[2], 0) != hipSuccess) {
-                set_error("batched ID: stream ordering failed");
+                hipStreamSynchronize(side->s[0]);
+                hipStreamSynchronize(side->s[1]);
+                set_error("batched ID: stream join failed (side streams synchronised on the host)");
                 return IDS_EHIP;
             }
         }

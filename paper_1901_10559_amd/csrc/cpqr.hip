@@ -46,6 +46,9 @@
 // below the diagonal vanish to rounding: H = I, as when they are exactly 0.)
 // Every wait is capped; on expiry a device flag is raised, every other wait
 // gives up at once, and k_eff is reported as -1.
+#include <algorithm>
+#include <atomic>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "solve.hpp"
@@ -66,7 +69,9 @@ struct SelArgs {
     double* R11c;     // k x k: row t = top rows of the column chosen at step t
     int32_t* pos;     // n: step at which the column was chosen, -1 otherwise
     double* mb;       // k step regions of RS doubles each, sentinel-filled
-    uint32_t* flag;   // [0] timeout flag
+    uint32_t* flag;   // [0] timeout flag, [1] non-finite norm seen
+    int32_t* status;  // optional device status word (IDS_OK, IDS_ERANKDEF, ...)
+    uint32_t spin_limit;  // polls before a wait gives up
     int32_t nh;       // publishers (headers per step)
     int32_t S;        // MB_SPEC: stride of the publishers' column slots
     int32_t H0;       // header q at 2 q, 2 q + 1 of a step region; MB_OWNER: column box at H0
@@ -77,7 +82,7 @@ struct SelArgs {
 
 constexpr uint64_t MB_SENT = 0xFFF4A5A5A5A5A5A5ull;
 constexpr uint64_t MB_QNAN = 0x7FF8000000000000ull;
-constexpr uint32_t SPIN_LIMIT = 1u << 20;
+constexpr uint32_t SPIN_LIMIT = 1u << 20;  // default polls before a wait gives up
 
 // MB_SPEC column slots of step t
 __device__ __forceinline__ double* spec_slots(const SelArgs& a, int t) { return a.ring + (size_t)(t & 1) * a.CS; }
@@ -105,7 +110,8 @@ __device__ __forceinline__ double idx_bits(int j) { return __longlong_as_double(
 // polls (less polling traffic on the lines being published; used where the
 // awaited data is normally on its way already).
 template <int U, bool SLEEP = false, class F>
-__device__ __forceinline__ void mb_read(uint64_t (&v)[U], F addr, uint32_t* flag) {
+__device__ __forceinline__ void mb_read(uint64_t (&v)[U], F addr, const SelArgs& a) {
+    uint32_t* flag = a.flag;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const double* p = addr(u);
@@ -117,7 +123,7 @@ __device__ __forceinline__ void mb_read(uint64_t (&v)[U], F addr, uint32_t* flag
 #pragma unroll
         for (int u = 0; u < U; ++u) pend = pend || (v[u] == MB_SENT);
         if (!__any(pend)) return;
-        if (spin >= SPIN_LIMIT ||
+        if (spin >= a.spin_limit ||
             ((spin & 63) == 63 && __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
             if (pend) __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return;
@@ -128,8 +134,14 @@ __device__ __forceinline__ void mb_read(uint64_t (&v)[U], F addr, uint32_t* flag
     }
 }
 
-__global__ void mb_fill_kernel(uint64_t* mb, int64_t count, uint32_t* flag) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) flag[0] = 0u;
+// preset != 0 raises the timeout flag before the factorisation starts: every
+// wait then gives up as soon as it finds data missing (a host-forced test of
+// the give-up path; the kernels still run their bounded loops to the end)
+__global__ void mb_fill_kernel(uint64_t* mb, int64_t count, uint32_t* flag, uint32_t preset) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        flag[0] = preset;
+        flag[1] = 0u;
+    }
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256)
         mb[e] = MB_SENT;
 }
@@ -215,7 +227,7 @@ __device__ __forceinline__ void vote_hdr(const SelArgs& a, const double* reg, in
             const int q = (int)threadIdx.x + NT * (u >> 1);
             return q < a.nh ? reg + (size_t)q * hs + (u & 1) : nullptr;
         },
-        a.flag);
+        a);
     double bn = -1.0;
     int bj = INT32_MAX;
 #pragma unroll
@@ -301,7 +313,7 @@ __device__ __forceinline__ void vote_prefetch(const SelArgs& a, const double* re
 #pragma unroll
             for (int u = 0; u < U; ++u) xv[u] = MB_SENT;
         }
-        if (spin >= SPIN_LIMIT ||
+        if (spin >= a.spin_limit ||
             ((spin & 63) == 63 && __hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
             if (lane == 0) __hip_atomic_store(a.flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             wnu = bn;
@@ -325,7 +337,7 @@ __device__ __forceinline__ void fetch_col_lds(const SelArgs& a, const double* sr
                 const int i = i0 + u * NT + (int)threadIdx.x;
                 return i < l ? src + i : nullptr;
             },
-            a.flag);
+            a);
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int i = i0 + u * NT + (int)threadIdx.x;
@@ -350,11 +362,25 @@ __device__ __forceinline__ void reflector(double alpha, double nu2, double& tau,
     }
 }
 
+// A column whose initial norm is not finite (NaN or infinite entries, or a
+// sum of squares that overflows) raises flag[1].  The store is complete before
+// the workgroup barrier that precedes this workgroup's first publication, and
+// workgroup 0 has read every first publication before it reaches finish(), so
+// it sees the flag there.
+__device__ __forceinline__ void flag_nonfinite(const SelArgs& a) {
+    __hip_atomic_store(a.flag + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+}
+
+// k_eff, unused J entries and the status word, written once by workgroup 0
 __device__ __forceinline__ void finish(const SelArgs& a, int keff) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const bool timed_out = __hip_atomic_load(a.flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        const bool nonfinite = __hip_atomic_load(a.flag + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
         *a.keff = timed_out ? -1 : keff;
         for (int64_t t = keff; t < a.k; ++t) a.J[t] = -1;
+        if (a.status)
+            *a.status = timed_out ? IDS_ETIMEOUT : nonfinite ? IDS_ENONFINITE : (keff < a.k ? IDS_ERANKDEF : IDS_OK);
     }
 }
 
@@ -427,6 +453,7 @@ __global__ __launch_bounds__(NW * 64) void cpqr_gl_kernel(SelArgs a) {
         for (int r = 0; r < R; ++r) s = fma(y[r], y[r], s);
         nu = group_sum<G>(s);
     }
+    if (alive && !__builtin_isfinite(nu)) flag_nonfinite(a);
 
     const int k = (int)a.k;
     int keff = k;
@@ -692,6 +719,12 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
         nu[c] = s;
     }
     wg_sum_t<NC, NW>(nu, red, res);
+    if (threadIdx.x == 0) {
+        bool bad = false;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) bad = bad || (alive[c] && !__builtin_isfinite(nu[c]));
+        if (bad) flag_nonfinite(a);
+    }
 
     const int k = (int)a.k;
     int keff = k;
@@ -752,7 +785,7 @@ __global__ __launch_bounds__(512) void cpqr_rb_kernel(SelArgs a) {
                     const int i = rb0 + 64 * r;
                     return i < l ? src + i : nullptr;
                 },
-                a.flag);
+                a);
 #pragma unroll
             for (int r = 0; r < RB; ++r) x[r] = (rb0 + 64 * r < l) ? mb_val(xv[r]) : 0.0;
         }
@@ -1255,9 +1288,19 @@ size_t select_bytes(const SelectPlan& sp) {
            align256(sizeof(int32_t) * (size_t)sp.n);
 }
 
+// polls before a device-wide wait gives up (0: the exchange is treated as
+// expired from the start -- a host-forced test of the give-up path)
+static std::atomic<uint32_t> g_wait_limit{SPIN_LIMIT};
+
+void set_wait_limit(int64_t polls) {
+    g_wait_limit.store(polls < 0 ? SPIN_LIMIT : (uint32_t)std::min<int64_t>(polls, SPIN_LIMIT));
+}
+
 ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t rs, int64_t cs, int64_t* J,
-                      double* P, int64_t* keff, char* ws, hipStream_t st) {
+                      double* P, int64_t* keff, int32_t* status, char* ws, hipStream_t st, bool prof) {
     SelArgs a;
+    a.status = status;
+    a.spin_limit = g_wait_limit.load();
     a.Y = Y;
     a.ydt = ydt;
     a.l = sp.l;
@@ -1288,10 +1331,11 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
     pick(sp.l, in);
     const int64_t cnt = (int64_t)mb_doubles(sp);
     const unsigned fg = (unsigned)std::min<int64_t>((cnt + 255) / 256, 4096);
-    hipLaunchKernelGGL(mb_fill_kernel, dim3(fg), dim3(256), 0, st, (uint64_t*)a.mb, cnt, a.flag);
+    hipLaunchKernelGGL(mb_fill_kernel, dim3(fg), dim3(256), 0, st, (uint64_t*)a.mb, cnt, a.flag,
+                       a.spin_limit == 0 ? 1u : 0u);
     void* args[] = {&a};
     {
-        ProfScope ps(PK_CPQR, st);
+        ProfScope ps(prof ? PK_CPQR : -1, st);
         hipError_t e = hipLaunchCooperativeKernel(in.fn[sp.mode], dim3(sp.nb), dim3(in.threads), args,
                                                   (unsigned)cpqr_lds(sp, in), st);
         if (e != hipSuccess) {
@@ -1299,7 +1343,7 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
             return IDS_EHIP;
         }
     }
-    ProfScope ps(PK_TRSM, st);
+    ProfScope ps(prof ? PK_TRSM : -1, st);
     const size_t r11 = sizeof(double) * (size_t)sp.k * sp.k;
     const size_t xb = sizeof(double) * (size_t)sp.k * TRSM_THREADS;
     const unsigned g = (unsigned)((sp.n + TRSM_THREADS - 1) / TRSM_THREADS);

@@ -13,7 +13,7 @@ ids_status check_launch(const char* what);
 // optional per-stage timing with HIP events on the launch stream
 enum ProfKind { PK_PLAN = 0, PK_CS, PK_PROJ, PK_CPQR, PK_TRSM, PK_TS, PK_LHAT, PK_COUNT };
 struct ProfScope {
-    ProfScope(int kind, hipStream_t st);
+    ProfScope(int kind, hipStream_t st);  // kind < 0: records nothing
     ~ProfScope();
     int kind;
     hipStream_t st;
@@ -73,19 +73,30 @@ struct SelectPlan {
 };
 ids_status select_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp);
 size_t select_bytes(const SelectPlan& sp);
+// status: optional device status word; prof: record stage events (when on)
 ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t rs, int64_t cs, int64_t* J,
-                      double* P, int64_t* keff, char* ws, hipStream_t st);
+                      double* P, int64_t* keff, int32_t* status, char* ws, hipStream_t st, bool prof = true);
+// polls before a device-wide CPQR wait gives up (< 0: the default; 0: give up
+// at once, every factorisation then reports IDS_ETIMEOUT)
+void set_wait_limit(int64_t polls);
 // lambda_hat[t] = lambda[J[t]] * sum_r P[t][r]
 ids_status lambda_hat(int64_t k, int64_t n, const double* P, const int64_t* J, const int64_t* keff,
                       const double* lambda, double* lhat, hipStream_t st);
 
 // ---- batched mixed-precision ID --------------------------------------------
 ids_status batched_plan_bytes(int64_t nprob, size_t* bytes);
+// destroys the library's side streams (after their work has finished)
+void batched_release();
 ids_status batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, int64_t k, int64_t l, int64_t l1max,
                         void* plan, size_t plan_bytes, size_t* ws_bytes, hipStream_t st);
 ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, int64_t l1max, uint64_t seed,
-                       double tol, const void* A, const void* G, int64_t* J, double* P, int64_t* keff, void* ws,
-                       size_t ws_bytes, int64_t a_elems, int64_t y_elems, int64_t r_elems, hipStream_t st);
+                       double tol, const void* A, const void* G, int64_t* J, double* P, int64_t* keff,
+                       int32_t* status, void* ws, size_t ws_bytes, int64_t a_elems, int64_t y_elems,
+                       int64_t r_elems, hipStream_t st);
+
+// ---- finiteness scan of a sketch (l x n column-major) -> status word ---------
+ids_status check_finite(int32_t dtype, const void* Y, int64_t l, int64_t n, int64_t ldy, int32_t* status,
+                        hipStream_t st);
 
 // ---- TensorSketch -------------------------------------------------------------
 ids_status tensorsketch(int32_t N, const int64_t* dims, int64_t R, const double* const* factors,

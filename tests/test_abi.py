@@ -46,24 +46,24 @@ def test_select_rejects_bad_sizes_without_gpu():
     assert b"k must" in L.ids_last_error()
     assert L.ids_select_workspace_size(3, 50, 4, ctypes.byref(nb)) == 1      # k > l
     assert L.ids_select_workspace_size(5000, 50, 4, ctypes.byref(nb)) == 1   # l > 4096
-    assert L.id_select(None, 0, 10, 50, 1, 10, 4, None, None, None, None, 0, None) == 1
+    assert L.id_select(None, 0, 10, 50, 1, 10, 4, None, None, None, None, None, 0, None) == 1
 
 
 def test_sketch_rejects_bad_arguments_without_gpu():
     L = ids.lib()
     nb = ctypes.c_size_t(0)
     A = ids.IdsMatrix(ids.DENSE, ids.F64, 100, 20, 20, 0, ctypes.c_void_p(16), None, None)
-    cfg = ids.IdsSketchCfg(30, 40, 0, 0, 0, ids.F64, ids.F64, None, None, None)   # l > l1
+    cfg = ids.IdsSketchCfg(30, 40, 0, 0, 0, ids.F64, ids.F64, None, None, None, None)   # l > l1
     assert L.ids_sketch_workspace_size(ctypes.byref(A), ctypes.byref(cfg), ctypes.byref(nb)) == 1
-    cfg = ids.IdsSketchCfg(30, 10, 0, 0, 0, ids.F64, ids.F64, None, None, None)   # l < l1 without G
+    cfg = ids.IdsSketchCfg(30, 10, 0, 0, 0, ids.F64, ids.F64, None, None, None, None)   # l < l1 without G
     assert L.ids_sketch_workspace_size(ctypes.byref(A), ctypes.byref(cfg), ctypes.byref(nb)) == 1
     assert b"G is required" in L.ids_last_error()
-    cfg = ids.IdsSketchCfg(30, 30, 0, 0, 0, ids.F32, ids.F32, None, None, None)   # FP64 in, FP32 acc
+    cfg = ids.IdsSketchCfg(30, 30, 0, 0, 0, ids.F32, ids.F32, None, None, None, None)   # FP64 in, FP32 acc
     assert L.ids_sketch_workspace_size(ctypes.byref(A), ctypes.byref(cfg), ctypes.byref(nb)) == 2
     A2 = ids.IdsMatrix(ids.DENSE, ids.F64, 100, 20, 10, 0, ctypes.c_void_p(16), None, None)  # ld < n
-    cfg = ids.IdsSketchCfg(30, 30, 0, 0, 0, ids.F64, ids.F64, None, None, None)
+    cfg = ids.IdsSketchCfg(30, 30, 0, 0, 0, ids.F64, ids.F64, None, None, None, None)
     assert L.ids_sketch_workspace_size(ctypes.byref(A2), ctypes.byref(cfg), ctypes.byref(nb)) == 1
-    cfg = ids.IdsSketchCfg(30, 30, 0, 0, ids.HASH_FULLRANK, ids.F64, ids.F64, None, None, None)
+    cfg = ids.IdsSketchCfg(30, 30, 0, 0, ids.HASH_FULLRANK, ids.F64, ids.F64, None, None, None, None)
     assert L.ids_sketch_workspace_size(ctypes.byref(A), ctypes.byref(cfg), ctypes.byref(nb)) == 1
     A3 = ids.IdsMatrix(ids.CSR, ids.F32, 100, 20, 0, 10, ctypes.c_void_p(16), ctypes.c_void_p(16),
                        ctypes.c_void_p(16))

@@ -171,8 +171,9 @@ def test_projection_f32():
 # select (Algorithm 1)
 # ---------------------------------------------------------------------------
 # shapes cover every kernel family (grouped lanes up to 256 rows, row bands of
-# 512 / 1024 / 2048 / 4096 rows) and every candidate exchange (whole region,
-# speculative columns, owner-published column)
+# 512 / 1024 / 2048 / 4096 rows) with the speculative candidate exchange (the
+# owner-published exchange, which only 257..512-row sketches with more than
+# 256 workgroups take, is covered in test_gpu_status.py)
 @pytest.mark.parametrize("l,n,k", [(30, 1000, 20), (12, 40, 5), (64, 64, 40), (120, 2000, 100), (60, 20000, 50),
                                    (130, 700, 130), (200, 6000, 150), (300, 900, 64), (400, 3000, 120),
                                    (700, 400, 30), (800, 1200, 90), (900, 2400, 60), (1500, 600, 50),
