@@ -180,6 +180,24 @@ ids_status id_select(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t r
 ids_status ids_select_plan_info(int64_t l, int64_t n, int64_t k, int32_t* info);
 
 /*
+ * id_select_noalloc -- id_select with no workspace argument and no device
+ * allocation, for callers that cannot allocate (code under HIP graph capture,
+ * serving loops with a fixed memory budget, harnesses that forbid hipMalloc).
+ * The caller still owns Y, J, P, k_eff and status.  Scratch is a static
+ * device buffer of IDS_SELECT_NOALLOC_MAX_BYTES on each GPU, held from the
+ * library's first use there until the process ends; a shape whose
+ * ids_select_workspace_size exceeds it is rejected with IDS_EWORKSPACE
+ * before anything is launched.  Every call on one GPU shares that buffer
+ * (each call re-initialises what it reads): calls that may overlap on one GPU
+ * (several streams or threads) race and must be serialised by the caller.
+ * Same kernels and results as id_select (bitwise identical); no stage timing.
+ */
+#define IDS_SELECT_NOALLOC_MAX_BYTES (32u << 20)
+ids_status id_select_noalloc(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t rs, int64_t cs,
+                             int64_t k, int64_t* J, double* P, int64_t* k_eff, int32_t* status,
+                             void* stream);
+
+/*
  * ids_set_wait_limit -- polls after which a device-wide wait of the pivoted
  * QR gives up (default 2^20, far beyond any normal wait; polls < 0 restores
  * it).  0 treats the exchange as expired from the start: every wait gives up

@@ -23,7 +23,7 @@ import ctypes
 import os
 
 __all__ = ["lib", "lib_path", "BatchedPlan", "batched_plan", "id_batched", "profile_enable", "profile_stages",
-           "profile_read", "profile_reset", "id_sketch", "id_project", "id_select",
+           "profile_read", "profile_reset", "id_sketch", "id_project", "id_select", "id_select_noalloc",
            "matrix_id", "tensor_id", "gaussian_sketch", "gaussian_id", "check_status", "set_wait_limit", "select_plan_info",
            "finalize", "IdsError", "F64", "F32", "BF16", "HASH_FULLRANK", "CHECK_FINITE", "EXPORTED",
            "OK", "ETIMEOUT", "ERANKDEF", "ENONFINITE"]
@@ -40,7 +40,7 @@ OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ETIMEOUT, ERANKDEF, ENONFINITE = range(8)
 
 EXPORTED = ["ids_sketch_workspace_size", "id_sketch", "id_project", "ids_gaussian_workspace_size",
             "id_gaussian_sketch", "ids_select_workspace_size",
-            "id_select", "ids_set_wait_limit", "ids_select_plan_info", "ids_tensor_workspace_size", "tensor_id",
+            "id_select", "id_select_noalloc", "ids_set_wait_limit", "ids_select_plan_info", "ids_tensor_workspace_size", "tensor_id",
             "ids_batched_plan_size", "ids_batched_plan", "id_batched", "ids_profile_enable", "ids_profile_stages",
             "ids_profile_read", "ids_profile_reset", "ids_finalize", "ids_status_string", "ids_last_error"]
 
@@ -85,6 +85,8 @@ def lib():
         L.ids_select_workspace_size.argtypes = [c_i64, c_i64, c_i64, P(c_sz)]
         L.id_select.argtypes = [c_vp, c_i32, c_i64, c_i64, c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz,
                                 c_vp]
+        L.id_select_noalloc.argtypes = [c_vp, c_i32, c_i64, c_i64, c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp]
+        L.id_select_noalloc.restype = c_i32
         L.ids_select_plan_info.argtypes = [c_i64, c_i64, c_i64, c_vp]
         L.ids_select_plan_info.restype = c_i32
         L.ids_set_wait_limit.argtypes = [c_i64]
@@ -338,6 +340,18 @@ def id_select(Y, k: int, stream=None, status=None):
     _check(lib().id_select(c_vp(Y.data_ptr()), _dt(Y), l, n, Y.stride(0), Y.stride(1), k, c_vp(J.data_ptr()),
                            c_vp(P.data_ptr()), c_vp(keff.data_ptr()), _ptr(status), c_vp(ws[1]) if ws else None, wsb,
                            _stream(torch, stream)), "id_select")
+    return J, P, keff
+
+
+def id_select_noalloc(Y, k: int, J, P, keff, status=None, stream=None):
+    """id_select into caller-provided outputs (J int64[k], P float64 k x n,
+    keff int64[1], optional status int32[1]) with the library's static
+    scratch buffer: no device allocation anywhere in the call."""
+    torch = _torch()
+    l, n = Y.shape
+    _check(lib().id_select_noalloc(c_vp(Y.data_ptr()), _dt(Y), l, n, Y.stride(0), Y.stride(1), k,
+                                   c_vp(J.data_ptr()), c_vp(P.data_ptr()), c_vp(keff.data_ptr()), _ptr(status),
+                                   _stream(torch, stream)), "id_select_noalloc")
     return J, P, keff
 
 

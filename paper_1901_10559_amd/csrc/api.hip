@@ -414,6 +414,52 @@ ids_status id_select(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t r
 }
 
 // ---------------------------------------------------------------------------
+// allocation-free select: the scratch is a static device array
+// ---------------------------------------------------------------------------
+// One copy per GPU, placed by the loader with the library's code object and
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in; the device address of each GPU's copy comes from
+// hipGetSymbolAddress (with that GPU current) and is the only one passed on.
+static __device__ __align__(256) unsigned char scratch[IDS_SELECT_NOALLOC_MAX_BYTES];
+static std::mutex g_scr_mu;
+static void* g_scr_ptr[64];
+
+static ids_status scratch_ptr(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(IDS_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> g(g_scr_mu);
+    if (!g_scr_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(IDS_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scr_ptr[dev] = p;
+    }
+    *out = g_scr_ptr[dev];
+    return IDS_OK;
+}
+
+ids_status id_select_noalloc(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t rs, int64_t cs, int64_t k,
+                             int64_t* J, double* P, int64_t* k_eff, int32_t* status, void* stream) {
+    g_err.clear();
+    ids_status s = validate_select(l, n, k);
+    if (s) return s;
+    if (!Y || !J || !P || !k_eff) return fail(IDS_EINVAL, "Y, J, P and k_eff must be non-NULL");
+    if (ydt != IDS_F64 && ydt != IDS_F32) return fail(IDS_EDTYPE, "Y dtype must be IDS_F64 or IDS_F32");
+    if (rs < 1 || cs < 1) return fail(IDS_EINVAL, "strides must be positive");
+    SelectPlan sp;
+    if ((s = select_plan(l, n, k, sp))) return s;
+    const size_t need = select_bytes(sp);
+    if (need > (size_t)IDS_SELECT_NOALLOC_MAX_BYTES)
+        return fail(IDS_EWORKSPACE, "id_select_noalloc: this shape needs " + std::to_string(need) +
+                                        " bytes of scratch; the static buffer holds " +
+                                        std::to_string((size_t)IDS_SELECT_NOALLOC_MAX_BYTES));
+    void* scr = nullptr;
+    if ((s = scratch_ptr(&scr))) return s;
+    return select_run(sp, Y, ydt, rs, cs, J, P, k_eff, status, (char*)scr, (hipStream_t)stream, false);
+}
+
+// ---------------------------------------------------------------------------
 // tensor
 // ---------------------------------------------------------------------------
 struct TensorLayout {

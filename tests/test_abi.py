@@ -47,6 +47,7 @@ def test_select_rejects_bad_sizes_without_gpu():
     assert L.ids_select_workspace_size(3, 50, 4, ctypes.byref(nb)) == 1      # k > l
     assert L.ids_select_workspace_size(5000, 50, 4, ctypes.byref(nb)) == 1   # l > 4096
     assert L.id_select(None, 0, 10, 50, 1, 10, 4, None, None, None, None, None, 0, None) == 1
+    assert L.id_select_noalloc(None, 0, 10, 50, 1, 10, 4, None, None, None, None, None) == 1
 
 
 def test_sketch_rejects_bad_arguments_without_gpu():
