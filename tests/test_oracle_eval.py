@@ -15,6 +15,8 @@
     (Steele, Lea & Flood 2014), written here from the publication, for several
     nonzero seeds and tags (the CountSketch maps h, D of Section 1.3).
 """
+import os
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -173,3 +175,32 @@ def test_tensor_mode_streams_are_tags_one_up():
         _, b, s = _py_maps(9, n + 1, d, 64)
         assert np.array_equal(maps[n][0].astype(np.int64), b)
         assert np.array_equal(maps[n][1].astype(np.int64), s)
+
+
+def test_pool_drivers_match_serial_oracle():
+    # the process-pool drivers only split independent work: a batch's oracle
+    # IDs and a TensorSketch's columns equal the serial oracle's bit for bit
+    import tempfile
+
+    from oracle import pool
+    m, n, flat = synth.batched_inputs(12, seed=3)
+    G = synth.bf16_bits(synth.gaussian(20, 64, seed=3))
+    d = tempfile.mkdtemp()
+    a_path = os.path.join(d, "A.npy")
+    np.save(a_path, flat)
+    jo, po, keff, _, _ = pool.batched_oracle(a_path, G, m, n, 15, 64, 3, d, workers=2)
+    Jo = np.load(jo)
+    Po = np.load(po)
+    a_off = np.concatenate([[0], np.cumsum(m * n)])
+    p_off = np.concatenate([[0], np.cumsum(15 * n)])
+    for p in (0, 7, 11):
+        A = synth.bf16_to_f64(flat[a_off[p]:a_off[p + 1]]).reshape(m[p], n[p])
+        l1 = min(int(m[p]), 64)
+        o = oracle.matrix_id(A, k=15, l1=l1, seed=3, tag=p, G=synth.bf16_to_f64(G)[:, :l1])
+        assert np.array_equal(Jo[p], o["J"])
+        assert np.array_equal(Po[p_off[p]:p_off[p + 1]].reshape(15, n[p]), o["P"])
+    res = pool.batched_ratios(a_path, m, n, 15, Jo, Po, jo, po, d, workers=2)
+    assert np.all(res[:, 0] == res[:, 1])
+    f, lam, _ = synth.cp_tensor(dims=(40, 30, 20), R=60, nbase=6, pert=1e-6, seed=6)
+    maps = oracle.tensor_maps(0, [40, 30, 20], 64)
+    assert np.array_equal(pool.tensorsketch(f, lam, maps, 64, workers=3), oracle.tensorsketch(f, lam, maps, 64))
