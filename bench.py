@@ -89,11 +89,15 @@ def workload(seed: int = 0):
 NB, KB, LB, L1B = 4096, 111, 121, 496
 
 
+def batched_cache_base(seed: int = 0) -> str:
+    return os.path.join(cache_dir(), f"batched_{NB}_seed{seed}_v2")
+
+
 def batched_workload(seed: int = 0):
     import numpy as np
 
     import synth
-    base = os.path.join(cache_dir(), f"batched_{NB}_seed{seed}_v2")
+    base = batched_cache_base(seed)
     if os.path.exists(base + "_A.npy"):
         A = np.load(base + "_A.npy", mmap_mode="r")
         m = np.load(base + "_m.npy")
@@ -172,25 +176,88 @@ def run_batched(ids, torch, np, m, n, Abits, Gb, steps: int, check: bool):
                                "sample": f"first {nfp} problems, one FP64 ID call each (id_sketch + id_select)"}
     res["speedup_vs_fp64"] = res["value"] / res["fp64_per_problem"]["value"]
     if check:
+        # every problem's residual against the FP64 oracle's on the same BF16
+        # inputs and BF16 G; the oracle runs over a process pool on all host
+        # cores, and its wall time is the batch's CPU baseline
+        from oracle import pool
         J = out["J"].cpu().numpy()
         P = out["P"].cpu().numpy()
-        ratios = []
-        for p in range(0, NB, NB // 24):
-            A64n = synth.bf16_to_f64(Abits[a_off[p]:a_off[p + 1]]).reshape(m[p], n[p])
-            l1 = min(int(m[p]), L1B)
-            o = oracle.matrix_id(A64n, k=KB, l1=l1, seed=0, tag=p, G=synth.bf16_to_f64(Gb)[:, :l1])
-            Pp = P[plan.p_off[p]:plan.p_off[p + 1]].reshape(KB, n[p])
-            ratios.append(oracle.residual_fro(A64n, J[p], Pp) / oracle.residual_fro(A64n, o["J"], o["P"]))
+        a_path = batched_cache_base() + "_A.npy"
+        wdir = os.path.join(cache_dir(), "batched_oracle")
+        jo, po, ko, wall, workers = pool.batched_oracle(a_path, Gb, m, n, KB, L1B, 0, wdir)
+        rr = pool.batched_ratios(a_path, m, n, KB, J, P, jo, po, wdir)
+        ratios = rr[:, 0] / rr[:, 1]
         res["residual_ratio_vs_oracle"] = {"median": float(np.median(ratios)), "max": float(np.max(ratios)),
-                                           "sample": len(ratios),
-                                           "note": "FP64 oracle on the same BF16 inputs and BF16 G"}
+                                           "sample": int(len(ratios)),
+                                           "residual_median_gpu": float(np.median(rr[:, 0])),
+                                           "residual_median_oracle_f64": float(np.median(rr[:, 1])),
+                                           "note": "all problems; FP64 oracle on the same BF16 inputs and BF16 G"}
+        hi = host_info()
+        res["cpu_baseline"] = {"value": NB / wall, "unit": "IDs/s", "cores": workers, "kind": "oracle",
+                               "sample": f"all {NB} problems, one FP64 oracle ID each, over a process pool of "
+                                         f"{workers} workers ({wall:.1f} s wall); host: {hi['cpu_model']}, "
+                                         f"{hi['cores_available']} cores available"}
     return res
 
 
-def other_workloads(ids, torch, np, steps: int = 10):
+def measured_read_gbps(ids, torch, buf, reps: int = 10) -> float:
+    """HBM read rate a plain streaming read of `buf` reaches here (GB/s, HIP
+    events on the launch stream around `reps` back-to-back reads): the
+    practical ceiling beside the 8 TB/s datasheet peak."""
+    chk = torch.zeros(1, dtype=torch.int32, device=buf.device)
+    for _ in range(2):
+        ids.stream_read(buf, chk)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        ids.stream_read(buf, chk)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    return buf.numel() * buf.element_size() / sec / 1e9
+
+
+def host_info():
+    """Host cores this process may use and the CPU model (for the baselines)."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cores_available": cores, "cpu_model": model}
+
+
+def oracle_timed(fn, budget_s: float, max_runs: int = 50):
+    """Calls of the (single-threaded) oracle function fn repeated until budget_s
+    seconds have passed; (calls per second, runs, seconds, last result)."""
+    runs = 0
+    t0 = time.perf_counter()
+    out = None
+    while True:
+        out = fn()
+        runs += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or runs >= max_runs:
+            return runs / el, runs, el, out
+
+
+def other_workloads(ids, torch, np, steps: int = 10, check: bool = True, cpu: bool = True):
     """Timings of the other workloads (same kernels, resident inputs): 2000 x 1000
     FP64, CSR 1e6 x 2e4, the 2000^3 CP tensor with and without the Gaussian
-    second stage, and the sparse 5-way CP tensor."""
+    second stage, and the sparse 5-way CP tensor.  Each reports its residual
+    next to the FP64 oracle's (same evaluator) and the oracle's own rate on
+    this host (one core; a bounded sample where a whole oracle ID is long)."""
+    import oracle
+    from oracle import pool
     import synth
     dev = torch.device("cuda:0")
     res = {}
@@ -199,25 +266,55 @@ def other_workloads(ids, torch, np, steps: int = 10):
         return time_and_stages(ids, torch, fn, steps, names)
 
     # c0: 2000 x 1000 FP64, k = 20, p = 10, l1 = 128 (latency of one small ID)
-    A0 = torch.from_numpy(synth.config0()).to(dev)
-    G0 = torch.from_numpy(synth.gaussian(30, 128, seed=0)).to(dev)
+    A0h = synth.config0()
+    G0h = synth.gaussian(30, 128, seed=0)
+    A0 = torch.from_numpy(A0h).to(dev)
+    G0 = torch.from_numpy(G0h).to(dev)
     ms, st = timed(lambda: ids.matrix_id(A0, 20, 128, 30, seed=0, G=G0),
                    ("plan", "countsketch", "project", "cpqr", "trsm"))
-    res["dense_2000x1000_f64"] = {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st}
+    w = {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st}
+    if check or cpu:
+        r = ids.matrix_id(A0, 20, 128, 30, seed=0, G=G0, check=True)
+        rate, runs, el, o = oracle_timed(lambda: oracle.matrix_id(A0h, k=20, l1=128, seed=0, G=G0h), 3.0)
+        Jg, Pg = r["J"].cpu().numpy(), r["P"].cpu().numpy()
+        w["residual"] = {"gpu": oracle.residual_fro(A0h, Jg, Pg), "oracle_f64": oracle.residual_fro(A0h, o["J"], o["P"]),
+                         "spectral_gpu": oracle.spectral_est(A0h, Jg, Pg),
+                         "spectral_oracle_f64": oracle.spectral_est(A0h, o["J"], o["P"]),
+                         "J_equal": bool(np.array_equal(Jg, o["J"])),
+                         "P_rel_diff": float(np.linalg.norm(Pg - o["P"]) / np.linalg.norm(o["P"])),
+                         "note": "Frobenius ratio and the power-iteration spectral estimate (50 iterations)"}
+        w["cpu_baseline"] = {"value": rate, "unit": "IDs/s", "cores": 1, "kind": "oracle",
+                             "sample": f"{runs} whole FP64 oracle IDs, {el:.1f} s"}
+    res["dense_2000x1000_f64"] = w
+    del A0, G0
 
     # c2: CSR 1e6 x 2e4, ~3e7 stored entries, FP64, k = 50, p = 10, l1 = 240
     rp, ci, v = synth.csr_zipf()
+    G2h = synth.gaussian(60, 240, seed=0)
     Ad = (torch.from_numpy(rp).to(dev), torch.from_numpy(ci).to(dev), torch.from_numpy(v).to(dev), 20000)
-    G2 = torch.from_numpy(synth.gaussian(60, 240, seed=0)).to(dev)
+    G2 = torch.from_numpy(G2h).to(dev)
     ms, st = timed(lambda: ids.matrix_id(Ad, 50, 240, 60, seed=0, G=G2),
                    ("plan", "countsketch", "project", "cpqr", "trsm"))
     nnz = v.shape[0]
     cs_bytes = nnz * 12 + (rp.shape[0]) * 8 + 240 * 20000 * 8
     gbs = cs_bytes / (st["countsketch"] / 1e3) / 1e9
-    res["csr_1e6x2e4_f64"] = {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st, "nnz": int(nnz),
-                              "countsketch_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBPS,
-                                                       "unit": "GB/s", "frac": gbs / HBM_PEAK_GBPS,
-                                                       "algorithmic_bytes": int(cs_bytes)}}
+    w = {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st, "nnz": int(nnz),
+         "countsketch_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBPS,
+                                  "unit": "GB/s", "frac": gbs / HBM_PEAK_GBPS,
+                                  "algorithmic_bytes": int(cs_bytes)}}
+    if check or cpu:
+        r = ids.matrix_id(Ad, 50, 240, 60, seed=0, G=G2, check=True)
+        rate, runs, el, o = oracle_timed(lambda: oracle.matrix_id(csr=(rp, ci, v), n=20000, k=50, l1=240, seed=0,
+                                                                  G=G2h), 5.0)
+        Jg, Pg = r["J"].cpu().numpy(), r["P"].cpu().numpy()
+        w["residual"] = {"gpu": oracle.residual_fro_csr(rp, ci, v, 20000, Jg, Pg),
+                         "oracle_f64": oracle.residual_fro_csr(rp, ci, v, 20000, o["J"], o["P"]),
+                         "J_equal": bool(np.array_equal(Jg, o["J"])),
+                         "P_rel_diff": float(np.linalg.norm(Pg - o["P"]) / np.linalg.norm(o["P"]))}
+        w["cpu_baseline"] = {"value": rate, "unit": "IDs/s", "cores": 1, "kind": "oracle",
+                             "sample": f"{runs} whole FP64 oracle IDs of the CSR input, {el:.1f} s"}
+    res["csr_1e6x2e4_f64"] = w
+    del Ad, G2, rp, ci, v
 
     # c3: CP tensor 2000^3, R = 2000, J = 4096, k = 50, FP64
     factors, lam, _ = synth.cp_tensor()
@@ -228,36 +325,97 @@ def other_workloads(ids, torch, np, steps: int = 10):
     ts_s = st["tensorsketch"] / 1e3
     ts_bytes = 3 * 2000 * 2000 * 8 + 4096 * 2000 * 8
     ts_flops = 1000 * 4 * 5 * 4096 * 12    # 4 complex FFTs of 4096 points per column pair
-    res["tensor_2000cubed_R2000_J4096_f64"] = {
-        "ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st,
-        "tensorsketch_roofline": {"hbm": {"achieved": ts_bytes / ts_s / 1e9, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                                          "frac": ts_bytes / ts_s / 1e9 / HBM_PEAK_GBPS, "algorithmic_bytes": ts_bytes},
-                                  "fp64": {"achieved": ts_flops / ts_s / 1e12, "peak": 78.6, "unit": "TFLOP/s",
-                                           "frac": ts_flops / ts_s / 1e12 / 78.6, "algorithmic_flops": ts_flops},
-                                  "note": "factors (96 MB) fit in the 256 MB last-level cache: warm figure"}}
+    w = {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st,
+         "tensorsketch_roofline": {"hbm": {"achieved": ts_bytes / ts_s / 1e9, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                           "frac": ts_bytes / ts_s / 1e9 / HBM_PEAK_GBPS,
+                                           "algorithmic_bytes": ts_bytes},
+                                   "fp64": {"achieved": ts_flops / ts_s / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                                            "frac": ts_flops / ts_s / 1e12 / 78.6, "algorithmic_flops": ts_flops},
+                                   "note": "factors (96 MB) fit in the 256 MB last-level cache: warm figure"}}
+    Gt = torch.from_numpy(synth.gaussian(60, 4096, seed=0)).to(dev)
+    maps = oracle.tensor_maps(0, [2000, 2000, 2000], 4096) if (check or cpu) else None
+    Yo = pool.tensorsketch(factors, lam, maps, 4096) if (check or cpu) else None
+    if check or cpu:
+        r = ids.tensor_id(ft, lt, 50, 4096, seed=0, check=True)
+        # oracle rate: its direct convolutions on 100 of the 2000 columns (one
+        # core) scaled to all columns, plus its pivoted QR and lambda_hat
+        cols = np.arange(0, 2000, 20)
+        t0 = time.perf_counter()
+        oracle.tensorsketch(factors, lam, maps, 4096, cols=cols)
+        t_ts = (time.perf_counter() - t0) * (2000 / len(cols))
+        t0 = time.perf_counter()
+        Jo, Po, ko, _, _ = oracle.cpqr_id(Yo, 50)
+        lo = oracle.lambda_hat(Po, Jo, lam)
+        t_sel = time.perf_counter() - t0
+        Jg, lg = r["J"].cpu().numpy(), r["lambda_hat"].cpu().numpy()
+        w["residual"] = {"gpu": oracle.tensor_error_sampled(factors, lam, Jg, lg),
+                         "oracle_f64": oracle.tensor_error_sampled(factors, lam, Jo, lo),
+                         "J_equal": bool(np.array_equal(Jg, Jo)),
+                         "lambda_hat_max_rel_diff": float(np.max(np.abs(lg - lo) / np.abs(lo))),
+                         "note": "||X - X_hat||_F / ||X||_F from 2e5 sampled entries (same entries for both)"}
+        w["cpu_baseline"] = {"value": 1.0 / (t_ts + t_sel), "unit": "IDs/s", "cores": 1, "kind": "oracle",
+                             "sample": f"direct-convolution TensorSketch of 100 of 2000 columns ({t_ts / 20:.1f} s, "
+                                       f"scaled x20) + pivoted QR of the 4096 x 2000 sketch and lambda_hat "
+                                       f"({t_sel:.1f} s)"}
+    res["tensor_2000cubed_R2000_J4096_f64"] = w
 
     # the same tensor with the Gaussian second stage: CPQR of G (T M), l = k + 10 = 60
-    Gt = torch.from_numpy(synth.gaussian(60, 4096, seed=0)).to(dev)
     ms, st = timed(lambda: ids.tensor_id(ft, lt, 50, 4096, seed=0, l=60, G=Gt),
                    ("plan", "tensorsketch", "project", "cpqr", "trsm", "lambda_hat"))
-    res["tensor_2000cubed_R2000_J4096_projected_l60_f64"] = {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st}
-    del ft, lt, Gt
+    w = {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st}
+    if check or cpu:
+        r = ids.tensor_id(ft, lt, 50, 4096, seed=0, l=60, G=Gt, check=True)
+        Gh = Gt.cpu().numpy()
+        t0 = time.perf_counter()
+        Jo, Po, ko, _, _ = oracle.cpqr_id(oracle.gemm(Gh, Yo), 50)
+        lo = oracle.lambda_hat(Po, Jo, lam)
+        t_sel = time.perf_counter() - t0
+        Jg, lg = r["J"].cpu().numpy(), r["lambda_hat"].cpu().numpy()
+        w["residual"] = {"gpu": oracle.tensor_error_sampled(factors, lam, Jg, lg),
+                         "oracle_f64": oracle.tensor_error_sampled(factors, lam, Jo, lo),
+                         "J_equal": bool(np.array_equal(Jg, Jo))}
+        w["cpu_baseline"] = {"value": 1.0 / (t_ts + t_sel), "unit": "IDs/s", "cores": 1, "kind": "oracle",
+                             "sample": "the same scaled TensorSketch sample + projection, pivoted QR and lambda_hat "
+                                       f"({t_sel:.1f} s)"}
+    res["tensor_2000cubed_R2000_J4096_projected_l60_f64"] = w
+    del ft, lt, Gt, Yo, factors
 
     # the paper's synthetic sparse 5-way CP tensor (density 1%), I = 10000,
     # R = 2000, K = 200, J = 2048, Gaussian second stage to l = K + 10
     factors5, lam5 = synth.cp_sparse(N=5, I=10000, R=2000, K=200, density=0.01, seed=0)
     ft5 = [torch.from_numpy(np.ascontiguousarray(f.T)).to(dev).t() for f in factors5]
-    del factors5
     lt5 = torch.from_numpy(lam5).to(dev)
-    G5 = torch.from_numpy(synth.gaussian(210, 2048, seed=0)).to(dev)
+    G5h = synth.gaussian(210, 2048, seed=0)
+    G5 = torch.from_numpy(G5h).to(dev)
     ms, st = timed(lambda: ids.tensor_id(ft5, lt5, 200, 2048, seed=0, l=210, G=G5),
                    ("plan", "tensorsketch", "project", "cpqr", "trsm", "lambda_hat"))
     ts5_bytes = 5 * 10000 * 2000 * 8 + 2048 * 2000 * 8
-    res["sparse5way_I10000_R2000_K200_J2048_l210_f64"] = {
-        "ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st,
-        "tensorsketch_hbm": {"achieved": ts5_bytes / (st["tensorsketch"] / 1e3) / 1e9, "peak": HBM_PEAK_GBPS,
-                             "unit": "GB/s", "algorithmic_bytes": ts5_bytes,
-                             "note": "factors stored dense (800 MB); the kernel reads every entry once"}}
+    w = {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st,
+         "tensorsketch_hbm": {"achieved": ts5_bytes / (st["tensorsketch"] / 1e3) / 1e9, "peak": HBM_PEAK_GBPS,
+                              "unit": "GB/s", "algorithmic_bytes": ts5_bytes,
+                              "note": "factors stored dense (800 MB); the kernel reads every entry once"}}
+    if check or cpu:
+        r = ids.tensor_id(ft5, lt5, 200, 2048, seed=0, l=210, G=G5, check=True)
+        maps5 = oracle.tensor_maps(0, [10000] * 5, 2048)
+        Y5 = pool.tensorsketch(factors5, lam5, maps5, 2048)
+        cols = np.arange(0, 2000, 20)
+        t0 = time.perf_counter()
+        oracle.tensorsketch(factors5, lam5, maps5, 2048, cols=cols)
+        t_ts = (time.perf_counter() - t0) * (2000 / len(cols))
+        t0 = time.perf_counter()
+        Jo, Po, ko, _, _ = oracle.cpqr_id(oracle.gemm(G5h, Y5), 200)
+        lo = oracle.lambda_hat(Po[:ko], Jo[:ko], lam5)
+        t_sel = time.perf_counter() - t0
+        Jg, lg = r["J"].cpu().numpy(), r["lambda_hat"].cpu().numpy()
+        w["residual"] = {"gpu": oracle.tensor_error_sparse(factors5, lam5, Jg, lg),
+                         "oracle_f64": oracle.tensor_error_sparse(factors5, lam5, Jo, lo),
+                         "J_equal": bool(np.array_equal(Jg, Jo)),
+                         "note": "||X - X_hat||_F / ||X||_F by the Gram identity in long double "
+                                 "(Grams summed over the factors' nonzeros)"}
+        w["cpu_baseline"] = {"value": 1.0 / (t_ts + t_sel), "unit": "IDs/s", "cores": 1, "kind": "oracle",
+                             "sample": f"direct-convolution TensorSketch of 100 of 2000 columns ({t_ts / 20:.1f} s, "
+                                       f"scaled x20) + projection, pivoted QR and lambda_hat ({t_sel:.1f} s)"}
+    res["sparse5way_I10000_R2000_K200_J2048_l210_f64"] = w
     return res
 
 
@@ -267,10 +425,11 @@ def synth_gaussian_f32(l: int, m: int):
     return np.ascontiguousarray(synth.gaussian(l, m, seed=1).astype(np.float32))
 
 
-def gaussian_baseline(ids, torch, At, Omega, cs_ms: float, steps: int = 10):
+def gaussian_baseline(ids, torch, At, Omega, cs_ms: float, steps: int = 10, A64=None):
     """The comparison method of the paper on the same GPU and input: Gaussian
     sketch Y = Omega A (FP32 MFMA, m split over workgroups), then the same
-    CPQR and solve."""
+    CPQR and solve.  With A64 (the input in FP64) its residual is reported
+    next to the oracle's Gaussian ID (FP64; Omega A by a library matmul)."""
     dev = At.device
     Om = torch.from_numpy(Omega).to(dev)
     l, m = Om.shape
@@ -279,11 +438,18 @@ def gaussian_baseline(ids, torch, At, Omega, cs_ms: float, steps: int = 10):
     st = {("gaussian_sketch" if nme == "project" else nme): v for nme, v in st0.items()}
     flops = 2.0 * l * m * n
     tf = flops / (st["gaussian_sketch"] / 1e3) / 1e12
-    return {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st,
-            "sketch_mfma": {"achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
-                            "algorithmic_flops": flops},
-            "countsketch_id_speedup": ms / cs_ms,
-            "note": f"same GPU, same CPQR and solve; FP32 Gaussian sketch Omega A with l = {l}"}
+    out = {"ms_per_id": ms, "IDs_per_s": 1e3 / ms, "stages_ms": st,
+           "sketch_mfma": {"achieved": tf, "peak": 157.3, "unit": "TFLOP/s", "frac": tf / 157.3,
+                           "algorithmic_flops": flops},
+           "countsketch_id_speedup": ms / cs_ms,
+           "note": f"same GPU, same CPQR and solve; FP32 Gaussian sketch Omega A with l = {l}"}
+    if A64 is not None:
+        import oracle
+        r = ids.gaussian_id(At, K, Om)
+        o = oracle.gaussian_id(A64, K, Omega.astype("float64"), blas=True)
+        out["residual"] = {"gpu": oracle.residual_fro(A64, r["J"].cpu().numpy(), r["P"].cpu().numpy()),
+                           "oracle_f64": oracle.residual_fro(A64, o["J"], o["P"])}
+    return out
 
 
 def source_hash(path: str) -> str:
@@ -456,13 +622,20 @@ def main():
         "cpu_baseline": None,
     }
 
+    read_gbps = measured_read_gbps(ids, torch, At)
+    out["roofline"]["measured_read_GBps"] = read_gbps
+    out["roofline"]["frac_of_measured_read"] = achieved / read_gbps
+    out["roofline"]["measured_read_note"] = ("ids_stream_read of the same 1.6 GB matrix (non-temporal 16-byte "
+                                             "loads, grid-stride): the read rate HBM delivers in practice")
     oracle_out = None
     if not args.no_cpu_baseline:
         print(f"[bench] cpu baseline: FP64 oracle, ~{args.cpu_budget:.0f} s", flush=True)
         rate, runs, el, oracle_out, A64 = cpu_baseline(A, G, l1, args.cpu_budget)
+        hi = host_info()
         out["cpu_baseline"] = {"value": rate, "unit": "IDs/s", "cores": 1, "kind": "oracle",
                                "sample": f"{runs} whole FP64 IDs of the same {M}x{N} input "
-                                         f"(CountSketch + projection + CPQR + solve), {el:.1f} s"}
+                                         f"(CountSketch + projection + CPQR + solve), {el:.1f} s; host: "
+                                         f"{hi['cpu_model']}, {hi['cores_available']} cores available"}
     if not args.no_check:
         import oracle
         if oracle_out is None:
@@ -476,11 +649,13 @@ def main():
                            "J_overlap": int(len(set(Jg.tolist()) & set(oracle_out["J"].tolist())))}
     if Omega is not None:
         print("[bench] Gaussian-sketch ID baseline on the same input", flush=True)
-        out["gaussian_baseline"] = gaussian_baseline(ids, torch, At, Omega, ms_per_step)
+        out["gaussian_baseline"] = gaussian_baseline(ids, torch, At, Omega, ms_per_step,
+                                                     A64=None if args.no_check else A64)
         del Omega
     if not args.no_others:
         print("[bench] other workloads (dense 2000x1000, CSR 1e6x2e4, tensors)", flush=True)
-        out["other_workloads"] = other_workloads(ids, torch, np)
+        out["other_workloads"] = other_workloads(ids, torch, np, check=not args.no_check,
+                                                 cpu=not args.no_cpu_baseline)
     if batch is not None:
         print("[bench] batched workload", flush=True)
         out["batched"] = run_batched(ids, torch, np, *batch, steps=args.batched_steps, check=not args.no_check)

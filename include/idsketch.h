@@ -296,6 +296,16 @@ ids_status ids_profile_stages(const char* stages);
 ids_status ids_profile_read(const char* stage, double* total_ms, int64_t* count);
 void ids_profile_reset(void);
 
+/*
+ * ids_stream_read -- measurement utility: reads every 16-byte chunk of the
+ * device buffer [p, p + bytes) once (non-temporal loads, as the dense
+ * CountSketch reads A) and writes the XOR of all 32-bit words to the device
+ * word *checksum.  Timed around, it gives the HBM read rate this device
+ * reaches in practice -- the ceiling beside the datasheet peak for kernels
+ * that stream their input once.  p and bytes must be 16-byte multiples.
+ */
+ids_status ids_stream_read(const void* p, size_t bytes, uint32_t* checksum, void* stream);
+
 /* ids_finalize -- release what the library holds between calls (the side
  * streams of id_batched, the stage-timing events), after the work queued on
  * them has finished.  Optional; later calls recreate what they need.  Call it

@@ -369,3 +369,78 @@ def tensor_error(factors, lam, J, lhat) -> float:
     num = d @ (H @ d)
     den = lam_l @ (H @ lam_l)
     return float(np.sqrt(max(num, 0) / den))
+
+
+def tensor_error_sampled(factors, lam, J, lhat, nsamp: int = 200000, seed: int = 7, entries=None) -> float:
+    """||X - X_hat||_F / ||X||_F estimated from uniformly sampled entries
+    (i_1, ..., i_N) of the CP tensors (def-X-tensor): each sampled entry of
+    X - X_hat is sum_r d_r prod_n A^(n)[i_n, r] with d_r = lambda_r -
+    [r = j_k] lambda_hat_k, evaluated directly (no Gram cancellation), and the
+    ratio of the two sums of squares estimates the ratio of the norms.  With
+    `entries` (an nsamp x N index array) those entries are used instead; all
+    entries of a small tensor give the exact value."""
+    N = len(factors)
+    R = factors[0].shape[1]
+    lam = np.asarray(lam, dtype=np.float64)
+    d = lam.copy()
+    for t, j in enumerate(np.asarray(J)):
+        if j >= 0:
+            d[j] -= float(lhat[t])
+    if entries is None:
+        g = np.random.default_rng(seed)
+        entries = np.stack([g.integers(0, f.shape[0], size=nsamp) for f in factors], axis=1)
+    num = 0.0
+    den = 0.0
+    for c0 in range(0, entries.shape[0], 8192):
+        idx = entries[c0:c0 + 8192]
+        prod = np.ones((idx.shape[0], R), dtype=np.float64)
+        for n_, f in enumerate(factors):
+            prod *= np.asarray(f)[idx[:, n_], :]
+        e = prod @ d
+        x = prod @ lam
+        num += float(e @ e)
+        den += float(x @ x)
+    return float(np.sqrt(num / den))
+
+
+def _gram_sparse_ld(F) -> np.ndarray:
+    """A^T A of a sparse-column factor in long double, summing v_ir v_is over
+    the rows i where both columns are nonzero (row by row, pairs within a row)."""
+    F = np.asarray(F, dtype=np.float64)
+    R = F.shape[1]
+    G = np.zeros((R, R), dtype=np.longdouble)
+    rows, cols = np.nonzero(F)
+    order = np.argsort(rows, kind="stable")
+    rows, cols = rows[order], cols[order]
+    vals = F[rows, cols].astype(np.longdouble)
+    starts = np.flatnonzero(np.r_[True, rows[1:] != rows[:-1]])
+    ends = np.r_[starts[1:], rows.shape[0]]
+    # group rows by their nonzero count, so each group is one vectorised outer product
+    cnt = ends - starts
+    for c in np.unique(cnt):
+        sel = starts[cnt == c]
+        idx = sel[:, None] + np.arange(c)[None, :]
+        cc = cols[idx]
+        vv = vals[idx]
+        np.add.at(G, (np.repeat(cc, c, axis=1).ravel(), np.tile(cc, (1, c)).ravel()),
+                  (vv[:, :, None] * vv[:, None, :]).reshape(-1))
+    return G
+
+
+def tensor_error_sparse(factors, lam, J, lhat) -> float:
+    """tensor_error (the Gram identity in long double) for factors whose
+    columns are sparse: each G_n = A^(n)T A^(n) is summed over the nonzeros of
+    the factor only, so the cost follows the number of nonzero pairs per row
+    instead of I_n R^2."""
+    R = factors[0].shape[1]
+    H = np.ones((R, R), dtype=np.longdouble)
+    for f in factors:
+        H *= _gram_sparse_ld(f)
+    lam_l = np.asarray(lam, dtype=np.longdouble)
+    d = lam_l.copy()
+    for t, j in enumerate(np.asarray(J)):
+        if j >= 0:
+            d[j] -= np.longdouble(lhat[t])
+    num = d @ (H @ d)
+    den = lam_l @ (H @ lam_l)
+    return float(np.sqrt(max(num, 0) / den))

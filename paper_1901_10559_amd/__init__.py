@@ -24,7 +24,7 @@ import os
 
 __all__ = ["lib", "lib_path", "BatchedPlan", "batched_plan", "id_batched", "profile_enable", "profile_stages",
            "profile_read", "profile_reset", "id_sketch", "id_project", "id_select", "id_select_noalloc",
-           "matrix_id", "tensor_id", "gaussian_sketch", "gaussian_id", "check_status", "set_wait_limit", "select_plan_info",
+           "matrix_id", "tensor_id", "gaussian_sketch", "gaussian_id", "check_status", "set_wait_limit", "select_plan_info", "stream_read",
            "finalize", "IdsError", "F64", "F32", "BF16", "HASH_FULLRANK", "CHECK_FINITE", "EXPORTED",
            "OK", "ETIMEOUT", "ERANKDEF", "ENONFINITE"]
 
@@ -40,7 +40,7 @@ OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ETIMEOUT, ERANKDEF, ENONFINITE = range(8)
 
 EXPORTED = ["ids_sketch_workspace_size", "id_sketch", "id_project", "ids_gaussian_workspace_size",
             "id_gaussian_sketch", "ids_select_workspace_size",
-            "id_select", "id_select_noalloc", "ids_set_wait_limit", "ids_select_plan_info", "ids_tensor_workspace_size", "tensor_id",
+            "id_select", "id_select_noalloc", "ids_set_wait_limit", "ids_select_plan_info", "ids_stream_read", "ids_tensor_workspace_size", "tensor_id",
             "ids_batched_plan_size", "ids_batched_plan", "id_batched", "ids_profile_enable", "ids_profile_stages",
             "ids_profile_read", "ids_profile_reset", "ids_finalize", "ids_status_string", "ids_last_error"]
 
@@ -89,6 +89,8 @@ def lib():
         L.id_select_noalloc.restype = c_i32
         L.ids_select_plan_info.argtypes = [c_i64, c_i64, c_i64, c_vp]
         L.ids_select_plan_info.restype = c_i32
+        L.ids_stream_read.argtypes = [c_vp, c_sz, c_vp, c_vp]
+        L.ids_stream_read.restype = c_i32
         L.ids_set_wait_limit.argtypes = [c_i64]
         L.ids_set_wait_limit.restype = None
         L.ids_finalize.argtypes = []
@@ -205,6 +207,15 @@ def select_plan_info(l: int, n: int, k: int) -> dict:
     _check(lib().ids_select_plan_info(l, n, k, ctypes.cast(info, c_vp)), "ids_select_plan_info")
     return {"family": "grouped_lanes" if info[0] == 0 else "row_bands",
             "exchange": "speculative" if info[1] == 0 else "owner", "workgroups": info[2], "publishers": info[3]}
+
+
+def stream_read(buf, checksum, stream=None):
+    """Read every byte of the device tensor `buf` once (measurement utility);
+    the XOR of its 32-bit words goes to the int32 device tensor `checksum`."""
+    torch = _torch()
+    nbytes = buf.numel() * buf.element_size()
+    _check(lib().ids_stream_read(c_vp(buf.data_ptr()), nbytes, c_vp(checksum.data_ptr()), _stream(torch, stream)),
+           "ids_stream_read")
 
 
 def set_wait_limit(polls: int | None = None):

@@ -385,6 +385,13 @@ ids_status ids_select_workspace_size(int64_t l, int64_t n, int64_t k, size_t* by
 
 void ids_set_wait_limit(int64_t polls) { set_wait_limit(polls); }
 
+ids_status ids_stream_read(const void* p, size_t bytes, uint32_t* checksum, void* stream) {
+    g_err.clear();
+    if (!p || !checksum) return fail(IDS_EINVAL, "p and checksum must be non-NULL");
+    if (((uintptr_t)p & 15) != 0 || (bytes & 15) != 0) return fail(IDS_EINVAL, "p and bytes must be 16-byte multiples");
+    return stream_read(p, bytes, checksum, (hipStream_t)stream);
+}
+
 ids_status ids_select_plan_info(int64_t l, int64_t n, int64_t k, int32_t* info) {
     g_err.clear();
     if (!info) return fail(IDS_EINVAL, "info is NULL");

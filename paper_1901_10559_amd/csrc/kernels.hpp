@@ -97,6 +97,8 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
 // ---- finiteness scan of a sketch (l x n column-major) -> status word ---------
 ids_status check_finite(int32_t dtype, const void* Y, int64_t l, int64_t n, int64_t ldy, int32_t* status,
                         hipStream_t st);
+// every 16-byte chunk of [p, p + bytes) read once; XOR of the words -> *sum
+ids_status stream_read(const void* p, size_t bytes, uint32_t* sum, hipStream_t st);
 
 // ---- TensorSketch -------------------------------------------------------------
 ids_status tensorsketch(int32_t N, const int64_t* dims, int64_t R, const double* const* factors,

@@ -138,3 +138,14 @@ def test_countsketch_f64_bit_exact_large_plans(m, n, L):
     Y = ids.id_sketch(dev(A), L, seed=7).cpu().numpy()
     b, s = oracle.hash_maps(7, 0, m, L)
     assert np.array_equal(Y, oracle.countsketch_dense(A, b, s, L))
+
+
+def test_stream_read_checksum():
+    # the measurement utility reads every word: XOR of all 32-bit words
+    g = np.random.default_rng(9)
+    words = g.integers(0, 2**32, size=(1 << 20) + 12, dtype=np.uint64).astype(np.uint32)
+    buf = dev(words.view(np.int32))
+    chk = torch.zeros(1, dtype=torch.int32, device=DEV)
+    ids.stream_read(buf, chk)
+    torch.cuda.synchronize()
+    assert int(chk.item()) & 0xFFFFFFFF == int(np.bitwise_xor.reduce(words))

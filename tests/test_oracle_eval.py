@@ -204,3 +204,38 @@ def test_pool_drivers_match_serial_oracle():
     f, lam, _ = synth.cp_tensor(dims=(40, 30, 20), R=60, nbase=6, pert=1e-6, seed=6)
     maps = oracle.tensor_maps(0, [40, 30, 20], 64)
     assert np.array_equal(pool.tensorsketch(f, lam, maps, 64, workers=3), oracle.tensorsketch(f, lam, maps, 64))
+
+
+def test_tensor_error_sampled_all_entries_is_exact():
+    # every entry of a small CP tensor: the sampled evaluator is the plain
+    # Frobenius-norm ratio of the explicit tensors (def-X-tensor)
+    f, lam, _ = synth.cp_tensor(dims=(6, 5, 4), R=9, nbase=3, pert=1e-3, seed=2)
+    J = np.array([0, 4, -1])
+    lhat = np.array([1.7, -0.3, 0.0])
+    X = np.einsum("r,ir,jr,kr->ijk", lam, *f)
+    Xh = lhat[0] * np.einsum("i,j,k->ijk", f[0][:, 0], f[1][:, 0], f[2][:, 0]) + \
+        lhat[1] * np.einsum("i,j,k->ijk", f[0][:, 4], f[1][:, 4], f[2][:, 4])
+    exact = np.linalg.norm(X - Xh) / np.linalg.norm(X)
+    ent = np.array(np.meshgrid(np.arange(6), np.arange(5), np.arange(4), indexing="ij")).reshape(3, -1).T
+    assert abs(oracle.tensor_error_sampled(f, lam, J, lhat, entries=ent) - exact) <= 1e-13 * exact
+    # and the Gram-identity evaluator agrees on the same case
+    assert abs(oracle.tensor_error(f, lam, J, lhat) - exact) <= 1e-12 * exact
+
+
+def test_tensor_error_sparse_matches_dense_evaluators():
+    # sparse factor columns (the synthetic sparse 5-way generator, scaled down):
+    # the sparse Gram path equals the dense long-double Gram identity, and both
+    # equal the explicit tensor difference on a tensor small enough to form
+    f, lam = synth.cp_sparse(N=3, I=7, R=10, K=4, density=0.3, seed=1)
+    J = np.array([1, 3, 6, -1])
+    lhat = np.array([0.9, -0.2, 0.05, 0.0])
+    X = np.einsum("r,ir,jr,kr->ijk", lam, *f)
+    Xh = sum(lhat[t] * np.einsum("i,j,k->ijk", f[0][:, j], f[1][:, j], f[2][:, j]) for t, j in enumerate(J) if j >= 0)
+    exact = np.linalg.norm(X - Xh) / np.linalg.norm(X)
+    assert abs(oracle.tensor_error_sparse(f, lam, J, lhat) - exact) <= 1e-12 * exact
+    f5, lam5 = synth.cp_sparse(N=5, I=300, R=80, K=20, density=0.05, seed=2)
+    J5 = np.arange(0, 80, 4)
+    lh5 = lam5[J5] * 1.01
+    a = oracle.tensor_error_sparse(f5, lam5, J5, lh5)
+    b = oracle.tensor_error(f5, lam5, J5, lh5)
+    assert abs(a - b) <= 1e-10 * b
