@@ -121,20 +121,35 @@ def run_batched(ids, torch, np, m, n, Abits, Gb, steps: int, check: bool):
     At = torch.from_numpy(Abits.view(np.int16)).to(dev).view(torch.bfloat16)
     Gt = torch.from_numpy(Gb.view(np.int16)).to(dev).view(torch.bfloat16)
     plan = ids.batched_plan(m, n, KB, LB, L1B)
-    ms, st0 = time_and_stages(ids, torch, lambda: ids.id_batched(plan, At, Gt, seed=0), steps,
-                              ("countsketch", "cpqr"))
-    # the CPQR and the solve of the three width classes run on concurrent
-    # streams: one stage
-    st = {"sketch_project": st0["countsketch"], "cpqr_and_solve": st0["cpqr"]}
-    out = ids.id_batched(plan, At, Gt, seed=0)   # result checked below
+    ms_eager, st0 = time_and_stages(ids, torch, lambda: ids.id_batched(plan, At, Gt, seed=0), steps,
+                                    ("countsketch", "cpqr", "trsm"))
+    # the CPQR of the three width classes run on concurrent streams: one stage
+    st = {"sketch_project": st0["countsketch"], "cpqr": st0["cpqr"], "solve": st0["trsm"]}
+    # IDs/s = problems / replay time of the batch recorded into one HIP graph
+    graph = ids.batched_graph(plan, At, Gt, seed=0)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        graph.launch()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        out = graph.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    out = {key: val.clone() for key, val in out.items()}   # result checked below
+    graph.close()
+    tuning = tuned_vs_default(ids, torch, lambda: ids.id_batched(plan, At, Gt, seed=0), steps, units=NB)
     sk_bytes = int((m * n).sum()) * 2 + int(n.sum()) * LB * 4      # read A (BF16), write Y (FP32)
     res = {"value": NB / (ms / 1e3), "unit": "IDs/s", "ms_per_batch": ms, "problems": NB,
+           "timing": "HIP graph replays of the whole batch (one graph launch per batch)",
+           "tuning": tuning,
+           "eager_ms_per_batch": ms_eager,
            "workload": f"{NB} problems, m~logU[256,4096], n~logU[128,1024], sigma_i=exp(-i/8), "
                        f"k={KB}, l={LB}, l1=min(m,{L1B}), A in bf16",
            "precision": {"countsketch": "bf16 in, f32 accumulate", "projection": "bf16 hi+lo MFMA, f32 acc",
-                         "cpqr": "f32 data, f64 norms", "solve": "f64"},
+                         "cpqr": "f32 data, f64 norms", "solve": "f64 (matrix cores)"},
            "stages_ms": st,
            "sketch_roofline": {"bound": "hbm", "achieved": sk_bytes / (st["sketch_project"] / 1e3) / 1e9,
                                "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -217,6 +232,37 @@ def measured_read_gbps(ids, torch, buf, reps: int = 10) -> float:
     torch.cuda.synchronize()
     sec = e0.elapsed_time(e1) / 1e3 / reps
     return buf.numel() * buf.element_size() / sec / 1e9
+
+
+def tuned_vs_default(ids, torch, fn, steps: int, per_call: str = "IDs/s", units: int = 1):
+    """Calls per second of fn with the tuned table and with every knob forced
+    to its hand-picked value (paper_1901_10559_amd/tune.py HAND_DEFAULTS)."""
+    from paper_1901_10559_amd import tune
+
+    def rate():
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return units * steps / (e0.elapsed_time(e1) / 1e3)
+
+    tuned = rate()
+    for key, v in tune.HAND_DEFAULTS.items():
+        ids.tune_set(key, v)
+    try:
+        default = rate()
+    finally:
+        for key in tune.HAND_DEFAULTS:
+            ids.tune_set(key, None)
+    changed = {k: ids.tune_get(k) for k, v in tune.HAND_DEFAULTS.items() if ids.tune_get(k) != v}
+    return {"tuned": tuned, "default": default, "unit": per_call, "speedup": tuned / default,
+            "knobs_changed_by_tuner": changed}
 
 
 def host_info():
@@ -622,6 +668,9 @@ def main():
         "cpu_baseline": None,
     }
 
+    # the autotuner's table against the hand-picked launch shapes it replaced
+    # (same work; knobs overridden for the default run only)
+    out["tuning"] = tuned_vs_default(ids, torch, step, args.steps)
     read_gbps = measured_read_gbps(ids, torch, At)
     out["roofline"]["measured_read_GBps"] = read_gbps
     out["roofline"]["frac_of_measured_read"] = achieved / read_gbps

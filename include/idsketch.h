@@ -280,6 +280,27 @@ ids_status id_batched(int64_t nprob, const int64_t* m, const int64_t* n, const v
                       void* stream);
 
 /*
+ * Batched ID as a HIP graph: ids_batched_graph_create records one id_batched
+ * call (the same arguments; the caller's plan, A, G, outputs and workspace
+ * fixed) into a graph -- the sketch, the three concurrent width-class
+ * factorisations on forked streams and the solve, with the fork and join as
+ * graph edges -- and instantiates it; nothing runs yet.  Each
+ * ids_batched_graph_launch replays the whole batch on `stream` as one graph
+ * launch (asynchronous, results as id_batched once the stream is
+ * synchronised); the recorded buffers must stay allocated and are
+ * overwritten by every replay.  Replays of one graph on several streams at
+ * once race on those buffers.  ids_batched_graph_destroy frees the graph
+ * (not the caller's buffers).  No memset or allocation is recorded.
+ */
+typedef struct ids_batched_graph_s* ids_batched_graph;
+ids_status ids_batched_graph_create(int64_t nprob, const int64_t* m, const int64_t* n, const void* plan,
+                                    int64_t k, int64_t l, int64_t l1max, uint64_t seed, double tol,
+                                    const void* A, const void* G, int64_t* J, double* P, int64_t* k_eff,
+                                    int32_t* status, void* ws, size_t ws_bytes, ids_batched_graph* graph);
+ids_status ids_batched_graph_launch(ids_batched_graph graph, void* stream);
+void ids_batched_graph_destroy(ids_batched_graph graph);
+
+/*
  * Stage timing.  While enabled, every call records a pair of HIP events on its
  * stream around each stage ("plan", "countsketch", "project", "cpqr", "trsm",
  * "tensorsketch", "lambda_hat").  ids_profile_read waits for the recorded
@@ -305,6 +326,23 @@ void ids_profile_reset(void);
  * that stream their input once.  p and bytes must be 16-byte multiples.
  */
 ids_status ids_stream_read(const void* p, size_t bytes, uint32_t* checksum, void* stream);
+
+/*
+ * Launch-shape knobs.  Each knob (a name and an integer) selects among
+ * kernel variants or launch shapes that give the same results, e.g.
+ * "select.gl.l128.n4k" (pivoted-QR workgroup size for sketches of 65..128
+ * rows and 1025..4096 columns: 0 = 8 waves, 1 = 4 waves), "trsm.k64" (lanes
+ * per column of the interpolation-matrix solve), "batched.rl512" (rows the
+ * 512-thread batched factorisation keeps in LDS: 36 or 0), "project.wgs"
+ * (workgroups the projection's K split aims for).  The library's defaults
+ * are the table the project's autotuner (paper_1901_10559_amd/tune.py)
+ * measured on the device.  ids_tune_set overrides a knob for later calls
+ * (value < 0 restores the table's value); an unknown name or a value the knob
+ * does not accept is IDS_EINVAL.  Process-wide; query workspace sizes after
+ * changing knobs.
+ */
+ids_status ids_tune_set(const char* key, int64_t value);
+ids_status ids_tune_get(const char* key, int64_t* value);
 
 /* ids_finalize -- release what the library holds between calls (the side
  * streams of id_batched, the stage-timing events), after the work queued on

@@ -22,9 +22,9 @@ import atexit
 import ctypes
 import os
 
-__all__ = ["lib", "lib_path", "BatchedPlan", "batched_plan", "id_batched", "profile_enable", "profile_stages",
+__all__ = ["lib", "lib_path", "BatchedPlan", "batched_plan", "id_batched", "BatchedGraph", "batched_graph", "profile_enable", "profile_stages",
            "profile_read", "profile_reset", "id_sketch", "id_project", "id_select", "id_select_noalloc",
-           "matrix_id", "tensor_id", "gaussian_sketch", "gaussian_id", "check_status", "set_wait_limit", "select_plan_info", "stream_read",
+           "matrix_id", "tensor_id", "gaussian_sketch", "gaussian_id", "check_status", "set_wait_limit", "select_plan_info", "stream_read", "tune_set", "tune_get",
            "finalize", "IdsError", "F64", "F32", "BF16", "HASH_FULLRANK", "CHECK_FINITE", "EXPORTED",
            "OK", "ETIMEOUT", "ERANKDEF", "ENONFINITE"]
 
@@ -40,8 +40,9 @@ OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ETIMEOUT, ERANKDEF, ENONFINITE = range(8)
 
 EXPORTED = ["ids_sketch_workspace_size", "id_sketch", "id_project", "ids_gaussian_workspace_size",
             "id_gaussian_sketch", "ids_select_workspace_size",
-            "id_select", "id_select_noalloc", "ids_set_wait_limit", "ids_select_plan_info", "ids_stream_read", "ids_tensor_workspace_size", "tensor_id",
-            "ids_batched_plan_size", "ids_batched_plan", "id_batched", "ids_profile_enable", "ids_profile_stages",
+            "id_select", "id_select_noalloc", "ids_set_wait_limit", "ids_select_plan_info", "ids_stream_read", "ids_tune_set", "ids_tune_get", "ids_tensor_workspace_size", "tensor_id",
+            "ids_batched_plan_size", "ids_batched_plan", "id_batched", "ids_batched_graph_create",
+            "ids_batched_graph_launch", "ids_batched_graph_destroy", "ids_profile_enable", "ids_profile_stages",
             "ids_profile_read", "ids_profile_reset", "ids_finalize", "ids_status_string", "ids_last_error"]
 
 c_i64 = ctypes.c_int64
@@ -89,6 +90,10 @@ def lib():
         L.id_select_noalloc.restype = c_i32
         L.ids_select_plan_info.argtypes = [c_i64, c_i64, c_i64, c_vp]
         L.ids_select_plan_info.restype = c_i32
+        L.ids_tune_set.argtypes = [ctypes.c_char_p, c_i64]
+        L.ids_tune_set.restype = c_i32
+        L.ids_tune_get.argtypes = [ctypes.c_char_p, P(c_i64)]
+        L.ids_tune_get.restype = c_i32
         L.ids_stream_read.argtypes = [c_vp, c_sz, c_vp, c_vp]
         L.ids_stream_read.restype = c_i32
         L.ids_set_wait_limit.argtypes = [c_i64]
@@ -102,7 +107,13 @@ def lib():
         L.ids_batched_plan.argtypes = [c_i64, c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_sz, P(c_sz), c_vp]
         L.id_batched.argtypes = [c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_u64, ctypes.c_double, c_vp, c_vp, c_vp,
                                  c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]
-        for fn in ("ids_batched_plan_size", "ids_batched_plan", "id_batched"):
+        L.ids_batched_graph_create.argtypes = [c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_u64, ctypes.c_double,
+                                               c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, P(c_vp)]
+        L.ids_batched_graph_launch.argtypes = [c_vp, c_vp]
+        L.ids_batched_graph_destroy.argtypes = [c_vp]
+        L.ids_batched_graph_destroy.restype = None
+        for fn in ("ids_batched_plan_size", "ids_batched_plan", "id_batched", "ids_batched_graph_create",
+                   "ids_batched_graph_launch"):
             getattr(L, fn).restype = c_i32
         L.ids_profile_enable.argtypes = [c_i32]
         L.ids_profile_enable.restype = None
@@ -216,6 +227,17 @@ def stream_read(buf, checksum, stream=None):
     nbytes = buf.numel() * buf.element_size()
     _check(lib().ids_stream_read(c_vp(buf.data_ptr()), nbytes, c_vp(checksum.data_ptr()), _stream(torch, stream)),
            "ids_stream_read")
+
+
+def tune_set(key: str, value: int | None):
+    """Override a launch-shape knob (None: back to the tuned table's value)."""
+    _check(lib().ids_tune_set(key.encode(), -1 if value is None else int(value)), "ids_tune_set")
+
+
+def tune_get(key: str) -> int:
+    v = c_i64(0)
+    _check(lib().ids_tune_get(key.encode(), ctypes.byref(v)), "ids_tune_get")
+    return v.value
 
 
 def set_wait_limit(polls: int | None = None):
@@ -483,3 +505,51 @@ def id_batched(plan: BatchedPlan, A, G, seed: int = 0, tol: float = 0.0, stream=
         start = ws[1] - ws[0].data_ptr()
         out["Y"] = ws[0][start:start + 4 * ny].view(torch.float32).clone()
     return out
+
+
+class BatchedGraph:
+    """One id_batched call recorded into a HIP graph (ids_batched_graph_create);
+    launch() replays the whole batch on the current stream.  It owns its
+    outputs (J, P, k_eff, status) and workspace, which every replay
+    overwrites."""
+
+    def __init__(self, plan: BatchedPlan, A, G, seed: int, tol: float):
+        torch = _torch()
+        dev = A.device
+        self.plan, self.A, self.G = plan, A, G
+        self.ws, self.wsb = _workspace(torch, plan.ws_bytes, dev)
+        self.J = torch.empty((plan.nprob, plan.k), dtype=torch.int64, device=dev)
+        self.P = torch.empty(int(plan.p_off[-1]), dtype=torch.float64, device=dev)
+        self.k_eff = torch.empty(plan.nprob, dtype=torch.int64, device=dev)
+        self.status = _status(torch, dev, plan.nprob)
+        h = c_vp()
+        _check(lib().ids_batched_graph_create(plan.nprob, c_vp(plan.m.ctypes.data), c_vp(plan.n.ctypes.data),
+                                              c_vp(plan.buf.data_ptr()), plan.k, plan.l, plan.l1max, seed,
+                                              float(tol), c_vp(A.data_ptr()), c_vp(G.data_ptr()),
+                                              c_vp(self.J.data_ptr()), c_vp(self.P.data_ptr()),
+                                              c_vp(self.k_eff.data_ptr()), _ptr(self.status), c_vp(self.ws[1]),
+                                              self.wsb, ctypes.byref(h)), "ids_batched_graph_create")
+        self.handle = h
+
+    def launch(self, stream=None):
+        torch = _torch()
+        _check(lib().ids_batched_graph_launch(self.handle, _stream(torch, stream)), "ids_batched_graph_launch")
+        return dict(J=self.J, P=self.P, k_eff=self.k_eff, status=self.status)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().ids_batched_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batched_graph(plan: BatchedPlan, A, G, seed: int = 0, tol: float = 0.0) -> BatchedGraph:
+    """Record the batched ID of `plan` on A, G into a HIP graph (see BatchedGraph)."""
+    if A.dtype.itemsize != 2 or G.dtype.itemsize != 2:
+        raise IdsError("A and G must be bfloat16")
+    return BatchedGraph(plan, A, G, seed, tol)

@@ -7,6 +7,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "tune.hpp"
 
 namespace ids {
 
@@ -35,6 +36,46 @@ size_t lds_limit() {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
     cache[dev] = (size_t)v;
     return (size_t)v;
+}
+
+// ---------------------------------------------------------------------------
+// launch-shape knobs (tuned table + run-time overrides)
+// ---------------------------------------------------------------------------
+struct TuneKnob {
+    const char* key;
+    int64_t value;
+};
+static const TuneKnob kTuned[] = {
+#include "tuned_table.inc"
+};
+// values each knob accepts
+static bool tune_valid(const std::string& key, int64_t v) {
+    if (key.rfind("select.gl.", 0) == 0) return v == 0 || v == 1;
+    if (key == "trsm.k32") return v == 1 || v == 2 || v == 4;
+    if (key == "trsm.k64") return v == 2 || v == 4;
+    if (key == "trsm.k128") return v == 4 || v == 8;
+    if (key == "batched.rl512" || key == "batched.rl256") return v == 0 || v == 36;
+    if (key == "project.wgs") return v >= 32 && v <= 4096;
+    return false;
+}
+static std::mutex g_tune_mu;
+static std::unordered_map<std::string, int64_t> g_tune_over;
+
+int64_t tune_get(const std::string& key, int64_t dflt) {
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_over.find(key);
+        if (it != g_tune_over.end()) return it->second;
+    }
+    for (const auto& t : kTuned)
+        if (key == t.key) return t.value;
+    return dflt;
+}
+
+static bool tune_known(const std::string& key) {
+    for (const auto& t : kTuned)
+        if (key == t.key) return true;
+    return false;
 }
 
 // ---------------------------------------------------------------------------
@@ -147,7 +188,7 @@ static SketchLayout sketch_layout(const ids_matrix* A, const ids_sketch_cfg* c) 
     L.bop = (A->fmt == IDS_CSR) ? align256(sizeof(int32_t) * (size_t)A->m) : 0;
     // a projection with few output tiles splits its K (the l1 sketch rows) so
     // that about 256 workgroups share it; the partial products need l x n each
-    L.splits = (c->l < c->l1) ? project_splits(c->l, c->l1, A->n, 256) : 1;
+    L.splits = (c->l < c->l1) ? project_splits(c->l, c->l1, A->n, tune_get("project.wgs", 256)) : 1;
     L.part = (L.splits > 1) ? align256(esize(c->acc) * (size_t)L.splits * c->l * A->n) : 0;
     L.total = L.plan + L.y1 + L.bop + L.part;
     return L;
@@ -385,6 +426,26 @@ ids_status ids_select_workspace_size(int64_t l, int64_t n, int64_t k, size_t* by
 
 void ids_set_wait_limit(int64_t polls) { set_wait_limit(polls); }
 
+ids_status ids_tune_set(const char* key, int64_t value) {
+    g_err.clear();
+    if (!key || !tune_known(key)) return fail(IDS_EINVAL, std::string("unknown knob ") + (key ? key : "(null)"));
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    if (value < 0) {
+        g_tune_over.erase(key);
+        return IDS_OK;
+    }
+    if (!tune_valid(key, value)) return fail(IDS_EINVAL, std::string("value not accepted by knob ") + key);
+    g_tune_over[key] = value;
+    return IDS_OK;
+}
+
+ids_status ids_tune_get(const char* key, int64_t* value) {
+    g_err.clear();
+    if (!key || !value || !tune_known(key)) return fail(IDS_EINVAL, "unknown knob or NULL value");
+    *value = tune_get(key, -1);
+    return IDS_OK;
+}
+
 ids_status ids_stream_read(const void* p, size_t bytes, uint32_t* checksum, void* stream) {
     g_err.clear();
     if (!p || !checksum) return fail(IDS_EINVAL, "p and checksum must be non-NULL");
@@ -607,23 +668,59 @@ ids_status ids_batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, i
     return batched_plan(nprob, m, n, k, l, l1max, plan, plan_bytes, ws_bytes, (hipStream_t)stream);
 }
 
-ids_status id_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* plan, int64_t k, int64_t l,
-                      int64_t l1max, uint64_t seed, double tol, const void* A, const void* G, int64_t* J, double* P,
-                      int64_t* k_eff, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
-    g_err.clear();
+static ids_status batched_args(int64_t nprob, const int64_t* m, const int64_t* n, const void* plan, int64_t k,
+                               int64_t l, int64_t l1max, double tol, const void* A, const void* G, int64_t* J,
+                               double* P, int64_t* k_eff, void* ws, size_t ws_bytes, int64_t* a_elems,
+                               int64_t* y_elems, int64_t* r_elems) {
     ids_status s = validate_batched(nprob, m, n, k, l, l1max);
     if (s) return s;
     if (!(tol >= 0.0 && tol < 1.0)) return fail(IDS_EINVAL, "tol must be in [0, 1)");
     if (!plan || !A || !G || !J || !P || !k_eff) return fail(IDS_EINVAL, "plan, A, G, J, P and k_eff required");
-    int64_t a_elems = 0, y_elems = 0, r_elems = 0;
+    *a_elems = *y_elems = *r_elems = 0;
     for (int64_t q = 0; q < nprob; ++q) {
-        a_elems += m[q] * n[q];
-        y_elems += l * n[q];
-        r_elems += n[q];
+        *a_elems += m[q] * n[q];
+        *y_elems += l * n[q];
+        *r_elems += n[q];
     }
-    const size_t need = align256(sizeof(float) * (size_t)y_elems) + align256(sizeof(double) * (size_t)r_elems * k) +
-                        align256(sizeof(int32_t) * (size_t)r_elems) + align256(sizeof(double) * (size_t)nprob * k);
-    if ((s = check_ws(ws, ws_bytes, need))) return s;
+    const size_t need = align256(sizeof(float) * (size_t)*y_elems) +
+                        align256(sizeof(double) * (size_t)*r_elems * k) +
+                        align256(sizeof(int32_t) * (size_t)*r_elems) + align256(sizeof(double) * (size_t)nprob * k);
+    return check_ws(ws, ws_bytes, need);
+}
+
+ids_status ids_batched_graph_create(int64_t nprob, const int64_t* m, const int64_t* n, const void* plan, int64_t k,
+                                    int64_t l, int64_t l1max, uint64_t seed, double tol, const void* A,
+                                    const void* G, int64_t* J, double* P, int64_t* k_eff, int32_t* status,
+                                    void* ws, size_t ws_bytes, ids_batched_graph* graph) {
+    g_err.clear();
+    if (!graph) return fail(IDS_EINVAL, "graph is NULL");
+    int64_t ae, ye, re;
+    ids_status s = batched_args(nprob, m, n, plan, k, l, l1max, tol, A, G, J, P, k_eff, ws, ws_bytes, &ae, &ye, &re);
+    if (s) return s;
+    void* h = nullptr;
+    if ((s = batched_graph_create(nprob, plan, k, l, l1max, seed, tol, A, G, J, P, k_eff, status, ws, ws_bytes, ae,
+                                  ye, re, &h)))
+        return s;
+    *graph = (ids_batched_graph)h;
+    return IDS_OK;
+}
+
+ids_status ids_batched_graph_launch(ids_batched_graph graph, void* stream) {
+    g_err.clear();
+    if (!graph) return fail(IDS_EINVAL, "graph is NULL");
+    return batched_graph_launch((void*)graph, (hipStream_t)stream);
+}
+
+void ids_batched_graph_destroy(ids_batched_graph graph) { batched_graph_destroy((void*)graph); }
+
+ids_status id_batched(int64_t nprob, const int64_t* m, const int64_t* n, const void* plan, int64_t k, int64_t l,
+                      int64_t l1max, uint64_t seed, double tol, const void* A, const void* G, int64_t* J, double* P,
+                      int64_t* k_eff, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    int64_t a_elems, y_elems, r_elems;
+    ids_status s = batched_args(nprob, m, n, plan, k, l, l1max, tol, A, G, J, P, k_eff, ws, ws_bytes, &a_elems,
+                                &y_elems, &r_elems);
+    if (s) return s;
     return batched_run(nprob, plan, k, l, l1max, seed, tol, A, G, J, P, k_eff, status, ws, ws_bytes, a_elems,
                        y_elems, r_elems, (hipStream_t)stream);
 }

@@ -25,6 +25,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "solve.hpp"
+#include "tune.hpp"
 
 namespace ids {
 
@@ -427,11 +428,10 @@ __global__ __launch_bounds__(BS_THREADS, 4) void batched_sketch_kernel(BatchArgs
 // K2: CPQR, FP32 data, FP64 norms
 // ---------------------------------------------------------------------------
 constexpr int BC_THREADS = 1024;  // largest workgroup: n_p <= 1024 columns, one per thread
-constexpr int BC_RL = 36;   // rows held in LDS (the first ones: frozen after step RL);
-                            // a multiple of 4, so the register rows' reflector entries
-                            // start 16-byte aligned in LDS
-constexpr int BC_RR = 86;   // rows held in registers (RL + RR >= l)
-static_assert(BC_RL + BC_RR >= 122 && BC_RL + BC_RR <= BS_LMAX, "batched CPQR row split");
+constexpr int BC_ROWS = 122;  // sketch rows held per column (l <= 122)
+constexpr int BC_RL = 36;     // rows in LDS for the 1024-thread class (a multiple of 4, so
+                              // the register rows' reflector entries start 16-byte aligned)
+static_assert(BC_ROWS <= BS_LMAX, "batched CPQR rows");
 
 // wave argmax of (nu, j): DPP max tree for nu, then DPP min tree over the j
 // of the lanes holding the maximum; both fold into lane 63 and are broadcast.
@@ -476,12 +476,17 @@ __device__ __forceinline__ double tree_sum_d(double (&s)[N]) {
 
 // NT threads per problem, launched for the problems with NT/2 < n_p <= NT
 // (n_p <= NT for the smallest NT), so small problems share a CU and hide each
-// other's per-step latency.
-template <int NT>
-__global__ __launch_bounds__(NT, 4) void batched_cpqr_kernel(BatchArgs a, int nt_min) {  // 4 waves per SIMD
-    extern __shared__ float ylds[];           // BC_RL x NT
+// other's per-step latency.  RL of the BC_ROWS rows live in LDS (the first
+// ones, frozen after step RL), the rest in registers: 1024 threads get at
+// most 128 VGPRs each (4 waves per SIMD), so the widest class keeps 36 rows in
+// LDS; 512 and 256 threads keep every row in registers (up to 256 VGPRs, 2
+// waves per SIMD).
+template <int NT, int RL>
+__global__ __launch_bounds__(NT, RL ? 4 : 2) void batched_cpqr_kernel(BatchArgs a, int nt_min) {
+    constexpr int RR = BC_ROWS - RL;          // rows in registers
+    extern __shared__ float ylds[];           // RL x NT
     __shared__ __attribute__((aligned(16))) float xf[BS_LMAX];  // pivot column (FP32)
-    __shared__ __attribute__((aligned(16))) float vb[BS_LMAX];  // reflector (FP32)
+    __shared__ double s_hh[2];                                  // tau scal^2, beta
     __shared__ double s_nu[16];
     __shared__ int s_j[16];
 
@@ -496,23 +501,23 @@ __global__ __launch_bounds__(NT, 4) void batched_cpqr_kernel(BatchArgs a, int nt
     bool alive = j < n;
     const float* Yp = a.Y + pr.y_off;
 
-    float y[BC_RR];
+    float y[RR];
     {
         // column j of Y_p (clamped addresses, so every load is unconditional
         // and all are in flight together; masked after compiler barriers):
         // the LDS rows travel through y first, then the register rows
-        static_assert(BC_RL <= BC_RR, "LDS rows are staged in y");
+        static_assert(RL <= RR, "LDS rows are staged in y");
         const float* colp = Yp + (int64_t)min(j, n - 1) * l;
 #pragma unroll
-        for (int r = 0; r < BC_RL; ++r) y[r] = colp[min(r, l - 1)];
+        for (int r = 0; r < RL; ++r) y[r] = colp[min(r, l - 1)];
         asm volatile("" ::: "memory");
 #pragma unroll
-        for (int r = 0; r < BC_RL; ++r) ylds[r * NT + j] = (alive && r < l) ? y[r] : 0.f;
+        for (int r = 0; r < RL; ++r) ylds[r * NT + j] = (alive && r < l) ? y[r] : 0.f;
 #pragma unroll
-        for (int r = 0; r < BC_RR; ++r) y[r] = colp[min(BC_RL + r, l - 1)];
+        for (int r = 0; r < RR; ++r) y[r] = colp[min(RL + r, l - 1)];
         asm volatile("" ::: "memory");
 #pragma unroll
-        for (int r = 0; r < BC_RR; ++r) y[r] = (alive && BC_RL + r < l) ? y[r] : 0.f;
+        for (int r = 0; r < RR; ++r) y[r] = (alive && RL + r < l) ? y[r] : 0.f;
     }
     // sum of squares over rows i >= t0: squares summed in FP32 over chunks of 8
     // rows, the chunk sums accumulated in FP64 (relative error <= 8 * 2^-24,
@@ -522,18 +527,18 @@ __global__ __launch_bounds__(NT, 4) void batched_cpqr_kernel(BatchArgs a, int nt
         double s = 0.0;
         float f[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
-        for (int r = t0; r < BC_RL; ++r) {
+        for (int r = t0; r < RL; ++r) {
             const float v = ylds[r * NT + j];
             f[r & 3] = fmaf(v, v, f[r & 3]);
         }
         s = (double)((f[0] + f[1]) + (f[2] + f[3]));
 #pragma unroll
-        for (int c = 0; c < BC_RR; c += 8) {
-            if (BC_RL + c + 8 > t0) {
+        for (int c = 0; c < RR; c += 8) {
+            if (RL + c + 8 > t0) {
                 float q = 0.f;
 #pragma unroll
-                for (int r = c; r < c + 8 && r < BC_RR; ++r) {
-                    const float v = (BC_RL + r >= t0) ? y[r] : 0.f;
+                for (int r = c; r < c + 8 && r < RR; ++r) {
+                    const float v = (RL + r >= t0) ? y[r] : 0.f;
                     q = fmaf(v, v, q);
                 }
                 s += (double)q;
@@ -579,57 +584,63 @@ __global__ __launch_bounds__(NT, 4) void batched_cpqr_kernel(BatchArgs a, int nt
             keff = t;
             break;
         }
-        // ---- pivot column to LDS: rows in registers by the owner lane, rows in
-        //      LDS copied by BC_RL threads
+        // ---- pivot column x to LDS (rows above t zeroed) and the Householder
+        //      scalars, formed by the pivot's owner lane in FP64 from
+        //      alpha = x_t and the published trailing norm wnu = ||x_{t..}||^2:
+        //      v = scal * x' with x'_t = alpha - beta (so v_t = 1) and x'_i = x_i
+        //      below t, so the update needs x' and the scalars only -- one
+        //      workgroup barrier for both.  The owner's register rows go out as
+        //      they are, its LDS rows and the other rows < RL are copied by the
+        //      threads j < RL (thread t leaves row t to the owner).
         if (j == wj) {
 #pragma unroll
-            for (int r = 0; r < BC_RR; ++r) xf[BC_RL + r] = y[r];
+            for (int r = 0; r < RR; ++r) xf[RL + r] = (RL + r < t) ? 0.f : y[r];
+            const double alpha = (double)((t < RL) ? ylds[t * NT + j] : xf[t]);
+            double tau_o, beta_o, scal_o;
+            if (!(wnu > alpha * alpha)) {
+                tau_o = 0.0;
+                beta_o = alpha;
+                scal_o = 0.0;
+            } else {
+                const double nrm = sqrt(wnu);
+                beta_o = (alpha >= 0.0) ? -nrm : nrm;
+                tau_o = (beta_o - alpha) / beta_o;
+                scal_o = 1.0 / (alpha - beta_o);
+            }
+            xf[t] = (float)(alpha - beta_o);
+            s_hh[0] = tau_o * scal_o * scal_o;  // H y = y - (tau scal^2 x'^T y) x'
+            s_hh[1] = beta_o;
         }
-        if (j < BC_RL) xf[j] = ylds[j * NT + wj];
+        if (j < RL && j != t) xf[j] = (j < t) ? 0.f : ylds[j * NT + wj];
         __syncthreads();
-        // ---- Householder reflector in FP64 (every wave, same bits); the norm of
-        //      the pivot's rows t.. is its published trailing norm wnu
-        const double alpha = (double)xf[t];
-        double tau, beta, scal;
-        if (!(wnu > alpha * alpha)) {
-            tau = 0.0;
-            beta = alpha;
-            scal = 0.0;
-        } else {
-            const double nrm = sqrt(wnu);
-            beta = (alpha >= 0.0) ? -nrm : nrm;
-            tau = (beta - alpha) / beta;
-            scal = 1.0 / (alpha - beta);
-        }
-        if (j < BS_LMAX) vb[j] = (j < t || j >= l) ? 0.f : (j == t ? 1.f : (float)((double)xf[j] * scal));
-        __syncthreads();
+        const double tss = s_hh[0], beta = s_hh[1];
         // ---- apply H to the live columns (FP32 dot and update), new norms
         if (wave_live) {
             if (alive) {
                 float d[4] = {0.f, 0.f, 0.f, 0.f};
-                if (t < BC_RL) {
+                if (t < RL) {
 #pragma unroll 4
-                    for (int r = t; r < BC_RL; ++r) d[r & 3] = fmaf(vb[r], ylds[r * NT + j], d[r & 3]);
+                    for (int r = t; r < RL; ++r) d[r & 3] = fmaf(xf[r], ylds[r * NT + j], d[r & 3]);
                 }
 #pragma unroll
-                for (int c = 0; c < BC_RR; c += 8)
-                    if (BC_RL + c + 8 > t) {
+                for (int c = 0; c < RR; c += 8)
+                    if (RL + c + 8 > t) {
 #pragma unroll
-                        for (int r = c; r < c + 8 && r < BC_RR; ++r)
-                            if (BC_RL + r < BS_LMAX) d[r & 3] = fmaf(vb[BC_RL + r], y[r], d[r & 3]);
+                        for (int r = c; r < c + 8 && r < RR; ++r)
+                            if (RL + r < BS_LMAX) d[r & 3] = fmaf(xf[RL + r], y[r], d[r & 3]);
                     }
-                const float dt = ((d[0] + d[1]) + (d[2] + d[3])) * (float)tau;
-                if (t < BC_RL) {
+                const float dt = (float)((double)((d[0] + d[1]) + (d[2] + d[3])) * tss);
+                if (t < RL) {
 #pragma unroll 4
-                    for (int r = t; r < BC_RL; ++r)
-                        ylds[r * NT + j] = fmaf(-dt, vb[r], ylds[r * NT + j]);
+                    for (int r = t; r < RL; ++r)
+                        ylds[r * NT + j] = fmaf(-dt, xf[r], ylds[r * NT + j]);
                 }
 #pragma unroll
-                for (int c = 0; c < BC_RR; c += 8)
-                    if (BC_RL + c + 8 > t) {
+                for (int c = 0; c < RR; c += 8)
+                    if (RL + c + 8 > t) {
 #pragma unroll
-                        for (int r = c; r < c + 8 && r < BC_RR; ++r)
-                            if (BC_RL + r < BS_LMAX) y[r] = fmaf(-dt, vb[BC_RL + r], y[r]);
+                        for (int r = c; r < c + 8 && r < RR; ++r)
+                            if (RL + r < BS_LMAX) y[r] = fmaf(-dt, xf[RL + r], y[r]);
                     }
                 if (j == wj) {
                     alive = false;
@@ -647,10 +658,10 @@ __global__ __launch_bounds__(NT, 4) void batched_cpqr_kernel(BatchArgs a, int nt
     // top keff rows of every column -> Rt (FP64); the pivots' diagonal is beta
     if (j < n) {
         double* Rj = a.Rt + roff * (int64_t)k + (int64_t)j * k;
-        for (int i = 0; i < min(keff, BC_RL); ++i) Rj[i] = (double)ylds[i * NT + j];
+        for (int i = 0; i < min(keff, RL); ++i) Rj[i] = (double)ylds[i * NT + j];
 #pragma unroll
-        for (int r = 0; r < BC_RR; ++r)
-            if (BC_RL + r < keff) Rj[BC_RL + r] = (double)y[r];
+        for (int r = 0; r < RR; ++r)
+            if (RL + r < keff) Rj[RL + r] = (double)y[r];
     }
     if (j == 0) {
         a.keff[p] = keff;
@@ -660,57 +671,158 @@ __global__ __launch_bounds__(NT, 4) void batched_cpqr_kernel(BatchArgs a, int nt
 }
 
 // ---------------------------------------------------------------------------
-// K3: interpolation matrix per problem (FP64)
+// K3: interpolation matrix per problem on the FP64 matrix cores
 // ---------------------------------------------------------------------------
-// One workgroup per problem: R11 staged transposed in LDS (the columns J[r] of
-// Rt, rows above the diagonal; reciprocal diagonals from the FP64 beta), then
-// the non-pivot columns are solved 512 / GQ at a time with the axpy
-// back-substitution (no workgroup barrier inside the solve).
-constexpr int BT_THREADS = 512;  // 32 right-hand-side slots per lane need up to 256 VGPRs
-template <int GQ>
-__global__ __launch_bounds__(BT_THREADS) void batched_trsm_kernel(BatchArgs a, int nlo, int nhi) {
-    constexpr int KS = TRSM_AX_KS, LDK = trsm_ax_ldk<GQ>(), NT = BT_THREADS;
-    extern __shared__ __attribute__((aligned(16))) double sm3[];
-    __shared__ int32_t Js[BS_LMAX];
-    const int p = blockIdx.x;
+// T = R11^{-1} R12 by block back-substitution over 16-row blocks,
+//   T_i = R_ii^{-1} (R12_i - sum_{l > i} R_il T_l),   i = nb - 1, ..., 0,
+// with R11 padded to 16 nb rows (identity past keff).  R11[t][t] is the FP64
+// beta of step t, the entries above the diagonal are the top rows of the
+// pivot columns (Rt).  The workgroup stages the blocks R_il (l > i, negated)
+// and the inverses of the 16 x 16 diagonal blocks (back-substitution, one
+// thread per column) in LDS, every block column-major so that the MFMA A
+// operand of K slice q is the 64 consecutive doubles 64 q .. 64 q + 63.  The
+// non-pivot columns are gathered into a list; each wave then solves whole
+// 16-column tiles of that list on its own (no barrier): the tile's nb
+// accumulators stay in registers, v_mfma_f64_16x16x4f64 forms every product
+// (4 K slices per block), and since the FP64 result layout (register r: row
+// 4 r + lane / 16, column lane % 16) is the B operand layout of K slice r, a
+// solved block T_l feeds the later products without any exchange.  Columns
+// are independent in every product, so a column's result does not depend on
+// the tile it lands in.  Pivot column J[t] gets e_t exactly.
+constexpr int BT_THREADS = 256;
+constexpr int BT_NBMAX = 8;  // 16-row blocks (k <= 128)
+typedef double v4f64 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int tri_blk(int i, int l) { return l * (l + 1) / 2 + i; }  // block (i, l), i <= l
+
+size_t batched_solve_lds(int64_t k) {
+    const int nb = (int)((k + 15) / 16);
+    return sizeof(double) * 256 * (size_t)(nb * (nb + 1) / 2);
+}
+
+__global__ __launch_bounds__(BT_THREADS) void batched_solve_kernel(BatchArgs a) {
+    extern __shared__ __attribute__((aligned(16))) double blk[];  // nb (nb + 1) / 2 blocks of 256
+    __shared__ int32_t Js[16 * BT_NBMAX];
+    __shared__ int16_t cl[1024];   // non-pivot columns
+    __shared__ int ncl;
+    const int p = a.order[blockIdx.x];
     const BProb pr = a.prob[p];
-    const int n = pr.n;
-    if (n <= nlo || n > nhi) return;  // another launch owns this problem
-    const int k = (int)a.k;
+    const int n = pr.n, k = (int)a.k;
     const int keff = (int)a.keff[p];
-    const int tid = threadIdx.x;
+    const int nb = (keff + 15) / 16;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t* J = a.J + (int64_t)p * k;
     const double* bt = a.beta + (int64_t)p * k;
     const double* Rt = a.Rt + pr.r_off * (int64_t)k;
     const int32_t* pos = a.pos + pr.r_off;
     double* P = a.P + pr.p_off;
-    double* R11T = sm3;                       // keff x LDK
-    double* rd = sm3 + (size_t)keff * LDK;    // keff
-    if (tid < keff) Js[tid] = (int32_t)J[tid];
+    if (tid == 0) ncl = 0;
+    for (int t = tid; t < 16 * nb; t += BT_THREADS) Js[t] = t < keff ? (int32_t)J[t] : 0;
     __syncthreads();
-    stage_r11t<GQ, 4>(R11T, keff, k, NT, [&](int r, int c) { return Rt[(int64_t)Js[r] * k + c]; });
-    copy_batched<1>(keff, NT, [&](int r) { return bt[r]; }, [&](int r, double v) { rd[r] = 1.0 / v; });
+    for (int j = tid; j < n; j += BT_THREADS)
+        if (pos[j] < 0) cl[atomicAdd(&ncl, 1)] = (int16_t)j;
+    // R11 blocks: element (m, kk) of block (i, l) = R11[16 i + m][16 l + kk] at
+    // kk * 16 + m; thread tid holds element (tid & 15, tid >> 4) of every
+    // block, and the loads of 8 blocks are issued before any is stored
+    const int nblk = nb * (nb + 1) / 2;
+    {
+        const int m = tid & 15, kk = tid >> 4;
+        for (int b0 = 0; b0 < nblk; b0 += 8) {
+            double v[8];
+            int rr[8], cc[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = min(b0 + u, nblk - 1);
+                int l = 0;
+                while ((l + 1) * (l + 2) / 2 <= b) ++l;
+                rr[u] = 16 * (b - l * (l + 1) / 2) + m;
+                cc[u] = 16 * l + kk;
+                const bool above = rr[u] < cc[u] && cc[u] < keff;
+                v[u] = Rt[above ? (int64_t)Js[cc[u]] * k + rr[u] : 0];
+            }
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (b0 + u >= nblk) break;
+                const int r = rr[u], c = cc[u];
+                double x;
+                if (r < keff && c < keff)
+                    x = r < c ? v[u] : (r == c ? bt[r] : 0.0);
+                else
+                    x = (r == c) ? 1.0 : 0.0;
+                // off-diagonal blocks negated (the updates subtract), diagonal
+                // blocks as they are (inverted below)
+                blk[256 * (b0 + u) + tid] = ((r >> 4) == (c >> 4)) ? x : -x;
+            }
+        }
+    }
     __syncthreads();
-    const int q = tid % GQ;
-    for (int j0 = 0; j0 < n; j0 += NT / GQ) {
-        const int j = j0 + tid / GQ;
-        if (j >= n) continue;
-        const int32_t pj = pos[j];
-        if (pj >= 0) {  // P[:, j] = e_pos
-            for (int c = q; c < k; c += GQ) P[(int64_t)c * n + j] = (c == pj) ? 1.0 : 0.0;
-            continue;
-        }
-        double b[KS];
+    // diagonal blocks -> inverses: thread (di, dc) solves R_ii x = e_dc
+    {
+        const int di = tid >> 4, dc = tid & 15;
+        double x[16];
+        const double* D = blk + 256 * tri_blk(min(di, BT_NBMAX - 1), min(di, BT_NBMAX - 1));
+        if (di < nb) {
 #pragma unroll
-        for (int sl = 0; sl < KS; ++sl) {
-            const int c = GQ * sl + q;
-            b[sl] = (c < keff) ? Rt[(int64_t)j * k + c] : 0.0;
-        }
-        axpy_solve<GQ>(b, R11T, rd, keff, q);
+            for (int r = 15; r >= 0; --r) {
+                double s = (r == dc) ? 1.0 : 0.0;
 #pragma unroll
-        for (int sl = 0; sl < KS; ++sl) {
-            const int c = GQ * sl + q;
-            if (c < k) P[(int64_t)c * n + j] = (c < keff) ? b[sl] : 0.0;
+                for (int c = r + 1; c < 16; ++c) s = fma(-D[c * 16 + r], x[c], s);
+                x[r] = s / D[r * 16 + r];
+            }
+        }
+        __syncthreads();
+        if (di < nb) {
+            double* Dw = blk + 256 * tri_blk(di, di);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) Dw[dc * 16 + r] = x[r];
+        }
+    }
+    __syncthreads();
+    // pivot columns: P[:, J[t]] = e_t
+    for (int e = tid; e < keff * k; e += BT_THREADS) {
+        const int t = e / k, row = e - t * k;
+        P[(int64_t)row * n + Js[t]] = (row == t) ? 1.0 : 0.0;
+    }
+    const int m_cl = ncl, col = lane & 15, rq = lane >> 4;
+    for (int t0 = 16 * w; t0 < m_cl; t0 += 16 * (BT_THREADS / 64)) {
+        const int jj = t0 + col;
+        const int j = cl[min(jj, m_cl - 1)];
+        v4f64 acc[BT_NBMAX];
+        // right-hand sides R[0:keff, j] (clamped loads, all in flight, then masked)
+#pragma unroll
+        for (int i = 0; i < BT_NBMAX; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][r] = Rt[(int64_t)j * k + min(16 * i + 4 * r + rq, max(keff - 1, 0))];
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int i = 0; i < BT_NBMAX; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][r] = (16 * i + 4 * r + rq < keff) ? acc[i][r] : 0.0;
+#pragma unroll
+        for (int i = BT_NBMAX - 1; i >= 0; --i) {
+            if (i >= nb) continue;
+#pragma unroll
+            for (int l = i + 1; l < BT_NBMAX; ++l) {
+                if (l >= nb) continue;
+                const double* A = blk + 256 * tri_blk(i, l);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[64 * q + lane], acc[l][q], acc[i], 0, 0, 0);
+            }
+            const double* Di = blk + 256 * tri_blk(i, i);
+            v4f64 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x = __builtin_amdgcn_mfma_f64_16x16x4f64(Di[64 * q + lane], acc[i][q], x, 0, 0, 0);
+            acc[i] = x;
+        }
+        if (jj < m_cl) {
+#pragma unroll
+            for (int i = 0; i < BT_NBMAX; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * i + 4 * r + rq;
+                    if (row < k) P[(int64_t)row * n + j] = (row < keff) ? acc[i][r] : 0.0;
+                }
         }
     }
 }
@@ -840,7 +952,7 @@ void batched_release() {
 ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, int64_t l1max, uint64_t seed,
                        double tol, const void* A, const void* G, int64_t* J, double* P, int64_t* keff,
                        int32_t* status, void* ws, size_t ws_bytes, int64_t a_elems, int64_t y_elems,
-                       int64_t r_elems, hipStream_t st) {
+                       int64_t r_elems, hipStream_t st, bool prof) {
     size_t op, o1, o2;
     plan_layout(nprob, &op, &o1, &o2);
     BatchArgs a;
@@ -870,16 +982,15 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
     a.status = status;
     (void)ws_bytes;
     {
-        ProfScope ps(PK_CS, st);
+        ProfScope ps(prof ? PK_CS : -1, st);
         a.order = (const int32_t*)((const char*)plan + o1);
         hipLaunchKernelGGL(batched_sketch_kernel, dim3((unsigned)nprob), dim3(BS_THREADS), 0, st, a);
     }
     {
-        // CPQR and solve together: the problems of each width class (n_p in
-        // (512, 1024], (256, 512], (0, 256]) go through their CPQR and then
-        // their solve on a stream of their own, so one class's solve overlaps
-        // the others' CPQR; stage timing covers both
-        ProfScope ps(PK_CPQR, st);
+        // the problems of each width class (n_p in (512, 1024], (256, 512],
+        // (0, 256]) go through their CPQR on a stream of their own, so the
+        // smaller classes fill the CUs the largest leave idle
+        ProfScope ps(prof ? PK_CPQR : -1, st);
         a.order = (const int32_t*)((const char*)plan + o2);
         std::lock_guard<std::mutex> g(g_side_mu);
         CpqrSide* side = cpqr_side();
@@ -894,28 +1005,20 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
                 s256 = side->s[1];
             }
         }
-        const int gq = k <= 32 ? 1 : (k <= 64 ? 2 : 4);
-        const size_t lds = sizeof(double) * (size_t)k * (gq * TRSM_AX_SQ + 1);
-        auto solve = [&](hipStream_t ss, int nlo, int nhi) {
-            if (gq == 1)
-                hipLaunchKernelGGL(batched_trsm_kernel<1>, dim3((unsigned)nprob), dim3(BT_THREADS), lds, ss, a, nlo,
-                                   nhi);
-            else if (gq == 2)
-                hipLaunchKernelGGL(batched_trsm_kernel<2>, dim3((unsigned)nprob), dim3(BT_THREADS), lds, ss, a, nlo,
-                                   nhi);
-            else
-                hipLaunchKernelGGL(batched_trsm_kernel<4>, dim3((unsigned)nprob), dim3(BT_THREADS), lds, ss, a, nlo,
-                                   nhi);
-        };
-        hipLaunchKernelGGL(batched_cpqr_kernel<1024>, dim3((unsigned)nprob), dim3(1024),
+        // rows in LDS of the 512- and 256-thread classes: tuned knobs (36 or 0)
+        const bool lds512 = tune_get("batched.rl512", BC_RL) != 0, lds256 = tune_get("batched.rl256", BC_RL) != 0;
+        hipLaunchKernelGGL((batched_cpqr_kernel<1024, BC_RL>), dim3((unsigned)nprob), dim3(1024),
                            sizeof(float) * BC_RL * 1024, st, a, 512);
-        hipLaunchKernelGGL(batched_cpqr_kernel<512>, dim3((unsigned)nprob), dim3(512), sizeof(float) * BC_RL * 512,
-                           s512, a, 256);
-        hipLaunchKernelGGL(batched_cpqr_kernel<256>, dim3((unsigned)nprob), dim3(256), sizeof(float) * BC_RL * 256,
-                           s256, a, 0);
-        solve(st, 512, 1024);
-        solve(s512, 256, 512);
-        solve(s256, 0, 256);
+        if (lds512)
+            hipLaunchKernelGGL((batched_cpqr_kernel<512, BC_RL>), dim3((unsigned)nprob), dim3(512),
+                               sizeof(float) * BC_RL * 512, s512, a, 256);
+        else
+            hipLaunchKernelGGL((batched_cpqr_kernel<512, 0>), dim3((unsigned)nprob), dim3(512), 0, s512, a, 256);
+        if (lds256)
+            hipLaunchKernelGGL((batched_cpqr_kernel<256, BC_RL>), dim3((unsigned)nprob), dim3(256),
+                               sizeof(float) * BC_RL * 256, s256, a, 0);
+        else
+            hipLaunchKernelGGL((batched_cpqr_kernel<256, 0>), dim3((unsigned)nprob), dim3(256), 0, s256, a, 0);
         if (s512 != st) {
             // join: the caller's stream waits for both side streams; if the
             // event route fails, wait for them on the host instead, so no work
@@ -931,7 +1034,81 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
             }
         }
     }
+    {
+        // interpolation matrices of all problems (largest n first)
+        ProfScope ps(prof ? PK_TRSM : -1, st);
+        a.order = (const int32_t*)((const char*)plan + o2);
+        hipLaunchKernelGGL(batched_solve_kernel, dim3((unsigned)nprob), dim3(BT_THREADS), batched_solve_lds(k), st,
+                           a);
+    }
     return check_launch("batched ID");
+}
+
+// ---------------------------------------------------------------------------
+// the whole batched call captured once into a HIP graph and replayed
+// ---------------------------------------------------------------------------
+// Captured on a private stream: the side streams join the capture through the
+// fork event, so the graph holds the sketch, the three concurrent CPQR
+// launches and the solve with the fork / join as edges.  No memset or
+// allocation is recorded; replays reuse the caller's buffers.
+struct BatchedGraph {
+    hipGraphExec_t exec = nullptr;
+};
+
+ids_status batched_graph_create(int64_t nprob, const void* plan, int64_t k, int64_t l, int64_t l1max, uint64_t seed,
+                                double tol, const void* A, const void* G, int64_t* J, double* P, int64_t* keff,
+                                int32_t* status, void* ws, size_t ws_bytes, int64_t a_elems, int64_t y_elems,
+                                int64_t r_elems, void** out) {
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        set_error("batched graph: stream creation failed");
+        return IDS_EHIP;
+    }
+    ids_status s = IDS_OK;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        set_error("batched graph: hipStreamBeginCapture failed");
+        s = IDS_EHIP;
+    } else {
+        s = batched_run(nprob, plan, k, l, l1max, seed, tol, A, G, J, P, keff, status, ws, ws_bytes, a_elems, y_elems,
+                        r_elems, cs, false);
+        const hipError_t e = hipStreamEndCapture(cs, &graph);
+        if (!s && (e != hipSuccess || !graph)) {
+            set_error(std::string("batched graph: hipStreamEndCapture: ") + hipGetErrorString(e));
+            s = IDS_EHIP;
+        }
+    }
+    BatchedGraph* bg = nullptr;
+    if (!s) {
+        bg = new BatchedGraph;
+        if (hipGraphInstantiate(&bg->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            set_error("batched graph: hipGraphInstantiate failed");
+            delete bg;
+            bg = nullptr;
+            s = IDS_EHIP;
+        }
+    }
+    if (graph) hipGraphDestroy(graph);
+    hipStreamDestroy(cs);
+    if (!s) *out = bg;
+    return s;
+}
+
+ids_status batched_graph_launch(void* g, hipStream_t st) {
+    BatchedGraph* bg = (BatchedGraph*)g;
+    const hipError_t e = hipGraphLaunch(bg->exec, st);
+    if (e != hipSuccess) {
+        set_error(std::string("batched graph launch: ") + hipGetErrorString(e));
+        return IDS_EHIP;
+    }
+    return IDS_OK;
+}
+
+void batched_graph_destroy(void* g) {
+    BatchedGraph* bg = (BatchedGraph*)g;
+    if (!bg) return;
+    if (bg->exec) hipGraphExecDestroy(bg->exec);
+    delete bg;
 }
 
 }  // namespace ids

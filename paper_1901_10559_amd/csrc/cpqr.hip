@@ -52,6 +52,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "solve.hpp"
+#include "tune.hpp"
 
 namespace ids {
 
@@ -1209,18 +1210,27 @@ static Inst inst_rb() {
             {(const void*)&cpqr_rb_kernel<NC, RB, MB_SPEC>, (const void*)&cpqr_rb_kernel<NC, RB, MB_OWNER>}};
 }
 
-static bool pick(int64_t l, Inst& in) {
+// kernel instance for l rows; variant 1 (a tuned knob) takes 4-wave
+// workgroups instead of 8 for the grouped-lane kernels (twice the
+// publishers, half the threads per vote)
+static bool pick(int64_t l, int variant, Inst& in) {
     // grouped-lane kernels for short sketches, row bands beyond 256 rows
-    if (l <= 32) in = inst_gl<2, 16, 8>();
-    else if (l <= 64) in = inst_gl<4, 16, 8>();
-    else if (l <= 128) in = inst_gl<8, 16, 8>();
-    else if (l <= 256) in = inst_gl<16, 16, 8>();
+    if (l <= 32) in = variant ? inst_gl<2, 16, 4>() : inst_gl<2, 16, 8>();
+    else if (l <= 64) in = variant ? inst_gl<4, 16, 4>() : inst_gl<4, 16, 8>();
+    else if (l <= 128) in = variant ? inst_gl<8, 16, 4>() : inst_gl<8, 16, 8>();
+    else if (l <= 256) in = variant ? inst_gl<16, 16, 4>() : inst_gl<16, 16, 8>();
     else if (l <= 512) in = inst_rb<16, 1>();
     else if (l <= 1024) in = inst_rb<16, 2>();
     else if (l <= 2048) in = inst_rb<8, 4>();
     else if (l <= 4096) in = inst_rb<8, 8>();
     else return false;
     return true;
+}
+
+static int gl_variant(int64_t l, int64_t n) {
+    if (l > 256) return 0;
+    const char* lb = l <= 32 ? "l32" : l <= 64 ? "l64" : l <= 128 ? "l128" : "l256";
+    return (int)tune_get(std::string("select.gl.") + lb + "." + n_bucket(n), 0);
 }
 
 static int64_t round32(int64_t x) { return (x + 31) / 32 * 32; }
@@ -1243,9 +1253,31 @@ static size_t cpqr_lds(const SelectPlan& sp, const Inst& in) {
     return in.gl ? 2 * sizeof(double) * (size_t)(in.rows + in.rows / in.lane_rows) : in.lds_fixed;
 }
 
+// the plan for one kernel variant; IDS_EINVAL if its workgroups cannot all be
+// co-resident for this n
+static ids_status select_plan_variant(int64_t l, int64_t n, int64_t k, int variant, SelectPlan& sp);
+
 ids_status select_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp) {
+    // the tuned variant; a grouped-lane shape too wide for it takes the other
+    // variant if that one holds it (4-wave workgroups are co-resident in
+    // larger numbers)
+    const int v = gl_variant(l, n);
+    ids_status s = select_plan_variant(l, n, k, v, sp);
+    if (s == IDS_EINVAL && l <= 256) {
+        SelectPlan alt;
+        if (select_plan_variant(l, n, k, 1 - v, alt) == IDS_OK) {
+            sp = alt;
+            set_error("");
+            return IDS_OK;
+        }
+    }
+    return s;
+}
+
+static ids_status select_plan_variant(int64_t l, int64_t n, int64_t k, int variant, SelectPlan& sp) {
     Inst in;
-    if (!pick(l, in)) {
+    sp.variant = variant;
+    if (!pick(l, sp.variant, in)) {
         set_error("id_select: l must be <= 4096");
         return IDS_EINVAL;
     }
@@ -1328,7 +1360,7 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
     a.pos = (int32_t*)p;
 
     Inst in;
-    pick(sp.l, in);
+    pick(sp.l, sp.variant, in);
     const int64_t cnt = (int64_t)mb_doubles(sp);
     const unsigned fg = (unsigned)std::min<int64_t>((cnt + 255) / 256, 4096);
     hipLaunchKernelGGL(mb_fill_kernel, dim3(fg), dim3(256), 0, st, (uint64_t*)a.mb, cnt, a.flag,
@@ -1365,12 +1397,17 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
             hipLaunchKernelGGL((trsm_chunk_kernel<KS>), dim3(g16), dim3(256), 0, st, sp.n, sp.k, Rt, R11c, pos,    \
                                (const int64_t*)keff, P);                                                           \
     } while (0)
+    // lanes per column of the solve for k <= 128 (tuned knobs; GQ lanes hold
+    // 32 slots each, so GQ = 1, 2, 4 serve k <= 32, 64, 128; 8 is the
+    // 16-lane dot-product kernel)
     const size_t ax = sizeof(double) * (size_t)sp.k * (trsm_ax_ldk<4>() + 1);
-    if (sp.k <= 32)
+    const int64_t gq = sp.k <= 32 ? tune_get("trsm.k32", 1) : sp.k <= 64 ? tune_get("trsm.k64", 2)
+                                                                            : tune_get("trsm.k128", 4);
+    if (sp.k <= 32 && gq == 1)
         IDS_TRSM_AXPY(1);
-    else if (sp.k <= 64)
+    else if (sp.k <= 64 && gq <= 2)
         IDS_TRSM_AXPY(2);
-    else if (sp.k <= 128 && ax <= lim)
+    else if (sp.k <= 128 && gq <= 4 && ax <= lim)
         IDS_TRSM_AXPY(4);
     else if (sp.k <= 128)
         IDS_TRSM_GROUP(8);

@@ -70,6 +70,7 @@ struct SelectPlan {
     int mode, S, H0;        // mailbox exchange: mode, slot stride, column box offset
     int64_t RS;             // mailbox doubles per factorisation step
     int64_t CS;             // speculative mode: doubles per set of column slots (two sets)
+    int variant;            // kernel variant (tuned knob)
 };
 ids_status select_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp);
 size_t select_bytes(const SelectPlan& sp);
@@ -92,7 +93,14 @@ ids_status batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, int64
 ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, int64_t l1max, uint64_t seed,
                        double tol, const void* A, const void* G, int64_t* J, double* P, int64_t* keff,
                        int32_t* status, void* ws, size_t ws_bytes, int64_t a_elems, int64_t y_elems,
-                       int64_t r_elems, hipStream_t st);
+                       int64_t r_elems, hipStream_t st, bool prof = true);
+// the same call captured into an instantiated HIP graph (opaque handle)
+ids_status batched_graph_create(int64_t nprob, const void* plan, int64_t k, int64_t l, int64_t l1max, uint64_t seed,
+                                double tol, const void* A, const void* G, int64_t* J, double* P, int64_t* keff,
+                                int32_t* status, void* ws, size_t ws_bytes, int64_t a_elems, int64_t y_elems,
+                                int64_t r_elems, void** out);
+ids_status batched_graph_launch(void* g, hipStream_t st);
+void batched_graph_destroy(void* g);
 
 // ---- finiteness scan of a sketch (l x n column-major) -> status word ---------
 ids_status check_finite(int32_t dtype, const void* Y, int64_t l, int64_t n, int64_t ldy, int32_t* status,

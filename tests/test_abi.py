@@ -99,3 +99,21 @@ def test_profile_stage_selection_without_gpu():
     assert b"unknown stage nosuch" in L.ids_last_error()
     assert L.ids_profile_stages(None) == 0
     assert L.ids_profile_stages(b"") == 0
+
+
+def test_tune_knobs_without_gpu():
+    import ctypes as ct
+    L = ids.lib()
+    v = ct.c_int64(0)
+    assert L.ids_tune_get(b"trsm.k64", ct.byref(v)) == 0 and v.value in (2, 4)
+    assert L.ids_tune_set(b"trsm.k64", 4) == 0
+    assert L.ids_tune_get(b"trsm.k64", ct.byref(v)) == 0 and v.value == 4
+    assert L.ids_tune_set(b"trsm.k64", 3) == 1            # not accepted by the knob
+    assert b"not accepted" in L.ids_last_error()
+    assert L.ids_tune_set(b"no.such.knob", 1) == 1
+    assert L.ids_tune_set(b"trsm.k64", -1) == 0           # back to the table's value
+    import paper_1901_10559_amd.tune as tune
+    assert set(tune.HAND_DEFAULTS) == set(tune.CANDIDATES)
+    for key, val in tune.HAND_DEFAULTS.items():
+        assert L.ids_tune_get(key.encode(), ct.byref(v)) == 0, key
+        assert val in tune.CANDIDATES[key]

@@ -147,3 +147,32 @@ def test_batched_fixed_accuracy_rank_and_residual():
         assert np.array_equal(Pp[:r][:, J[p, :r]], np.eye(r))
         of = oracle.matrix_id(A64, k=r, l1=l1, seed=7, tag=p, G=G64[:, :l1])
         assert oracle.residual_fro(A64, J[p, :r], Pp[:r]) <= 2.0 * oracle.residual_fro(A64, of["J"], of["P"])
+
+
+def test_batched_graph_replays_match_eager():
+    # the whole batch recorded into a HIP graph: every replay (with eager work
+    # and synchronisations in between) gives the eager call's bits
+    nprob, k, l, l1max = 96, 30, 40, 128
+    m, n, flat = synth.batched_inputs(nprob, seed=7, mrange=(64, 900), nrange=(40, 1024))
+    Gb = synth.bf16_bits(synth.gaussian(l, l1max, seed=7))
+    plan = ids.batched_plan(m, n, k, l, l1max)
+    At = torch.from_numpy(flat.view(np.int16)).to(DEV).view(torch.bfloat16)
+    Gt = torch.from_numpy(Gb.view(np.int16)).to(DEV).view(torch.bfloat16)
+    for tol in (0.0, 1e-2):
+        eager = ids.id_batched(plan, At, Gt, seed=7, tol=tol)
+        torch.cuda.synchronize()
+        Je, Pe, ke = eager["J"].cpu().numpy(), eager["P"].cpu().numpy(), eager["k_eff"].cpu().numpy()
+        g = ids.batched_graph(plan, At, Gt, seed=7, tol=tol)
+        for rep in range(4):
+            g.P.fill_(float("nan"))
+            g.J.fill_(-7)
+            out = g.launch()
+            torch.cuda.synchronize()
+            assert np.array_equal(out["J"].cpu().numpy(), Je), rep
+            assert np.array_equal(out["k_eff"].cpu().numpy(), ke), rep
+            assert np.array_equal(out["P"].cpu().numpy(), Pe), rep
+            assert set(out["status"].cpu().numpy().tolist()) == {ids.OK}
+            # eager work between replays
+            ids.id_batched(plan, At, Gt, seed=8, tol=tol)
+            torch.cuda.synchronize()
+        g.close()

@@ -149,3 +149,93 @@ def test_stream_read_checksum():
     ids.stream_read(buf, chk)
     torch.cuda.synchronize()
     assert int(chk.item()) & 0xFFFFFFFF == int(np.bitwise_xor.reduce(words))
+
+
+# ---------------------------------------------------------------------------
+# every value of the tuned knobs gives the oracle's results
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("l,n,k", [(30, 1000, 20), (60, 20000, 50), (120, 2000, 100), (120, 9000, 60),
+                                   (250, 800, 201), (250, 4500, 100)])
+def test_select_four_wave_variant(l, n, k):
+    lb = "l32" if l <= 32 else "l64" if l <= 64 else "l128" if l <= 128 else "l256"
+    nb = "n1k" if n <= 1024 else "n4k" if n <= 4096 else "n16k" if n <= 16384 else "ninf"
+    key = f"select.gl.{lb}.{nb}"
+    g = np.random.default_rng(l + n + k + 1)
+    Y = g.standard_normal((l, n)) * g.uniform(0.1, 10, n)[None, :]
+    ids.tune_set(key, 1)
+    try:
+        info = ids.select_plan_info(l, n, k)
+        print(f"4-wave variant: l={l} n={n} k={k} {info}", flush=True)
+        st = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+        J, P, keff = ids.id_select(dev(Y), k, status=st)
+        torch.cuda.synchronize()
+    finally:
+        ids.tune_set(key, None)
+    Jo, Po, ko, _, nu = oracle.cpqr_id(Y, k, trace=True)
+    assert ids.check_status(st) == {ids.OK}
+    assert int(keff.item()) == ko == k
+    assert np.array_equal(J.cpu().numpy(), Jo)
+    assert np.linalg.norm(P.cpu().numpy() - Po) <= 1e-10 * np.linalg.norm(Po)
+
+
+@pytest.mark.parametrize("key,value,l,n,k", [("trsm.k32", 2, 30, 700, 20), ("trsm.k32", 4, 30, 700, 20),
+                                             ("trsm.k64", 4, 60, 900, 50), ("trsm.k128", 8, 120, 1500, 100)])
+def test_solve_variants(key, value, l, n, k):
+    g = np.random.default_rng(k + value)
+    Y = g.standard_normal((l, n))
+    ids.tune_set(key, value)
+    try:
+        J, P, keff = ids.id_select(dev(Y), k)
+        torch.cuda.synchronize()
+    finally:
+        ids.tune_set(key, None)
+    Jo, Po, ko, _, _ = oracle.cpqr_id(Y, k)
+    assert np.array_equal(J.cpu().numpy(), Jo)
+    assert np.linalg.norm(P.cpu().numpy() - Po) <= 1e-10 * np.linalg.norm(Po)
+    assert np.array_equal(P.cpu().numpy()[:, Jo], np.eye(k))
+
+
+@pytest.mark.parametrize("rl512,rl256", [(0, 0), (36, 0), (0, 36)])
+def test_batched_row_placement_variants(rl512, rl256):
+    # rows in LDS or in registers: the same reflections; the FP32 partial sums
+    # of the trailing norms are grouped differently (LDS rows in one run,
+    # register rows in chunks of 8), so P agrees to the FP32 data's rounding
+    m = np.array([300, 900, 500, 2000, 700])
+    n = np.array([200, 400, 100, 700, 300])
+    g = np.random.default_rng(4)
+    bits = np.concatenate([synth.bf16_bits(g.standard_normal((mi, ni))).reshape(-1) for mi, ni in zip(m, n)])
+    At = dev(bits.view(np.int16)).view(torch.bfloat16)
+    Gt = dev(synth.bf16_bits(synth.gaussian(60, 128, seed=2)).view(np.int16)).view(torch.bfloat16)
+    plan = ids.batched_plan(m, n, 50, 60, 128)
+    ref = ids.id_batched(plan, At, Gt, seed=3)
+    torch.cuda.synchronize()
+    Jr, Pr = ref["J"].cpu().numpy(), ref["P"].cpu().numpy()
+    ids.tune_set("batched.rl512", rl512)
+    ids.tune_set("batched.rl256", rl256)
+    try:
+        out = ids.id_batched(plan, At, Gt, seed=3)
+        torch.cuda.synchronize()
+    finally:
+        ids.tune_set("batched.rl512", None)
+        ids.tune_set("batched.rl256", None)
+    assert np.array_equal(out["J"].cpu().numpy(), Jr)
+    assert np.linalg.norm(out["P"].cpu().numpy() - Pr) <= 1e-5 * np.linalg.norm(Pr)
+
+
+def test_select_wide_shape_falls_back_to_four_waves():
+    # 60 x 40000: 8-wave workgroups cannot all be co-resident; the plan takes
+    # the 4-wave variant whatever the knob says, and the result is the oracle's
+    l, n, k = 60, 40000, 40
+    g = np.random.default_rng(40)
+    Y = g.standard_normal((l, n)) * g.uniform(0.1, 10, n)[None, :]
+    ids.tune_set("select.gl.l64.ninf", 0)
+    try:
+        info = ids.select_plan_info(l, n, k)
+        J, P, keff = ids.id_select(dev(Y), k)
+        torch.cuda.synchronize()
+    finally:
+        ids.tune_set("select.gl.l64.ninf", None)
+    assert info["workgroups"] == (n + 63) // 64   # 64 columns per 4-wave workgroup
+    Jo, Po, ko, _, _ = oracle.cpqr_id(Y, k)
+    assert np.array_equal(J.cpu().numpy(), Jo)
+    assert np.linalg.norm(P.cpu().numpy() - Po) <= 1e-10 * np.linalg.norm(Po)
