@@ -96,7 +96,12 @@ typedef struct {
     int32_t proj;           /* projection arithmetic: IDS_F64 (FP64 MFMA) or       */
                             /* IDS_F32 (FP32 MFMA); must equal acc                 */
     const void* G;          /* l x l1 row-major Gaussian, element type = proj;     */
-                            /* ignored when l == l1                                */
+                            /* ignored when l == l1; NULL: drawn on the device     */
+                            /* from the stream (seed, tag | 2^63): entry e uses    */
+                            /* outputs 2e, 2e+1 as uniforms u1 = ((z >> 11) + 1)   */
+                            /* 2^-53, u2 = (z >> 11) 2^-53 and the Box-Muller      */
+                            /* value sqrt(-2 ln u1) cos(2 pi u2), in FP64, rounded  */
+                            /* to proj (the workspace grows by l x l1 elements)    */
     const int64_t* fr_pi;   /* IDS_HASH_FULLRANK: permutation pi of [0, m)        */
     const int32_t* fr_x;    /* IDS_HASH_FULLRANK: x[q] in [0, l1) for q >= l1     */
     int32_t* status;        /* IDS_CHECK_FINITE: device int32 status word          */
@@ -220,7 +225,8 @@ void ids_set_wait_limit(int64_t polls);
  *            1.2.1 applied to the TensorSketch): l = 0 factors T M itself
  *            (Algorithm 3 as printed); k <= l <= Jlen factors G (T M), G an
  *            l x Jlen row-major FP64 device buffer (caller-owned, e.g. N(0,1)
- *            entries; NULL is an error when l > 0).
+ *            entries) or NULL: drawn on the device from the stream
+ *            (seed, 0 | 2^63) as ids_sketch_cfg.G describes.
  *   Y        optional output (may be NULL): the sketch T M, Jlen x R
  *            column-major (leading dimension Jlen), before any projection.
  *   J, P, k_eff, status  as in id_select; lambda_hat double[k] (entries >=
@@ -244,7 +250,9 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
  *   CountSketch of A_p to l1_p = min(m_p, l1max) rows, stream (seed, tag = p),
  *   FP32 accumulation; the sketch is split into BF16 hi + lo parts and
  *   projected by G[:, 0:l1_p] (G: l x l1max row-major BF16, shared by all
- *   problems) on the BF16 matrix cores with FP32 accumulation; column-pivoted
+ *   problems; NULL: drawn on the device from the stream (seed, 0 | 2^63) as
+ *   ids_sketch_cfg.G describes, FP64 rounded to FP32 then to BF16, in the
+ *   workspace) on the BF16 matrix cores with FP32 accumulation; column-pivoted
  *   QR of the l x n_p projection with FP32 data and FP64 norms recomputed
  *   every step; FP64 back-substitution for P_p.
  * Limits: 1 <= k <= l <= 122, l <= l1max <= 512, l <= m_p <= 4096,

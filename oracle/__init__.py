@@ -66,6 +66,7 @@ def lib():
         L.orc_cpqr_id.argtypes = [c_i64, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp]
         L.orc_tensorsketch.argtypes = [c_i32, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp]
         L.orc_lambda_hat.argtypes = [c_i64, c_i64, c_vp, c_vp, c_vp, c_vp]
+        L.orc_gaussian.argtypes = [c_u64, c_u64, c_i64, c_vp]
         _lib = L
     return _lib
 
@@ -106,6 +107,15 @@ def fullrank_buckets(pi: np.ndarray, x: np.ndarray, L: int) -> np.ndarray:
     out = np.empty(pi.shape[0], dtype=np.int32)
     lib().orc_fullrank_hash(c_i64(pi.shape[0]), c_i64(L), _p(pi), _p(x), _p(out))
     return out
+
+
+def gaussian(seed: int, tag: int, l: int, q: int) -> np.ndarray:
+    """l x q N(0, 1) matrix from the stream (seed, tag | 2^63) by the
+    Box-Muller transform of its uniforms (the generator a NULL G asks the
+    library to run on the device)."""
+    g = np.empty(l * q, dtype=np.float64)
+    lib().orc_gaussian(c_u64(seed), c_u64(tag), c_i64(l * q), _p(g))
+    return g.reshape(l, q)
 
 
 # --------------------------------------------------------------------------

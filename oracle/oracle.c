@@ -278,3 +278,20 @@ void orc_lambda_hat(int64_t k, int64_t n, const double* P, const int64_t* J,
         lhat[t] = lambda[J[t]] * s;
     }
 }
+
+/* Gaussian matrix entries drawn from the stream (seed, tag | 2^63): entry e
+ * (row-major) takes outputs 2e and 2e+1 of the stream as uniforms
+ * u1 = ((z >> 11) + 1) 2^-53 in (0, 1] and u2 = (z >> 11) 2^-53 in [0, 1),
+ * and the Box-Muller transform g = sqrt(-2 ln u1) cos(2 pi u2)
+ * (Box & Muller 1958) gives an N(0, 1) value. */
+void orc_gaussian(uint64_t seed, uint64_t tag, int64_t count, double* g) {
+    const uint64_t key = orc_stream_key(seed, tag | (1ULL << 63));
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t e = 0; e < count; ++e) {
+        const uint64_t z1 = orc_mix64(key + (uint64_t)(2 * e + 1) * 0x9e3779b97f4a7c15ULL);
+        const uint64_t z2 = orc_mix64(key + (uint64_t)(2 * e + 2) * 0x9e3779b97f4a7c15ULL);
+        const double u1 = (double)((z1 >> 11) + 1) * 0x1p-53;
+        const double u2 = (double)(z2 >> 11) * 0x1p-53;
+        g[e] = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+    }
+}

@@ -294,7 +294,7 @@ def id_sketch(A, l1: int, l: int | None = None, *, seed: int = 0, tag: int = 0, 
     cfg = IdsSketchCfg(l1, l, seed, tag, flags, acc, acc, c_vp(G.data_ptr()) if G is not None else None,
                        c_vp(pi.data_ptr()) if pi is not None else None, c_vp(x.data_ptr()) if x is not None else None,
                        _ptr(check_finite))
-    if G is not None and l < l1:
+    if G is not None and l < l1:   # G None: drawn on the device from the stream (seed, tag | 2^63)
         if _dt(G) != acc or tuple(G.shape) != (l, l1) or not G.is_contiguous():
             raise IdsError("G must be a contiguous l x l1 tensor of the accumulation dtype")
     nbytes = c_sz(0)
@@ -416,8 +416,8 @@ def tensor_id(factors, lam, k: int, Jlen: int, *, seed: int = 0, l: int = 0, G=N
     ld = (c_i64 * N)(*[f.stride(1) for f in factors])
     fptr = (c_vp * N)(*[f.data_ptr() for f in factors])
     dev = factors[0].device
-    if l:
-        if G is None or G.dtype != torch.float64 or tuple(G.shape) != (l, Jlen) or not G.is_contiguous():
+    if l and G is not None:   # G None: drawn on the device from the stream (seed, 0 | 2^63)
+        if G.dtype != torch.float64 or tuple(G.shape) != (l, Jlen) or not G.is_contiguous():
             raise IdsError("G must be a contiguous float64 l x Jlen tensor when l > 0")
     nbytes = c_sz(0)
     _check(lib().ids_tensor_workspace_size(N, ctypes.cast(dims, c_vp), R, k, Jlen, l, ctypes.byref(nbytes)),
@@ -430,7 +430,8 @@ def tensor_id(factors, lam, k: int, Jlen: int, *, seed: int = 0, l: int = 0, G=N
     keff = torch.empty(1, dtype=torch.int64, device=dev)
     st = _status(torch, dev)
     _check(lib().tensor_id(N, ctypes.cast(dims, c_vp), R, ctypes.cast(fptr, c_vp), ctypes.cast(ld, c_vp),
-                           c_vp(lam.data_ptr()), k, Jlen, l, c_vp(G.data_ptr()) if l else None, seed,
+                           c_vp(lam.data_ptr()), k, Jlen, l, c_vp(G.data_ptr()) if (l and G is not None) else None,
+                           seed,
                            c_vp(Y.data_ptr()) if Y is not None else None,
                            c_vp(J.data_ptr()), c_vp(P.data_ptr()), c_vp(lh.data_ptr()), c_vp(keff.data_ptr()),
                            _ptr(st), c_vp(ws[1]) if ws else None, wsb, _stream(torch, stream)), "tensor_id")
@@ -481,10 +482,10 @@ def id_batched(plan: BatchedPlan, A, G, seed: int = 0, tol: float = 0.0, stream=
     k_eff (nprob) and, if asked, Y (flat float32, Y_p column-major l x n_p).
     tol > 0: fixed accuracy, problem p stops once |r_tt| <= tol |r_11|."""
     torch = _torch()
-    if A.dtype != torch.bfloat16 or G.dtype != torch.bfloat16:
+    if A.dtype != torch.bfloat16 or (G is not None and G.dtype != torch.bfloat16):
         raise IdsError("A and G must be bfloat16")
-    if tuple(G.shape) != (plan.l, plan.l1max) or not G.is_contiguous():
-        raise IdsError("G must be a contiguous l x l1max tensor")
+    if G is not None and (tuple(G.shape) != (plan.l, plan.l1max) or not G.is_contiguous()):
+        raise IdsError("G must be a contiguous l x l1max tensor (or None: drawn on the device)")
     if A.numel() < int(plan.a_off[-1]):
         raise IdsError("A is smaller than the batch")
     dev = A.device
@@ -496,7 +497,7 @@ def id_batched(plan: BatchedPlan, A, G, seed: int = 0, tol: float = 0.0, stream=
     _check(lib().id_batched(plan.nprob, c_vp(plan.m.ctypes.data), c_vp(plan.n.ctypes.data),
                             c_vp(plan.buf.data_ptr()), plan.k, plan.l, plan.l1max, seed, float(tol),
                             c_vp(A.data_ptr()),
-                            c_vp(G.data_ptr()), c_vp(J.data_ptr()), c_vp(P.data_ptr()), c_vp(keff.data_ptr()),
+                            _ptr(G), c_vp(J.data_ptr()), c_vp(P.data_ptr()), c_vp(keff.data_ptr()),
                             _ptr(st), c_vp(ws[1]), wsb, _stream(torch, stream)), "id_batched")
     out = dict(J=J, P=P, k_eff=keff, status=st)
     if return_Y:
@@ -525,7 +526,7 @@ class BatchedGraph:
         h = c_vp()
         _check(lib().ids_batched_graph_create(plan.nprob, c_vp(plan.m.ctypes.data), c_vp(plan.n.ctypes.data),
                                               c_vp(plan.buf.data_ptr()), plan.k, plan.l, plan.l1max, seed,
-                                              float(tol), c_vp(A.data_ptr()), c_vp(G.data_ptr()),
+                                              float(tol), c_vp(A.data_ptr()), _ptr(G),
                                               c_vp(self.J.data_ptr()), c_vp(self.P.data_ptr()),
                                               c_vp(self.k_eff.data_ptr()), _ptr(self.status), c_vp(self.ws[1]),
                                               self.wsb, ctypes.byref(h)), "ids_batched_graph_create")
@@ -550,6 +551,6 @@ class BatchedGraph:
 
 def batched_graph(plan: BatchedPlan, A, G, seed: int = 0, tol: float = 0.0) -> BatchedGraph:
     """Record the batched ID of `plan` on A, G into a HIP graph (see BatchedGraph)."""
-    if A.dtype.itemsize != 2 or G.dtype.itemsize != 2:
+    if A.dtype.itemsize != 2 or (G is not None and G.dtype.itemsize != 2):
         raise IdsError("A and G must be bfloat16")
     return BatchedGraph(plan, A, G, seed, tol)

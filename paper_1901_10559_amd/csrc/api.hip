@@ -56,6 +56,7 @@ static bool tune_valid(const std::string& key, int64_t v) {
     if (key == "trsm.k128") return v == 4 || v == 8;
     if (key == "batched.rl512" || key == "batched.rl256") return v == 0 || v == 36;
     if (key == "project.wgs") return v >= 32 && v <= 4096;
+    if (key == "cs.dense.wpc") return v == 0 || (v >= 2 && v <= 8);
     return false;
 }
 static std::mutex g_tune_mu;
@@ -162,10 +163,7 @@ static ids_status validate_sketch(const ids_matrix* A, const ids_sketch_cfg* c) 
     if (c->acc != IDS_F64 && c->acc != IDS_F32) return fail(IDS_EDTYPE, "acc must be IDS_F64 or IDS_F32");
     if (A->dtype == IDS_F64 && c->acc != IDS_F64) return fail(IDS_EDTYPE, "FP64 input needs FP64 accumulation");
     if (A->fmt == IDS_CSR && c->acc != IDS_F64) return fail(IDS_EDTYPE, "CSR input needs FP64 accumulation");
-    if (c->l < c->l1) {
-        if (c->proj != c->acc) return fail(IDS_EDTYPE, "proj must equal acc");
-        if (!c->G) return fail(IDS_EINVAL, "G is required when l < l1");
-    }
+    if (c->l < c->l1 && c->proj != c->acc) return fail(IDS_EDTYPE, "proj must equal acc");
     if (c->flags & ~(IDS_HASH_FULLRANK | IDS_CHECK_FINITE)) return fail(IDS_EINVAL, "unknown flag bits");
     if ((c->flags & IDS_CHECK_FINITE) && !c->status) return fail(IDS_EINVAL, "IDS_CHECK_FINITE needs status");
     if ((c->flags & IDS_HASH_FULLRANK) && (!c->fr_pi || !c->fr_x))
@@ -176,7 +174,7 @@ static ids_status validate_sketch(const ids_matrix* A, const ids_sketch_cfg* c) 
 
 struct SketchLayout {
     PlanShape ps;
-    size_t plan, y1, bop, part, total;
+    size_t plan, y1, bop, part, gdraw, total;
     int splits;  // projection K split (1: one pass)
 };
 
@@ -190,7 +188,9 @@ static SketchLayout sketch_layout(const ids_matrix* A, const ids_sketch_cfg* c) 
     // that about 256 workgroups share it; the partial products need l x n each
     L.splits = (c->l < c->l1) ? project_splits(c->l, c->l1, A->n, tune_get("project.wgs", 256)) : 1;
     L.part = (L.splits > 1) ? align256(esize(c->acc) * (size_t)L.splits * c->l * A->n) : 0;
-    L.total = L.plan + L.y1 + L.bop + L.part;
+    // G drawn on the device when the caller passes none
+    L.gdraw = (c->l < c->l1 && !c->G) ? align256(esize(c->acc) * (size_t)c->l * c->l1) : 0;
+    L.total = L.plan + L.y1 + L.bop + L.part + L.gdraw;
     return L;
 }
 
@@ -320,6 +320,8 @@ ids_status id_sketch(const ids_matrix* A, const ids_sketch_cfg* c, void* Y, int3
     int32_t* bop = (int32_t*)p;
     p += L.bop;
     void* part = p;
+    p += L.part;
+    void* gdraw = p;
 
     const bool proj = c->l < c->l1;
     const uint64_t key = stream_key(c->seed, c->tag);
@@ -345,7 +347,12 @@ ids_status id_sketch(const ids_matrix* A, const ids_sketch_cfg* c, void* Y, int3
     if (s) return s;
     if (proj) {
         ProfScope ps(PK_PROJ, st);
-        s = project_split(c->acc, c->l, c->l1, A->n, c->G, Y1, A->n, false, Y, ldy, L.splits, part, st);
+        const void* G = c->G;
+        if (!G) {
+            s = gaussian_fill(c->seed, c->tag, c->l, c->l1, c->acc, gdraw, st);
+            G = gdraw;
+        }
+        if (!s) s = project_split(c->acc, c->l, c->l1, A->n, G, Y1, A->n, false, Y, ldy, L.splits, part, st);
     }
     if (!s && (c->flags & IDS_CHECK_FINITE)) s = check_finite(c->acc, Y, c->l, A->n, ldy, c->status, st);
     return s;
@@ -532,7 +539,7 @@ ids_status id_select_noalloc(const void* Y, int32_t ydt, int64_t l, int64_t n, i
 // ---------------------------------------------------------------------------
 struct TensorLayout {
     PlanShape ps[8];
-    size_t plans, tw, y, yp, part, sel, total;
+    size_t plans, tw, y, yp, part, gdraw, sel, total;
     int splits;
     SelectPlan sp;
 };
@@ -561,10 +568,11 @@ static ids_status tensor_layout(int32_t N, const int64_t* dims, int64_t R, int64
     T.yp = l ? align256(sizeof(double) * (size_t)l * R) : 0;
     T.splits = l ? project_splits(l, Jlen, R, 512) : 1;
     T.part = T.splits > 1 ? align256(sizeof(double) * (size_t)T.splits * l * R) : 0;
+    T.gdraw = l ? align256(sizeof(double) * (size_t)l * Jlen) : 0;  // used when G is NULL
     ids_status s = select_plan(l ? l : Jlen, R, k, T.sp);
     if (s) return s;
     T.sel = select_bytes(T.sp);
-    T.total = T.plans + T.tw + T.y + T.yp + T.part + T.sel;
+    T.total = T.plans + T.tw + T.y + T.yp + T.part + T.gdraw + T.sel;
     return IDS_OK;
 }
 
@@ -587,7 +595,6 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
     g_err.clear();
     ids_status s = validate_tensor(N, dims, R, k, Jlen, l);
     if (s) return s;
-    if (l && !G) return fail(IDS_EINVAL, "G must be non-NULL when l > 0");
     if (!factors || !ld || !lambda || !J || !P || !lambda_hat || !k_eff)
         return fail(IDS_EINVAL, "factors, ld, lambda, J, P, lambda_hat and k_eff must be non-NULL");
     for (int n = 0; n < N; ++n) {
@@ -610,6 +617,8 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
     p += T.yp;
     double* part = (double*)p;
     p += T.part;
+    double* gdraw = (double*)p;
+    p += T.gdraw;
     char* sel = p;
     double* Yout = Y ? Y : Yw;
     uint64_t keys[8];
@@ -626,6 +635,10 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
     if (l) {
         // Gaussian second stage: Yp (l x R, column-major) = G (l x Jlen) T M
         ProfScope ps(PK_PROJ, st);
+        if (!G) {
+            if ((s = gaussian_fill(seed, 0, l, Jlen, IDS_F64, gdraw, st))) return s;
+            G = gdraw;
+        }
         if ((s = project_split(IDS_F64, l, Jlen, R, G, Yout, Jlen, true, Yp, l, T.splits, part, st))) return s;
     }
     if ((s = select_run(T.sp, l ? Yp : Yout, IDS_F64, 1, l ? l : Jlen, J, P, k_eff, status, sel, st))) return s;
@@ -675,7 +688,7 @@ static ids_status batched_args(int64_t nprob, const int64_t* m, const int64_t* n
     ids_status s = validate_batched(nprob, m, n, k, l, l1max);
     if (s) return s;
     if (!(tol >= 0.0 && tol < 1.0)) return fail(IDS_EINVAL, "tol must be in [0, 1)");
-    if (!plan || !A || !G || !J || !P || !k_eff) return fail(IDS_EINVAL, "plan, A, G, J, P and k_eff required");
+    if (!plan || !A || !J || !P || !k_eff) return fail(IDS_EINVAL, "plan, A, J, P and k_eff required");
     *a_elems = *y_elems = *r_elems = 0;
     for (int64_t q = 0; q < nprob; ++q) {
         *a_elems += m[q] * n[q];
@@ -684,7 +697,8 @@ static ids_status batched_args(int64_t nprob, const int64_t* m, const int64_t* n
     }
     const size_t need = align256(sizeof(float) * (size_t)*y_elems) +
                         align256(sizeof(double) * (size_t)*r_elems * k) +
-                        align256(sizeof(int32_t) * (size_t)*r_elems) + align256(sizeof(double) * (size_t)nprob * k);
+                        align256(sizeof(int32_t) * (size_t)*r_elems) + align256(sizeof(double) * (size_t)nprob * k) +
+                        align256(sizeof(uint16_t) * (size_t)l * l1max);
     return check_ws(ws, ws_bytes, need);
 }
 

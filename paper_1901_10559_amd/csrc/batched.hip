@@ -889,7 +889,8 @@ ids_status batched_plan(int64_t nprob, const int64_t* m, const int64_t* n, int64
     }
     // workspace: Y (FP32), Rt (FP64 n x k per problem), pos (int32), beta (FP64)
     *ws_bytes = align256(sizeof(float) * (size_t)y_off) + align256(sizeof(double) * (size_t)r_off * k) +
-                align256(sizeof(int32_t) * (size_t)r_off) + align256(sizeof(double) * (size_t)nprob * k);
+                align256(sizeof(int32_t) * (size_t)r_off) + align256(sizeof(double) * (size_t)nprob * k) +
+                align256(sizeof(uint16_t) * (size_t)l * l1max);  // G drawn on the device when none is given
     return IDS_OK;
 }
 
@@ -976,11 +977,20 @@ ids_status batched_run(int64_t nprob, const void* plan, int64_t k, int64_t l, in
     a.pos = (int32_t*)p;
     p += align256(sizeof(int32_t) * (size_t)r_elems);
     a.beta = (double*)p;
+    p += align256(sizeof(double) * (size_t)nprob * k);
+    uint16_t* gdraw = (uint16_t*)p;
     a.J = J;
     a.P = P;
     a.keff = keff;
     a.status = status;
     (void)ws_bytes;
+    if (!G) {
+        // the shared l x l1max Gaussian from the stream (seed, 0 | 2^63), BF16
+        ids_status s = gaussian_fill(seed, 0, l, l1max, IDS_BF16, gdraw, st);
+        if (s) return s;
+        a.G = gdraw;
+        a.g_vec = (l1max % 8 == 0);
+    }
     {
         ProfScope ps(prof ? PK_CS : -1, st);
         a.order = (const int32_t*)((const char*)plan + o1);

@@ -16,8 +16,10 @@
 //   3. CSR: workgroup (bucket, row chunk) scatters the stored entries of its
 //      rows into an LDS copy of the bucket's Y1 row (FP64 LDS atomics), then
 //      adds it to Y1 in HBM.
+#include <algorithm>
 #include "common.hpp"
 #include "kernels.hpp"
+#include "tune.hpp"
 
 namespace ids {
 
@@ -514,13 +516,22 @@ __global__ __launch_bounds__(CS_THREADS) void cs_dense_kernel(const T* __restric
         if (e < nvalid) Y[(int64_t)b * rs + (c0 + e) * cs] = acc[e];
 }
 
+// Workgroups resident per CU (tuned knob "cs.dense.wpc", 0 = as many as fit):
+// a dynamic LDS reservation the kernel does not use caps residency, so fewer
+// buckets stream their rows at once (fewer DRAM pages contended).
+static size_t dense_lds_reserve() {
+    const int64_t wpc = tune_get("cs.dense.wpc", 0);
+    if (wpc <= 0) return 0;
+    return std::min<size_t>(lds_limit(), (size_t)(160 * 1024) / (size_t)wpc);
+}
+
 template <typename T, typename ACC, int VEC>
 static void launch_dense(const void* A, int64_t lda, int64_t n, const PlanBufs& pb, int64_t L, void* Y,
                          int64_t rs, int64_t cs, hipStream_t st) {
     int64_t nvec = (n + VEC - 1) / VEC;
     dim3 grid((unsigned)((nvec + CS_THREADS - 1) / CS_THREADS), (unsigned)L);
-    hipLaunchKernelGGL((cs_dense_kernel<T, ACC, VEC>), grid, dim3(CS_THREADS), 0, st, (const T*)A, lda, n,
-                       (const int32_t*)pb.off, (const int32_t*)pb.rows, (ACC*)Y, rs, cs);
+    hipLaunchKernelGGL((cs_dense_kernel<T, ACC, VEC>), grid, dim3(CS_THREADS), dense_lds_reserve(), st, (const T*)A,
+                       lda, n, (const int32_t*)pb.off, (const int32_t*)pb.rows, (ACC*)Y, rs, cs);
 }
 
 ids_status cs_dense(int32_t dtype, int32_t acc, const void* A, int64_t lda, int64_t n, const PlanBufs& pb,

@@ -102,6 +102,9 @@ ids_status batched_graph_create(int64_t nprob, const void* plan, int64_t k, int6
 ids_status batched_graph_launch(void* g, hipStream_t st);
 void batched_graph_destroy(void* g);
 
+// ---- l x q N(0, 1) matrix from the stream (seed, tag | 2^63), Box-Muller ----
+ids_status gaussian_fill(uint64_t seed, uint64_t tag, int64_t l, int64_t q, int32_t dtype, void* out, hipStream_t st);
+
 // ---- finiteness scan of a sketch (l x n column-major) -> status word ---------
 ids_status check_finite(int32_t dtype, const void* Y, int64_t l, int64_t n, int64_t ldy, int32_t* status,
                         hipStream_t st);

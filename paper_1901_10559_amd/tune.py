@@ -36,11 +36,12 @@ MARGIN = 0.03   # a knob leaves its hand-picked value only for a gain above this
 
 HAND_DEFAULTS = {f"select.gl.{lb}.{nb}": 0 for lb in L_BUCKETS for nb in N_BUCKETS}
 HAND_DEFAULTS.update({"trsm.k32": 1, "trsm.k64": 2, "trsm.k128": 4, "batched.rl512": 36, "batched.rl256": 36,
-                      "project.wgs": 256})
+                      "project.wgs": 256, "cs.dense.wpc": 0})
 
 CANDIDATES = {f"select.gl.{lb}.{nb}": [0, 1] for lb in L_BUCKETS for nb in N_BUCKETS}
 CANDIDATES.update({"trsm.k32": [1, 2, 4], "trsm.k64": [2, 4], "trsm.k128": [4, 8],
-                   "batched.rl512": [36, 0], "batched.rl256": [36, 0], "project.wgs": [128, 256, 512, 1024]})
+                   "batched.rl512": [36, 0], "batched.rl256": [36, 0], "project.wgs": [128, 256, 512, 1024],
+                   "cs.dense.wpc": [0, 2, 3, 4]})
 
 
 def _timed(torch, fn, reps: int) -> float:
@@ -136,6 +137,13 @@ def run(out_dir: str, reps: int = 20) -> dict:
                                    lambda: ids.id_sketch(A, 480, 120, seed=0, G=G, acc=ids.F32), reps, stage="project")
     print(f"project.wgs: {timings['project.wgs']}", flush=True)
     del A, G
+
+    # dense CountSketch residency: the 200000 x 2000 FP32 pass to l1 = 480
+    A = torch.randn(200000, 2000, dtype=torch.float32, device=dev)
+    timings["cs.dense.wpc"] = sweep(ids, torch, "cs.dense.wpc", lambda: ids.id_sketch(A, 480, seed=0, acc=ids.F32),
+                                    reps, stage="countsketch")
+    print(f"cs.dense.wpc: {timings['cs.dense.wpc']}", flush=True)
+    del A
 
     # batched factorisation: rows in LDS per width class, on the 4096-problem batch
     m, n, flat = synth.batched_inputs(4096, seed=0, workers=16)

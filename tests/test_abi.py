@@ -56,9 +56,12 @@ def test_sketch_rejects_bad_arguments_without_gpu():
     A = ids.IdsMatrix(ids.DENSE, ids.F64, 100, 20, 20, 0, ctypes.c_void_p(16), None, None)
     cfg = ids.IdsSketchCfg(30, 40, 0, 0, 0, ids.F64, ids.F64, None, None, None, None)   # l > l1
     assert L.ids_sketch_workspace_size(ctypes.byref(A), ctypes.byref(cfg), ctypes.byref(nb)) == 1
-    cfg = ids.IdsSketchCfg(30, 10, 0, 0, 0, ids.F64, ids.F64, None, None, None, None)   # l < l1 without G
-    assert L.ids_sketch_workspace_size(ctypes.byref(A), ctypes.byref(cfg), ctypes.byref(nb)) == 1
-    assert b"G is required" in L.ids_last_error()
+    cfg = ids.IdsSketchCfg(30, 10, 0, 0, 0, ids.F64, ids.F64, None, None, None, None)   # l < l1, G drawn
+    assert L.ids_sketch_workspace_size(ctypes.byref(A), ctypes.byref(cfg), ctypes.byref(nb)) == 0
+    without_g = nb.value
+    cfg = ids.IdsSketchCfg(30, 10, 0, 0, 0, ids.F64, ids.F64, ctypes.c_void_p(256), None, None, None)
+    assert L.ids_sketch_workspace_size(ctypes.byref(A), ctypes.byref(cfg), ctypes.byref(nb)) == 0
+    assert without_g - nb.value == 8 * 10 * 30 + (-(8 * 10 * 30)) % 256   # room for the drawn l x l1 G
     cfg = ids.IdsSketchCfg(30, 30, 0, 0, 0, ids.F32, ids.F32, None, None, None, None)   # FP64 in, FP32 acc
     assert L.ids_sketch_workspace_size(ctypes.byref(A), ctypes.byref(cfg), ctypes.byref(nb)) == 2
     A2 = ids.IdsMatrix(ids.DENSE, ids.F64, 100, 20, 10, 0, ctypes.c_void_p(16), None, None)  # ld < n

@@ -131,7 +131,9 @@ def test_tensor_id_sparse5_parity(I, R, K, Jlen, l):
         assert eg <= 1.01 * eo + 1e-12
 
 
-def test_tensor_id_projection_rejects_missing_G():
+def test_tensor_id_projection_rejects_misshaped_G():
+    # (G = None is valid: the library draws it; see test_gpu_gauss.py)
     factors, lam, _ = synth.cp_tensor(dims=(20, 20, 20), R=30, nbase=5, seed=1)
+    G = torch.zeros((10, 32), dtype=torch.float64, device=DEV)
     with pytest.raises(ids.IdsError):
-        ids.tensor_id([dev_cols(f) for f in factors], torch.from_numpy(lam).to(DEV), 5, 64, l=10, G=None)
+        ids.tensor_id([dev_cols(f) for f in factors], torch.from_numpy(lam).to(DEV), 5, 64, l=10, G=G)

@@ -93,3 +93,21 @@ def test_gemm_matches_numpy():
     Gi = g.integers(-9, 9, size=(8, 30)).astype(np.float64)
     Bi = g.integers(-9, 9, size=(30, 11)).astype(np.float64)
     assert np.array_equal(oracle.gemm(Gi, Bi), Gi @ Bi)
+
+
+def test_gaussian_stream_draw():
+    # the oracle's G generator (Box-Muller on the stream's uniforms): N(0, 1)
+    # by moments and a Kolmogorov-Smirnov test, a new stream per (seed, tag),
+    # and entry e built from outputs 2e, 2e+1 of the stream (seed, tag | 2^63)
+    from scipy import stats
+    g = oracle.gaussian(11, 5, 400, 500).ravel()
+    assert abs(g.mean()) < 5 / np.sqrt(g.size)
+    assert abs(g.var() - 1) < 5 * np.sqrt(2 / g.size)
+    assert abs(np.mean(g ** 4) - 3) < 0.1
+    assert stats.kstest(g, "norm").pvalue > 1e-3
+    assert not np.array_equal(oracle.gaussian(11, 6, 4, 5), oracle.gaussian(11, 5, 4, 5))
+    z = oracle.stream(11, 5 | (1 << 63), 2 * 20)
+    u1 = ((z[0::2] >> np.uint64(11)) + np.uint64(1)).astype(np.float64) * 2.0 ** -53
+    u2 = (z[1::2] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    ref = np.sqrt(-2 * np.log(u1)) * np.cos(2 * np.pi * u2)
+    np.testing.assert_allclose(oracle.gaussian(11, 5, 4, 5).ravel(), ref, rtol=1e-14, atol=1e-15)
