@@ -242,6 +242,26 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
                      size_t ws_bytes, void* stream);
 
 /*
+ * tensor_id_csc -- tensor_id for factors with sparse columns (the paper's
+ * sparse CP tensors, whose TensorSketch costs O(N nnz) plus the FFTs).
+ * Factor n is I_n x R in compressed sparse column form (host arrays of N
+ * device pointers): column r's nonzeros are rowind[n][q], val[n][q] for
+ * q in [colptr[n][r], colptr[n][r + 1]), rows strictly ascending within a
+ * column and in [0, dims[n]); colptr int64[R + 1], rowind int32, val FP64.
+ * Each bucket of a mode's CountSketch takes its entries in ascending row
+ * order, as the dense path does, so the results equal tensor_id's on the
+ * same tensor stored densely.  Everything else as tensor_id; workspace:
+ * ids_tensor_csc_workspace_size (no bucket plans).
+ */
+ids_status ids_tensor_csc_workspace_size(int32_t N, const int64_t* dims, int64_t R, int64_t k,
+                                         int64_t Jlen, int64_t l, size_t* bytes);
+ids_status tensor_id_csc(int32_t N, const int64_t* dims, int64_t R, const int64_t* const* colptr,
+                         const int32_t* const* rowind, const double* const* val, const double* lambda,
+                         int64_t k, int64_t Jlen, int64_t l, const double* G, uint64_t seed, double* Y,
+                         int64_t* J, double* P, double* lambda_hat, int64_t* k_eff, int32_t* status,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Batched mixed-precision matrix ID (hierarchical-matrix style block
  * compression): nprob independent dense problems A_p (m_p x n_p, BF16,
  * row-major, stored back to back in A: A_p starts at element

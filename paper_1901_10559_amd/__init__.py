@@ -24,7 +24,7 @@ import os
 
 __all__ = ["lib", "lib_path", "BatchedPlan", "batched_plan", "id_batched", "BatchedGraph", "batched_graph", "profile_enable", "profile_stages",
            "profile_read", "profile_reset", "id_sketch", "id_project", "id_select", "id_select_noalloc",
-           "matrix_id", "tensor_id", "gaussian_sketch", "gaussian_id", "check_status", "set_wait_limit", "select_plan_info", "stream_read", "tune_set", "tune_get",
+           "matrix_id", "tensor_id", "tensor_id_csc", "gaussian_sketch", "gaussian_id", "check_status", "set_wait_limit", "select_plan_info", "stream_read", "tune_set", "tune_get",
            "finalize", "IdsError", "F64", "F32", "BF16", "HASH_FULLRANK", "CHECK_FINITE", "EXPORTED",
            "OK", "ETIMEOUT", "ERANKDEF", "ENONFINITE"]
 
@@ -40,7 +40,7 @@ OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ETIMEOUT, ERANKDEF, ENONFINITE = range(8)
 
 EXPORTED = ["ids_sketch_workspace_size", "id_sketch", "id_project", "ids_gaussian_workspace_size",
             "id_gaussian_sketch", "ids_select_workspace_size",
-            "id_select", "id_select_noalloc", "ids_set_wait_limit", "ids_select_plan_info", "ids_stream_read", "ids_tune_set", "ids_tune_get", "ids_tensor_workspace_size", "tensor_id",
+            "id_select", "id_select_noalloc", "ids_set_wait_limit", "ids_select_plan_info", "ids_stream_read", "ids_tune_set", "ids_tune_get", "ids_tensor_workspace_size", "tensor_id", "ids_tensor_csc_workspace_size", "tensor_id_csc",
             "ids_batched_plan_size", "ids_batched_plan", "id_batched", "ids_batched_graph_create",
             "ids_batched_graph_launch", "ids_batched_graph_destroy", "ids_profile_enable", "ids_profile_stages",
             "ids_profile_read", "ids_profile_reset", "ids_finalize", "ids_status_string", "ids_last_error"]
@@ -103,6 +103,11 @@ def lib():
         L.ids_tensor_workspace_size.argtypes = [c_i32, c_vp, c_i64, c_i64, c_i64, c_i64, P(c_sz)]
         L.tensor_id.argtypes = [c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_u64, c_vp, c_vp, c_vp,
                                 c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]
+        L.ids_tensor_csc_workspace_size.argtypes = [c_i32, c_vp, c_i64, c_i64, c_i64, c_i64, P(c_sz)]
+        L.ids_tensor_csc_workspace_size.restype = c_i32
+        L.tensor_id_csc.argtypes = [c_i32, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_u64,
+                                    c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_sz, c_vp]
+        L.tensor_id_csc.restype = c_i32
         L.ids_batched_plan_size.argtypes = [c_i64, P(c_sz)]
         L.ids_batched_plan.argtypes = [c_i64, c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_sz, P(c_sz), c_vp]
         L.id_batched.argtypes = [c_i64, c_vp, c_vp, c_vp, c_i64, c_i64, c_i64, c_u64, ctypes.c_double, c_vp, c_vp, c_vp,
@@ -437,6 +442,50 @@ def tensor_id(factors, lam, k: int, Jlen: int, *, seed: int = 0, l: int = 0, G=N
                            _ptr(st), c_vp(ws[1]) if ws else None, wsb, _stream(torch, stream)), "tensor_id")
     if check:
         check_status(st, "tensor_id")
+    out = dict(J=J, P=P, lambda_hat=lh, k_eff=keff, status=st)
+    if Y is not None:
+        out["Y"] = Y.t()
+    return out
+
+
+def tensor_id_csc(factors, lam, k: int, Jlen: int, *, seed: int = 0, l: int = 0, G=None, return_Y: bool = False,
+                  stream=None, check: bool = False):
+    """Algorithm 3 for factors with sparse columns.  factors: list of
+    (colptr int64[R+1], rowind int32, val float64, I_n) device tensors, the
+    compressed sparse columns of each I_n x R factor (rows ascending within a
+    column).  Otherwise as tensor_id."""
+    torch = _torch()
+    N = len(factors)
+    R = factors[0][0].numel() - 1
+    for cp, ri, v, _ in factors:
+        if cp.dtype != torch.int64 or ri.dtype != torch.int32 or v.dtype != torch.float64 or cp.numel() != R + 1:
+            raise IdsError("CSC factors need int64 colptr[R+1], int32 rowind and float64 val")
+    dims = (c_i64 * N)(*[int(f[3]) for f in factors])
+    cps = (c_vp * N)(*[f[0].data_ptr() for f in factors])
+    ris = (c_vp * N)(*[f[1].data_ptr() for f in factors])
+    vs = (c_vp * N)(*[f[2].data_ptr() for f in factors])
+    dev = factors[0][2].device
+    if l and G is not None:
+        if G.dtype != torch.float64 or tuple(G.shape) != (l, Jlen) or not G.is_contiguous():
+            raise IdsError("G must be a contiguous float64 l x Jlen tensor when l > 0")
+    nbytes = c_sz(0)
+    _check(lib().ids_tensor_csc_workspace_size(N, ctypes.cast(dims, c_vp), R, k, Jlen, l, ctypes.byref(nbytes)),
+           "ids_tensor_csc_workspace_size")
+    ws, wsb = _workspace(torch, nbytes.value, dev, stream)
+    Y = torch.empty((R, Jlen), dtype=torch.float64, device=dev) if return_Y else None
+    J = torch.empty(k, dtype=torch.int64, device=dev)
+    P = torch.empty((k, R), dtype=torch.float64, device=dev)
+    lh = torch.empty(k, dtype=torch.float64, device=dev)
+    keff = torch.empty(1, dtype=torch.int64, device=dev)
+    st = _status(torch, dev)
+    _check(lib().tensor_id_csc(N, ctypes.cast(dims, c_vp), R, ctypes.cast(cps, c_vp), ctypes.cast(ris, c_vp),
+                               ctypes.cast(vs, c_vp), c_vp(lam.data_ptr()), k, Jlen, l,
+                               c_vp(G.data_ptr()) if (l and G is not None) else None, seed,
+                               c_vp(Y.data_ptr()) if Y is not None else None, c_vp(J.data_ptr()),
+                               c_vp(P.data_ptr()), c_vp(lh.data_ptr()), c_vp(keff.data_ptr()), _ptr(st),
+                               c_vp(ws[1]) if ws else None, wsb, _stream(torch, stream)), "tensor_id_csc")
+    if check:
+        check_status(st, "tensor_id_csc")
     out = dict(J=J, P=P, lambda_hat=lh, k_eff=keff, status=st)
     if Y is not None:
         out["Y"] = Y.t()

@@ -557,9 +557,9 @@ static ids_status validate_tensor(int32_t N, const int64_t* dims, int64_t R, int
 }
 
 static ids_status tensor_layout(int32_t N, const int64_t* dims, int64_t R, int64_t k, int64_t Jlen, int64_t l,
-                                TensorLayout& T) {
+                                TensorLayout& T, bool csc = false) {
     T.plans = 0;
-    for (int n = 0; n < N; ++n) {
+    for (int n = 0; n < N && !csc; ++n) {   // CSC factors need no bucket plans
         T.ps[n] = plan_shape(dims[n], Jlen);
         T.plans += plan_bytes(T.ps[n]);
     }
@@ -588,27 +588,32 @@ ids_status ids_tensor_workspace_size(int32_t N, const int64_t* dims, int64_t R, 
     return IDS_OK;
 }
 
-ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* const* factors, const int64_t* ld,
-                     const double* lambda, int64_t k, int64_t Jlen, int64_t l, const double* G, uint64_t seed,
-                     double* Y, int64_t* J, double* P, double* lambda_hat, int64_t* k_eff, int32_t* status,
-                     void* ws, size_t ws_bytes, void* stream) {
-    g_err.clear();
+static ids_status tensor_run(int32_t N, const int64_t* dims, int64_t R, const double* const* factors,
+                             const int64_t* ld, const int64_t* const* colptr, const int32_t* const* rowind,
+                             const double* const* val, const double* lambda, int64_t k, int64_t Jlen, int64_t l,
+                             const double* G, uint64_t seed, double* Y, int64_t* J, double* P, double* lambda_hat,
+                             int64_t* k_eff, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    const bool csc = colptr != nullptr;
     ids_status s = validate_tensor(N, dims, R, k, Jlen, l);
     if (s) return s;
-    if (!factors || !ld || !lambda || !J || !P || !lambda_hat || !k_eff)
-        return fail(IDS_EINVAL, "factors, ld, lambda, J, P, lambda_hat and k_eff must be non-NULL");
+    if (!lambda || !J || !P || !lambda_hat || !k_eff)
+        return fail(IDS_EINVAL, "lambda, J, P, lambda_hat and k_eff must be non-NULL");
     for (int n = 0; n < N; ++n) {
-        if (!factors[n]) return fail(IDS_EINVAL, "factors[n] is NULL");
-        if (ld[n] < dims[n]) return fail(IDS_EINVAL, "ld[n] < dims[n]");
+        if (csc) {
+            if (!colptr[n] || !rowind[n] || !val[n]) return fail(IDS_EINVAL, "colptr, rowind and val[n] required");
+        } else {
+            if (!factors[n]) return fail(IDS_EINVAL, "factors[n] is NULL");
+            if (ld[n] < dims[n]) return fail(IDS_EINVAL, "ld[n] < dims[n]");
+        }
     }
     if (ts_lds_bytes(Jlen) > lds_limit()) return fail(IDS_EINVAL, "Jlen too large for the LDS FFT on this device");
     TensorLayout T;
-    if ((s = tensor_layout(N, dims, R, k, Jlen, l, T))) return s;
+    if ((s = tensor_layout(N, dims, R, k, Jlen, l, T, csc))) return s;
     if ((s = check_ws(ws, ws_bytes, T.total))) return s;
     hipStream_t st = (hipStream_t)stream;
     char* p = (char*)ws;
     PlanBufs pb[8];
-    for (int n = 0; n < N; ++n) pb[n] = plan_carve(T.ps[n], p);
+    for (int n = 0; n < N && !csc; ++n) pb[n] = plan_carve(T.ps[n], p);
     double2* tw = (double2*)p;
     p += T.tw;
     double* Yw = (double*)p;
@@ -625,12 +630,13 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
     for (int n = 0; n < N; ++n) keys[n] = stream_key(seed, (uint64_t)n + 1);
     {
         ProfScope ps(PK_PLAN, st);
-        if ((s = plan_build_many(N, T.ps, keys, pb, st))) return s;
+        if (!csc && (s = plan_build_many(N, T.ps, keys, pb, st))) return s;
         if ((s = twiddles(Jlen, tw, st))) return s;
     }
     {
         ProfScope ps(PK_TS, st);
-        if ((s = tensorsketch(N, dims, R, factors, ld, lambda, Jlen, pb, keys, tw, Yout, st))) return s;
+        if ((s = tensorsketch(N, dims, R, factors, ld, lambda, Jlen, pb, keys, tw, Yout, st, colptr, rowind, val)))
+            return s;
     }
     if (l) {
         // Gaussian second stage: Yp (l x R, column-major) = G (l x Jlen) T M
@@ -644,6 +650,39 @@ ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* co
     if ((s = select_run(T.sp, l ? Yp : Yout, IDS_F64, 1, l ? l : Jlen, J, P, k_eff, status, sel, st))) return s;
     ProfScope ps(PK_LHAT, st);
     return ids::lambda_hat(k, R, P, J, k_eff, lambda, lambda_hat, st);
+}
+
+ids_status tensor_id(int32_t N, const int64_t* dims, int64_t R, const double* const* factors, const int64_t* ld,
+                     const double* lambda, int64_t k, int64_t Jlen, int64_t l, const double* G, uint64_t seed,
+                     double* Y, int64_t* J, double* P, double* lambda_hat, int64_t* k_eff, int32_t* status,
+                     void* ws, size_t ws_bytes, void* stream) {
+    g_err.clear();
+    if (!factors || !ld) return fail(IDS_EINVAL, "factors and ld must be non-NULL");
+    return tensor_run(N, dims, R, factors, ld, nullptr, nullptr, nullptr, lambda, k, Jlen, l, G, seed, Y, J, P,
+                      lambda_hat, k_eff, status, ws, ws_bytes, stream);
+}
+
+ids_status ids_tensor_csc_workspace_size(int32_t N, const int64_t* dims, int64_t R, int64_t k, int64_t Jlen,
+                                         int64_t l, size_t* bytes) {
+    g_err.clear();
+    if (!bytes) return fail(IDS_EINVAL, "bytes is NULL");
+    ids_status s = validate_tensor(N, dims, R, k, Jlen, l);
+    if (s) return s;
+    TensorLayout T;
+    if ((s = tensor_layout(N, dims, R, k, Jlen, l, T, true))) return s;
+    *bytes = T.total;
+    return IDS_OK;
+}
+
+ids_status tensor_id_csc(int32_t N, const int64_t* dims, int64_t R, const int64_t* const* colptr,
+                         const int32_t* const* rowind, const double* const* val, const double* lambda, int64_t k,
+                         int64_t Jlen, int64_t l, const double* G, uint64_t seed, double* Y, int64_t* J, double* P,
+                         double* lambda_hat, int64_t* k_eff, int32_t* status, void* ws, size_t ws_bytes,
+                         void* stream) {
+    g_err.clear();
+    if (!colptr || !rowind || !val) return fail(IDS_EINVAL, "colptr, rowind and val must be non-NULL");
+    return tensor_run(N, dims, R, nullptr, nullptr, colptr, rowind, val, lambda, k, Jlen, l, G, seed, Y, J, P,
+                      lambda_hat, k_eff, status, ws, ws_bytes, stream);
 }
 
 // ---------------------------------------------------------------------------

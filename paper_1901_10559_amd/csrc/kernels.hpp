@@ -112,9 +112,12 @@ ids_status check_finite(int32_t dtype, const void* Y, int64_t l, int64_t n, int6
 ids_status stream_read(const void* p, size_t bytes, uint32_t* sum, hipStream_t st);
 
 // ---- TensorSketch -------------------------------------------------------------
+// colptr / rowind / val (non-NULL): CSC factors instead of dense ones
 ids_status tensorsketch(int32_t N, const int64_t* dims, int64_t R, const double* const* factors,
                         const int64_t* ld, const double* lambda, int64_t Jlen, const PlanBufs* plans,
-                        const uint64_t* keys, const double2* twiddle, double* Y, hipStream_t st);
+                        const uint64_t* keys, const double2* twiddle, double* Y, hipStream_t st,
+                        const int64_t* const* colptr = nullptr, const int32_t* const* rowind = nullptr,
+                        const double* const* val = nullptr);
 ids_status twiddles(int64_t Jlen, double2* tw, hipStream_t st);
 size_t ts_lds_bytes(int64_t J);
 

@@ -23,7 +23,8 @@
 // recomputes each row's bucket from the hash, and adds the entries into a
 // running bucket sum that it writes out when the bucket changes.  Every bucket
 // is summed by one thread, from 0, in ascending row order: the result does not
-// depend on scheduling.
+// depend on scheduling.  CSC factors (sparse columns) take the per-column
+// path below instead: the nonzeros only, no plan.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -138,7 +139,56 @@ struct TsArgs {
     const double2* tw;
     double* Y;  // J x R column-major
     uint64_t key[8];  // hash key of each mode's plan
+    // CSC factors (colptr == nullptr: dense): column r's nonzeros are
+    // rowind / val [colptr[r], colptr[r + 1]), rows ascending
+    const int64_t* colptr[8];
+    const int32_t* rowind[8];
+    const double* val[8];
 };
+
+// Mode CountSketch of one CSC column into component `comp` (0: re, 1: im) of
+// the packed LDS buffer, by one wave: the column's nonzeros in batches of 64
+// (lane q holds entry p0 + q, rows ascending), each entry's bucket and sign
+// from the hash.  Entries of a batch that share a bucket are ranked by lane
+// (peer mask from one ballot per bucket bit, rank = peers below), and rank 0,
+// 1, ... add in turn, so every bucket takes its entries in ascending row
+// order -- the order of the dense path and of the textbook sum.
+__device__ __forceinline__ void cs_sparse_column(double* bufd, int comp, int J, uint64_t key, const int64_t* colptr,
+                                                 const int32_t* rowind, const double* val, int64_t r) {
+    const int lane = threadIdx.x & 63;
+    const int64_t q0 = colptr[r], q1 = colptr[r + 1];
+    const int nbits = 32 - __clz(J - 1);  // J is a power of two
+    for (int64_t p0 = q0; p0 < q1; p0 += 64) {
+        const int64_t p = p0 + lane;
+        const bool live = p < q1;
+        uint32_t b = 0;
+        double v = 0.0;
+        if (live) {
+            const int64_t i = rowind[p];
+            bool ng;
+            hash_row(key, i, (uint32_t)J, b, ng);
+            v = ng ? -val[p] : val[p];
+        }
+        // lanes holding the same bucket: AND over the bucket bits
+        uint64_t peers = __ballot(live);
+        for (int t = 0; t < nbits; ++t) {
+            const uint64_t m = __ballot(live && ((b >> t) & 1u));
+            peers &= ((b >> t) & 1u) ? m : ~m;
+        }
+        const int rank = __popcll(peers & ((1ull << lane) - 1ull));
+        int maxrank = live ? rank : 0;
+        for (int o = 32; o > 0; o >>= 1) maxrank = max(maxrank, __shfl_xor(maxrank, o, 64));
+        for (int k = 0; k <= maxrank; ++k) {
+            if (live && rank == k) {
+                double* d = bufd + 2 * padi((int)b) + comp;
+                *d = *d + v;
+            }
+            // the wave's LDS operations complete in program order, so the next
+            // round reads what this one wrote
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
 
 constexpr int TS_CB = 8;  // plan positions loaded together
 
@@ -161,7 +211,15 @@ __global__ __launch_bounds__(256) void tensorsketch_kernel(TsArgs a) {
         const int32_t* off = a.off[md];
         const int32_t* rows = a.rows[md];
         // mode-n CountSketch of columns r0, r0+1 packed as re + i im
-        {
+        if (a.colptr[md]) {
+            // CSC factor: zero the buffer, then waves 0 and 1 add the nonzeros
+            // of columns r0 and r0 + 1 into the real and imaginary parts
+            for (int b = tid; b < J; b += 256) buf[padi(b)] = make_double2(0.0, 0.0);
+            __syncthreads();
+            const int w = tid >> 6;
+            if (w == 0 || (w == 1 && two))
+                cs_sparse_column((double*)buf, w, J, a.key[md], a.colptr[md], a.rowind[md], a.val[md], r0 + w);
+        } else {
             const int bA = (int)(((int64_t)tid * J) >> 8), bB = (int)(((int64_t)(tid + 1) * J) >> 8);
             const int pA = off[bA], pB = off[bB];
             const uint64_t key = a.key[md];
@@ -270,18 +328,23 @@ size_t ts_lds_bytes(int64_t J) { return sizeof(double2) * (size_t)(J + J / 16); 
 
 ids_status tensorsketch(int32_t N, const int64_t* dims, int64_t R, const double* const* factors, const int64_t* ld,
                         const double* lambda, int64_t Jlen, const PlanBufs* plans, const uint64_t* keys,
-                        const double2* tw, double* Y, hipStream_t st) {
+                        const double2* tw, double* Y, hipStream_t st, const int64_t* const* colptr,
+                        const int32_t* const* rowind, const double* const* val) {
     (void)dims;
     TsArgs a;
     a.N = N;
     a.R = R;
     a.J = (int32_t)Jlen;
     for (int n = 0; n < N; ++n) {
-        a.fac[n] = factors[n];
-        a.ld[n] = ld[n];
-        a.off[n] = plans[n].off;
-        a.rows[n] = plans[n].rows;
+        const bool csc = colptr != nullptr;
+        a.fac[n] = csc ? nullptr : factors[n];
+        a.ld[n] = csc ? 0 : ld[n];
+        a.off[n] = csc ? nullptr : plans[n].off;
+        a.rows[n] = csc ? nullptr : plans[n].rows;
         a.key[n] = keys[n];
+        a.colptr[n] = csc ? colptr[n] : nullptr;
+        a.rowind[n] = csc ? rowind[n] : nullptr;
+        a.val[n] = csc ? val[n] : nullptr;
     }
     a.lambda = lambda;
     a.tw = tw;

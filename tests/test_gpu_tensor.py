@@ -137,3 +137,58 @@ def test_tensor_id_projection_rejects_misshaped_G():
     G = torch.zeros((10, 32), dtype=torch.float64, device=DEV)
     with pytest.raises(ids.IdsError):
         ids.tensor_id([dev_cols(f) for f in factors], torch.from_numpy(lam).to(DEV), 5, 64, l=10, G=G)
+
+
+def csc_dev(F):
+    import scipy.sparse as sp
+    c = sp.csc_matrix(np.asarray(F))
+    c.sort_indices()
+    return (torch.from_numpy(c.indptr.astype(np.int64)).to(DEV), torch.from_numpy(c.indices.astype(np.int32)).to(DEV),
+            torch.from_numpy(c.data.astype(np.float64)).to(DEV), F.shape[0])
+
+
+# CSC factors: the per-mode CountSketch over the nonzeros only
+@pytest.mark.parametrize("N,I,R,K,density,Jlen,l", [(5, 1000, 500, 50, 0.01, 512, 60), (5, 400, 120, 12, 0.01, 256, 0),
+                                                    (3, 300, 64, 8, 0.3, 1024, 0), (4, 2000, 33, 5, 0.05, 64, 0)])
+def test_tensor_id_csc_parity(N, I, R, K, density, Jlen, l):
+    factors, lam = synth.cp_sparse(N=N, I=I, R=R, K=K, density=density, seed=I + R)
+    G = synth.gaussian(l, Jlen, seed=9) if l else None
+    Gd = torch.from_numpy(G).to(DEV) if l else None
+    r = ids.tensor_id_csc([csc_dev(f) for f in factors], torch.from_numpy(lam).to(DEV), K, Jlen, seed=5, l=l, G=Gd,
+                          return_Y=True, check=True)
+    # the same tensor stored densely through the dense path: the same sketch bits
+    rd = ids.tensor_id([dev_cols(f) for f in factors], torch.from_numpy(lam).to(DEV), K, Jlen, seed=5, l=l, G=Gd,
+                       return_Y=True)
+    assert np.array_equal(r["Y"].cpu().numpy(), rd["Y"].cpu().numpy())
+    o = oracle.tensor_id(factors, lam, k=K, Jlen=Jlen, seed=5, G=G, trace=True)
+    Yo = oracle.tensorsketch(factors, lam, oracle.tensor_maps(5, [I] * N, Jlen), Jlen)
+    scale = np.linalg.norm(Yo, axis=0, keepdims=True)
+    assert np.max(np.abs(r["Y"].cpu().numpy() - Yo) / scale) <= 1e-13
+    J = r["J"].cpu().numpy()
+    assert int(r["k_eff"].item()) == o["k_eff"] == K
+    assert tie_aware_J(J, o["J"], o["nu"])
+    if np.array_equal(J, o["J"]):
+        P = r["P"].cpu().numpy()
+        assert np.linalg.norm(P - o["P"]) <= 1e-10 * np.linalg.norm(o["P"])
+        lh = r["lambda_hat"].cpu().numpy()
+        assert np.max(np.abs(lh - o["lambda_hat"]) / np.abs(o["lambda_hat"])) <= 1e-10
+
+
+def test_tensor_id_csc_empty_and_long_columns():
+    # an empty column, a column with more than 64 nonzeros sharing buckets
+    # (J = 16 forces collisions inside every batch of 64)
+    g = np.random.default_rng(3)
+    dims, R, Jlen = (300, 200), 6, 16
+    factors = [g.standard_normal((d, R)) for d in dims]
+    factors[0][:, 2] = 0.0
+    lam = g.uniform(0.5, 2.0, R)
+    r = ids.tensor_id_csc([csc_dev(f) for f in factors], torch.from_numpy(lam).to(DEV), 2, Jlen, seed=4,
+                          return_Y=True)
+    Yo = oracle.tensorsketch(factors, lam, oracle.tensor_maps(4, dims, Jlen), Jlen)
+    # two columns share one complex FFT, so the empty column carries rounding
+    # at the level of its partner's norm
+    scale = np.linalg.norm(Yo, axis=0, keepdims=True)
+    scale = np.maximum(scale, np.repeat(np.maximum(scale[:, 0::2], scale[:, 1::2]), 2, axis=1)[:, :scale.shape[1]])
+    assert np.max(np.abs(r["Y"].cpu().numpy() - Yo) / scale) <= 1e-13
+    rd = ids.tensor_id([dev_cols(f) for f in factors], torch.from_numpy(lam).to(DEV), 2, Jlen, seed=4, return_Y=True)
+    assert np.array_equal(r["Y"].cpu().numpy(), rd["Y"].cpu().numpy())
