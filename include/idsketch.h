@@ -159,8 +159,10 @@ ids_status id_gaussian_sketch(const ids_matrix* A, int64_t l, const void* Omega,
  * P = [I, R11^{-1} R12] Pi^T in the original column order (P[:, J[t]] = e_t).
  *   Y      entry (i, j) at Y[i*rs + j*cs]; ydt IDS_F64 or IDS_F32 (FP32 is
  *          widened to FP64 on load; all arithmetic is FP64).
- *   k      1 <= k < n and k <= l; l <= 4096; n at most what fits the
- *          register-resident factorisation (IDS_EINVAL otherwise).
+ *   k      1 <= k < n and k <= l; l <= 4096.  Shapes the register-resident
+ *          factorisation cannot hold (about 2000-8000 columns for long
+ *          sketches, 30000-60000 for short ones) run as column steps
+ *          (columns in HBM, two kernels per pivot step; same results).
  *   J      int64[k]   chosen columns (entries >= k_eff are set to -1).
  *   P      double[k*n] row-major (rows >= k_eff are zero).
  *   k_eff  int64[1]   number of pivots taken: k unless a zero trailing norm
@@ -178,9 +180,12 @@ ids_status id_select(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t r
 /*
  * ids_select_plan_info -- how id_select runs a shape (host only, nothing is
  * launched): info[0] kernel family (0: grouped lanes, l <= 256; 1: row
- * bands), info[1] candidate exchange (0: speculative column slots; 1: the
- * owner publishes the winner's column after the vote), info[2] workgroups,
- * info[3] candidate publishers per pivot step.  int32 info[4], host memory.
+ * bands; 2: column steps -- the columns in HBM and two ordinary kernels per
+ * pivot step, for shapes wider than the register-resident kernels hold),
+ * info[1] candidate exchange (0: speculative column slots; 1: the owner
+ * publishes the winner's column after the vote; 2: none), info[2]
+ * workgroups, info[3] candidate publishers per pivot step.  int32 info[4],
+ * host memory.
  */
 ids_status ids_select_plan_info(int64_t l, int64_t n, int64_t k, int32_t* info);
 

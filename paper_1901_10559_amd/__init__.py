@@ -221,8 +221,8 @@ def select_plan_info(l: int, n: int, k: int) -> dict:
     exchange, workgroups, publishers per step); host only."""
     info = (c_i32 * 4)()
     _check(lib().ids_select_plan_info(l, n, k, ctypes.cast(info, c_vp)), "ids_select_plan_info")
-    return {"family": "grouped_lanes" if info[0] == 0 else "row_bands",
-            "exchange": "speculative" if info[1] == 0 else "owner", "workgroups": info[2], "publishers": info[3]}
+    return {"family": ["grouped_lanes", "row_bands", "column_steps"][info[0]],
+            "exchange": ["speculative", "owner", "none"][info[1]], "workgroups": info[2], "publishers": info[3]}
 
 
 def stream_read(buf, checksum, stream=None):

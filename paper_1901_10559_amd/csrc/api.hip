@@ -57,6 +57,7 @@ static bool tune_valid(const std::string& key, int64_t v) {
     if (key == "batched.rl512" || key == "batched.rl256") return v == 0 || v == 36;
     if (key == "project.wgs") return v >= 32 && v <= 4096;
     if (key == "cs.dense.wpc") return v == 0 || (v >= 2 && v <= 8);
+    if (key == "select.steps") return v == 0 || v == 1;
     return false;
 }
 static std::mutex g_tune_mu;
@@ -467,10 +468,10 @@ ids_status ids_select_plan_info(int64_t l, int64_t n, int64_t k, int32_t* info) 
     if (s) return s;
     SelectPlan sp;
     if ((s = select_plan(l, n, k, sp))) return s;
-    info[0] = l <= 256 ? 0 : 1;
-    info[1] = sp.mode;
-    info[2] = sp.nb;
-    info[3] = sp.nh;
+    info[0] = sp.steps ? 2 : (l <= 256 ? 0 : 1);
+    info[1] = sp.steps ? 2 : sp.mode;           // the column-steps path exchanges nothing
+    info[2] = sp.steps ? (int32_t)((n + 3) / 4) : sp.nb;  // its update kernel: 4 columns per workgroup
+    info[3] = sp.steps ? 0 : sp.nh;
     return IDS_OK;
 }
 

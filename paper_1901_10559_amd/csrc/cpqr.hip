@@ -1257,10 +1257,27 @@ static size_t cpqr_lds(const SelectPlan& sp, const Inst& in) {
 // co-resident for this n
 static ids_status select_plan_variant(int64_t l, int64_t n, int64_t k, int variant, SelectPlan& sp);
 
+// the column-steps plan (columns in HBM, two kernels per pivot step)
+static ids_status steps_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp) {
+    if (l > 4096) {
+        set_error("id_select: l must be <= 4096");
+        return IDS_EINVAL;
+    }
+    sp = SelectPlan{};
+    sp.l = l;
+    sp.n = n;
+    sp.k = k;
+    sp.steps = 1;
+    set_error("");
+    return IDS_OK;
+}
+
 ids_status select_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp) {
+    if (tune_get("select.steps", 0)) return steps_plan(l, n, k, sp);
     // the tuned variant; a grouped-lane shape too wide for it takes the other
     // variant if that one holds it (4-wave workgroups are co-resident in
-    // larger numbers)
+    // larger numbers); a shape too wide for the register-resident
+    // factorisation altogether takes the column-steps one
     const int v = gl_variant(l, n);
     ids_status s = select_plan_variant(l, n, k, v, sp);
     if (s == IDS_EINVAL && l <= 256) {
@@ -1271,11 +1288,13 @@ ids_status select_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp) {
             return IDS_OK;
         }
     }
+    if (s == IDS_EINVAL && l <= 4096) return steps_plan(l, n, k, sp);
     return s;
 }
 
 static ids_status select_plan_variant(int64_t l, int64_t n, int64_t k, int variant, SelectPlan& sp) {
     Inst in;
+    sp.steps = 0;
     sp.variant = variant;
     if (!pick(l, sp.variant, in)) {
         set_error("id_select: l must be <= 4096");
@@ -1315,6 +1334,9 @@ static ids_status select_plan_variant(int64_t l, int64_t n, int64_t k, int varia
 static size_t mb_doubles(const SelectPlan& sp) { return (size_t)sp.k * sp.RS + 2 * (size_t)sp.CS; }
 
 size_t select_bytes(const SelectPlan& sp) {
+    if (sp.steps)
+        return steps_bytes(sp.l, sp.n, sp.k, nullptr) + align256(sizeof(double) * (size_t)sp.n * sp.k) +
+               align256(sizeof(double) * (size_t)sp.k * sp.k) + align256(sizeof(int32_t) * (size_t)sp.n);
     return align256(sizeof(double) * mb_doubles(sp)) + align256(sizeof(uint32_t) * 2) +
            align256(sizeof(double) * (size_t)sp.n * sp.k) + align256(sizeof(double) * (size_t)sp.k * sp.k) +
            align256(sizeof(int32_t) * (size_t)sp.n);
@@ -1328,8 +1350,26 @@ void set_wait_limit(int64_t polls) {
     g_wait_limit.store(polls < 0 ? SPIN_LIMIT : (uint32_t)std::min<int64_t>(polls, SPIN_LIMIT));
 }
 
+static ids_status solve_p(const SelectPlan& sp, const double* Rt, const double* R11c, const int32_t* pos,
+                          int64_t* keff, double* P, hipStream_t st, bool prof);
+
 ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t rs, int64_t cs, int64_t* J,
                       double* P, int64_t* keff, int32_t* status, char* ws, hipStream_t st, bool prof) {
+    if (sp.steps) {
+        char* p = ws + steps_bytes(sp.l, sp.n, sp.k, nullptr);
+        double* Rt = (double*)p;
+        p += align256(sizeof(double) * (size_t)sp.n * sp.k);
+        double* R11c = (double*)p;
+        p += align256(sizeof(double) * (size_t)sp.k * sp.k);
+        int32_t* pos = (int32_t*)p;
+        ids_status s;
+        {
+            ProfScope ps(prof ? PK_CPQR : -1, st);
+            s = steps_factor(Y, ydt, sp.l, sp.n, rs, cs, sp.k, J, keff, status, Rt, R11c, pos, ws, st);
+        }
+        if (s) return s;
+        return solve_p(sp, Rt, R11c, pos, keff, P, st, prof);
+    }
     SelArgs a;
     a.status = status;
     a.spin_limit = g_wait_limit.load();
@@ -1375,14 +1415,17 @@ ids_status select_run(const SelectPlan& sp, const void* Y, int32_t ydt, int64_t 
             return IDS_EHIP;
         }
     }
+    return solve_p(sp, a.Rt, a.R11c, a.pos, keff, P, st, prof);
+}
+
+// P = [I, R11^{-1} R12] Pi^T from Rt, R11c and the pivot positions
+static ids_status solve_p(const SelectPlan& sp, const double* Rt, const double* R11c, const int32_t* pos,
+                          int64_t* keff, double* P, hipStream_t st, bool prof) {
     ProfScope ps(prof ? PK_TRSM : -1, st);
     const size_t r11 = sizeof(double) * (size_t)sp.k * sp.k;
     const size_t xb = sizeof(double) * (size_t)sp.k * TRSM_THREADS;
     const unsigned g = (unsigned)((sp.n + TRSM_THREADS - 1) / TRSM_THREADS);
     const size_t lim = lds_limit();
-    const double* Rt = a.Rt;
-    const double* R11c = a.R11c;
-    const int32_t* pos = a.pos;
     const unsigned g16 = (unsigned)((sp.n + 15) / 16);
 #define IDS_TRSM_AXPY(GQ)                                                                                          \
     hipLaunchKernelGGL((trsm_axpy_kernel<GQ>), dim3((unsigned)((sp.n + 256 / GQ - 1) / (256 / GQ))), dim3(256),     \

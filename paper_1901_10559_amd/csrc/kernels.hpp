@@ -71,7 +71,13 @@ struct SelectPlan {
     int64_t RS;             // mailbox doubles per factorisation step
     int64_t CS;             // speculative mode: doubles per set of column slots (two sets)
     int variant;            // kernel variant (tuned knob)
+    int steps = 0;          // 1: columns in HBM, two kernels per pivot step
 };
+// the column-steps factorisation (cpqr_steps.hip): workspace bytes before Rt
+size_t steps_bytes(int64_t l, int64_t n, int64_t k, int64_t* ldw);
+ids_status steps_factor(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t rs, int64_t cs, int64_t k,
+                        int64_t* J, int64_t* keff, int32_t* status, double* Rt, double* R11c, int32_t* pos, char* ws,
+                        hipStream_t st);
 ids_status select_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp);
 size_t select_bytes(const SelectPlan& sp);
 // status: optional device status word; prof: record stage events (when on)
