@@ -908,49 +908,6 @@ __device__ __forceinline__ void stage_r11(double* R11s, const double* __restrict
         });
 }
 
-// P[:, j]: e_t for a chosen column, R11^{-1} R[0:keff, j] otherwise, by
-// back-substitution (one thread per column, in the order of the textbook
-// recurrence x_r = (b_r - sum_{c>r} R11[r][c] x_c) / R11[r][r]).  The solution
-// vector of each thread lives in LDS (xs[c][thread]); R11 is staged in LDS
-// when it fits.
-constexpr int TRSM_THREADS = 64;
-template <bool R11_LDS, bool X_LDS>
-__global__ __launch_bounds__(TRSM_THREADS) void trsm_p_kernel(int64_t n, int64_t k, const double* __restrict__ Rt,
-                                                              const double* __restrict__ R11c,
-                                                              const int32_t* __restrict__ pos,
-                                                              const int64_t* __restrict__ keffp, double* P) {
-    extern __shared__ double sm[];
-    const int64_t keff = *keffp;
-    if (keff < 0) return;
-    double* R11s = sm;
-    double* xs = sm + (R11_LDS ? k * k : 0);
-    if (R11_LDS) {
-        stage_r11(R11s, R11c, k, (int)keff, TRSM_THREADS);
-        __syncthreads();
-    }
-    const int tid = threadIdx.x;
-    const int64_t j = (int64_t)blockIdx.x * TRSM_THREADS + tid;
-    if (j >= n) return;
-    const int32_t pj = pos[j];
-    if (pj >= 0) {
-        for (int64_t r = 0; r < k; ++r) P[r * n + j] = (r == pj) ? 1.0 : 0.0;
-        return;
-    }
-    for (int64_t r = keff - 1; r >= 0; --r) {
-        double s = Rt[j * k + r];
-        for (int64_t c = r + 1; c < keff; ++c) {
-            const double rc = R11_LDS ? R11s[r * keff + c] : R11c[c * k + r];
-            const double xc = X_LDS ? xs[c * TRSM_THREADS + tid] : P[c * n + j];
-            s = fma(-rc, xc, s);
-        }
-        const double d = R11_LDS ? R11s[r * keff + r] : R11c[r * k + r];
-        const double x = s / d;
-        if (X_LDS) xs[r * TRSM_THREADS + tid] = x;
-        P[r * n + j] = x;
-    }
-    for (int64_t r = keff; r < k; ++r) P[r * n + j] = 0.0;
-}
-
 // Faster variant for k <= 16*KS with R11 in LDS: a group of 16 lanes solves one column.  Lane q
 // of the group keeps x_c and b_c for c = 16*s + q in register slot s; at step r
 // every lane forms its part of b_r - sum_{c>r} R11[r][c] x_c, the 16 parts are
@@ -1423,8 +1380,6 @@ static ids_status solve_p(const SelectPlan& sp, const double* Rt, const double* 
                           int64_t* keff, double* P, hipStream_t st, bool prof) {
     ProfScope ps(prof ? PK_TRSM : -1, st);
     const size_t r11 = sizeof(double) * (size_t)sp.k * sp.k;
-    const size_t xb = sizeof(double) * (size_t)sp.k * TRSM_THREADS;
-    const unsigned g = (unsigned)((sp.n + TRSM_THREADS - 1) / TRSM_THREADS);
     const size_t lim = lds_limit();
     const unsigned g16 = (unsigned)((sp.n + 15) / 16);
 #define IDS_TRSM_AXPY(GQ)                                                                                          \
@@ -1458,15 +1413,8 @@ static ids_status solve_p(const SelectPlan& sp, const double* Rt, const double* 
         IDS_TRSM_GROUP(16);
 #undef IDS_TRSM_GROUP
 #undef IDS_TRSM_AXPY
-    else if (r11 + xb <= lim)
-        hipLaunchKernelGGL((trsm_p_kernel<true, true>), dim3(g), dim3(TRSM_THREADS), r11 + xb, st, sp.n, sp.k, Rt,
-                           R11c, pos, (const int64_t*)keff, P);
-    else if (xb <= lim)
-        hipLaunchKernelGGL((trsm_p_kernel<false, true>), dim3(g), dim3(TRSM_THREADS), xb, st, sp.n, sp.k, Rt,
-                           R11c, pos, (const int64_t*)keff, P);
     else
-        hipLaunchKernelGGL((trsm_p_kernel<false, false>), dim3(g), dim3(TRSM_THREADS), 0, st, sp.n, sp.k, Rt,
-                           R11c, pos, (const int64_t*)keff, P);
+        return solve_blocked(sp.n, sp.k, Rt, R11c, pos, keff, P, st);  // k > 256
     return check_launch("cpqr / interpolation matrix");
 }
 

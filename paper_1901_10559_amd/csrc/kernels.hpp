@@ -73,6 +73,10 @@ struct SelectPlan {
     int variant;            // kernel variant (tuned knob)
     int steps = 0;          // 1: columns in HBM, two kernels per pivot step
 };
+// P from Rt / R11c / pos for large k: blocked back-substitution on the FP64
+// matrix cores, in place in P (solve_blk.hip)
+ids_status solve_blocked(int64_t n, int64_t k, const double* Rt, const double* R11c, const int32_t* pos,
+                         const int64_t* keff, double* P, hipStream_t st);
 // the column-steps factorisation (cpqr_steps.hip): workspace bytes before Rt
 size_t steps_bytes(int64_t l, int64_t n, int64_t k, int64_t* ldw);
 ids_status steps_factor(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t rs, int64_t cs, int64_t k,

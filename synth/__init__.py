@@ -152,18 +152,32 @@ def cp_tensor(dims=(2000, 2000, 2000), R: int = 2000, nbase: int = 50, pert: flo
     return factors, lam, base_of
 
 
-def cp_sparse(N: int = 5, I: int = 10000, R: int = 2000, K: int = 200, density: float = 0.01, seed: int = 0):
+def cp_sparse(N: int = 5, I: int = 10000, R: int = 2000, K: int = 200, density: float = 0.01, seed: int = 0,
+              fmt: str = "dense"):
     """Sparse N-way CP tensor of the paper's synthetic tensor experiment (Section
     on tensor ID experiments, experiment 1): every factor column is a random
     sparse vector with the given density (nonzero positions uniform without
     replacement, N(0, 1) values), scaled to unit 2-norm as the CP form requires;
     lambda_r = 10^(-8 (r - 1) / R) for r <= K and 10^-8 beyond (the schedule
     as printed, with the paper's R = 10000 and K = 1000 scaled down to R, K).
-    Factors are returned dense, I x R, column-major."""
+    Factors are returned dense, I x R, column-major, or with fmt="csc" as
+    (colptr int64[R+1], rowind int32 ascending within a column, val) triples
+    holding the same entries (the same draws)."""
     g = rng(seed, _T_SPARSE)
     nnz = max(1, int(round(density * I)))
     factors = []
     for _ in range(N):
+        if fmt == "csc":
+            ri = np.empty(R * nnz, dtype=np.int32)
+            va = np.empty(R * nnz, dtype=np.float64)
+            for r in range(R):
+                rows = g.choice(I, size=nnz, replace=False)
+                v = g.standard_normal(nnz)
+                o = np.argsort(rows)
+                ri[r * nnz:(r + 1) * nnz] = rows[o]
+                va[r * nnz:(r + 1) * nnz] = (v / np.linalg.norm(v))[o]
+            factors.append((np.arange(0, (R + 1) * nnz, nnz, dtype=np.int64), ri, va))
+            continue
         F = np.zeros((I, R), dtype=np.float64, order="F")
         for r in range(R):
             rows = g.choice(I, size=nnz, replace=False)

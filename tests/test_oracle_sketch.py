@@ -111,3 +111,13 @@ def test_gaussian_stream_draw():
     u2 = (z[1::2] >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
     ref = np.sqrt(-2 * np.log(u1)) * np.cos(2 * np.pi * u2)
     np.testing.assert_allclose(oracle.gaussian(11, 5, 4, 5).ravel(), ref, rtol=1e-14, atol=1e-15)
+
+
+def test_cp_sparse_csc_form_holds_the_same_entries():
+    import scipy.sparse as sp
+    dense, lam = synth.cp_sparse(N=3, I=50, R=7, K=3, density=0.1, seed=4)
+    csc, lam2 = synth.cp_sparse(N=3, I=50, R=7, K=3, density=0.1, seed=4, fmt="csc")
+    assert np.array_equal(lam, lam2)
+    for F, (cp, ri, va) in zip(dense, csc):
+        assert np.all(np.diff(ri.reshape(7, -1), axis=1) > 0)
+        assert np.array_equal(sp.csc_matrix((va, ri, cp), shape=F.shape).toarray(), F)
