@@ -348,6 +348,11 @@ def other_workloads(ids, torch, np, steps: int = 10, check: bool = True, cpu: bo
          "countsketch_roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBPS,
                                   "unit": "GB/s", "frac": gbs / HBM_PEAK_GBPS,
                                   "algorithmic_bytes": int(cs_bytes)}}
+    # the ordered (bitwise-reproducible) CountSketch, IDS_DETERMINISTIC
+    ms_d, st_d = timed(lambda: ids.matrix_id(Ad, 50, 240, 60, seed=0, G=G2, deterministic=True),
+                       ("countsketch",))
+    w["deterministic"] = {"ms_per_id": ms_d, "countsketch_ms": st_d["countsketch"],
+                          "countsketch_GBps": cs_bytes / (st_d["countsketch"] / 1e3) / 1e9}
     if check or cpu:
         r = ids.matrix_id(Ad, 50, 240, 60, seed=0, G=G2, check=True)
         rate, runs, el, o = oracle_timed(lambda: oracle.matrix_id(csr=(rp, ci, v), n=20000, k=50, l1=240, seed=0,

@@ -73,6 +73,12 @@ enum { IDS_DENSE = 0, IDS_CSR = 1 };
 #define IDS_CHECK_FINITE 2u  /* scan the finished sketch Y and write IDS_OK or
                                 IDS_ENONFINITE to cfg->status (a NaN or infinity
                                 anywhere in A reaches Y through its bucket) */
+#define IDS_DETERMINISTIC 4u /* CSR A: add the entries of a bucket in increasing
+                                row order (a row's entries in storage order), the
+                                order of the definition of S A, so repeated runs
+                                give bitwise-identical Y (and J, P); slower than
+                                the default atomic accumulation.  Dense A is
+                                always summed in this order; no effect there */
 
 typedef struct {
     int32_t fmt;            /* IDS_DENSE: row-major m x n, leading dim ld (elements)
@@ -90,7 +96,8 @@ typedef struct {
     int64_t l;              /* final sketch height; l == l1: no projection (the   */
                             /* paper's Algorithm 2 exactly); l < l1: Y = G (S A)  */
     uint64_t seed, tag;     /* random-map stream                                   */
-    uint32_t flags;         /* IDS_HASH_FULLRANK                                   */
+    uint32_t flags;         /* IDS_HASH_FULLRANK | IDS_CHECK_FINITE |
+                               IDS_DETERMINISTIC                                   */
     int32_t acc;            /* CountSketch accumulation: IDS_F64 or IDS_F32        */
                             /* (F64 input requires IDS_F64)                        */
     int32_t proj;           /* projection arithmetic: IDS_F64 (FP64 MFMA) or       */
@@ -120,7 +127,8 @@ typedef struct {
  * row order, the order of the textbook definition).  CSR A is summed with
  * atomic adds whose order is not fixed: Y can differ between runs by
  * rounding (FP64, a few ulps of the bucket sums), and is exact whenever the
- * sums are (e.g. integer-valued entries).
+ * sums are (e.g. integer-valued entries); with IDS_DETERMINISTIC it is summed
+ * in the definition's order and is bitwise reproducible.
  */
 ids_status ids_sketch_workspace_size(const ids_matrix* A, const ids_sketch_cfg* cfg,
                                      size_t* bytes);

@@ -35,6 +35,7 @@ F64, F32, BF16 = 0, 1, 2
 DENSE, CSR = 0, 1
 HASH_FULLRANK = 1
 CHECK_FINITE = 2
+DETERMINISTIC = 4
 # status codes (returned by calls: 0..4; written to device status words: 0, 5..7)
 OK, EINVAL, EDTYPE, EWORKSPACE, EHIP, ETIMEOUT, ERANKDEF, ENONFINITE = range(8)
 
@@ -279,10 +280,11 @@ def profile_reset():
 
 
 def id_sketch(A, l1: int, l: int | None = None, *, seed: int = 0, tag: int = 0, G=None, acc: int | None = None,
-              fullrank=None, stream=None, check_finite=None):
+              fullrank=None, stream=None, check_finite=None, deterministic: bool = False):
     """Y = (G) S A, returned as an l x n view of a column-major buffer.
     check_finite: an int32 device tensor that receives IDS_OK or
-    IDS_ENONFINITE from a scan of Y (flag IDS_CHECK_FINITE)."""
+    IDS_ENONFINITE from a scan of Y (flag IDS_CHECK_FINITE).
+    deterministic: CSR entries summed in row order (flag IDS_DETERMINISTIC)."""
     torch = _torch()
     desc, dev = _matrix_desc(A)
     if l is None:
@@ -296,6 +298,8 @@ def id_sketch(A, l1: int, l: int | None = None, *, seed: int = 0, tag: int = 0, 
         flags |= HASH_FULLRANK
     if check_finite is not None:
         flags |= CHECK_FINITE
+    if deterministic:
+        flags |= DETERMINISTIC
     cfg = IdsSketchCfg(l1, l, seed, tag, flags, acc, acc, c_vp(G.data_ptr()) if G is not None else None,
                        c_vp(pi.data_ptr()) if pi is not None else None, c_vp(x.data_ptr()) if x is not None else None,
                        _ptr(check_finite))
@@ -394,11 +398,13 @@ def id_select_noalloc(Y, k: int, J, P, keff, status=None, stream=None):
 
 
 def matrix_id(A, k: int, l1: int, l: int | None = None, *, seed: int = 0, tag: int = 0, G=None,
-              acc: int | None = None, fullrank=None, stream=None, check: bool = False):
+              acc: int | None = None, fullrank=None, stream=None, check: bool = False,
+              deterministic: bool = False):
     """Algorithm 2 (+ optional projection), then Algorithm 1.  Returns dict
     with Y, J, P, k_eff and the device status word ("status").  check=True
     waits for the result and raises on IDS_ETIMEOUT / IDS_ENONFINITE."""
-    Y = id_sketch(A, l1, l, seed=seed, tag=tag, G=G, acc=acc, fullrank=fullrank, stream=stream)
+    Y = id_sketch(A, l1, l, seed=seed, tag=tag, G=G, acc=acc, fullrank=fullrank, stream=stream,
+                  deterministic=deterministic)
     st = _status(_torch(), Y.device)
     J, P, keff = id_select(Y, k, stream=stream, status=st)
     if check:

@@ -165,7 +165,8 @@ static ids_status validate_sketch(const ids_matrix* A, const ids_sketch_cfg* c) 
     if (A->dtype == IDS_F64 && c->acc != IDS_F64) return fail(IDS_EDTYPE, "FP64 input needs FP64 accumulation");
     if (A->fmt == IDS_CSR && c->acc != IDS_F64) return fail(IDS_EDTYPE, "CSR input needs FP64 accumulation");
     if (c->l < c->l1 && c->proj != c->acc) return fail(IDS_EDTYPE, "proj must equal acc");
-    if (c->flags & ~(IDS_HASH_FULLRANK | IDS_CHECK_FINITE)) return fail(IDS_EINVAL, "unknown flag bits");
+    if (c->flags & ~(IDS_HASH_FULLRANK | IDS_CHECK_FINITE | IDS_DETERMINISTIC))
+        return fail(IDS_EINVAL, "unknown flag bits");
     if ((c->flags & IDS_CHECK_FINITE) && !c->status) return fail(IDS_EINVAL, "IDS_CHECK_FINITE needs status");
     if ((c->flags & IDS_HASH_FULLRANK) && (!c->fr_pi || !c->fr_x))
         return fail(IDS_EINVAL, "IDS_HASH_FULLRANK needs fr_pi and fr_x");
@@ -343,7 +344,7 @@ ids_status id_sketch(const ids_matrix* A, const ids_sketch_cfg* c, void* Y, int3
             s = cs_dense(A->dtype, c->acc, A->val, A->ld, A->n, pb, c->l1, dst, rs, cs, st);
         else
             s = cs_csr(A->rowptr, A->colind, (const double*)A->val, A->m, A->n, pb, c->l1, (double*)dst, rs, cs,
-                       bop, st);
+                       bop, (c->flags & IDS_DETERMINISTIC) != 0, st);
     }
     if (s) return s;
     if (proj) {

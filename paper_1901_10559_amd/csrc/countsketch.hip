@@ -594,18 +594,70 @@ __device__ __forceinline__ int wave_max_scan(int x) {
     return x;
 }
 
+// one batch of up to 64 rows of a bucket's row list, one row per lane: the
+// lengths scanned over the wave so that the batch's entries form one sequence
+struct CsrBatch {
+    int64_t T;      // entries in the batch
+    int64_t pre;    // start of this lane's row in the batch's sequence
+    int64_t len;    // this lane's row length (0 past the list's end)
+    int64_t base2;  // 2 (first entry of the row - pre) + sign bit
+    int64_t e_any;  // an entry index every lane may load
+};
+
+__device__ __forceinline__ CsrBatch csr_batch(const int64_t* __restrict__ rowptr, bool have, int32_t code,
+                                              int64_t nnz) {
+    CsrBatch q;
+    int64_t e0 = 0;
+    q.len = 0;
+    if (have) {
+        const int64_t i = code >= 0 ? code : -(int64_t)code - 1;
+        e0 = rowptr[i];
+        q.len = rowptr[i + 1] - e0;
+    }
+    const int64_t inc = wave_incl_scan(q.len);
+    q.T = __shfl(inc, 63, 64);
+    q.pre = inc - q.len;
+    q.base2 = 2 * (e0 - q.pre) + (code < 0 ? 1 : 0);
+    const uint64_t nz = __ballot(q.len > 0);
+    q.e_any = nz ? min(__shfl(e0, __ffsll((unsigned long long)nz) - 1, 64), nnz - 1) : 0;
+    return q;
+}
+
+// entry index (e), validity (ok) and row sign (sg) of this lane's entry in
+// each of the CSR_U 64-entry chunks that start at entry B of the batch.  The
+// row holding entry Bu is the last row whose start is <= Bu: the row running
+// into the chunk comes from one ballot (rows are in start order), each row
+// starting inside the chunk announces its index at its start lane with one
+// forward permute, and a max-scan over the lanes hands every lane its row.
+// Branch-free, so the searches of the chunks interleave; lanes past the end
+// get e_any.
+__device__ __forceinline__ void csr_chunk_entries(const CsrBatch& q, int64_t B, int64_t nnz, int64_t (&e)[CSR_U],
+                                                  bool (&ok)[CSR_U], bool (&sg)[CSR_U]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < CSR_U; ++u) {
+        const int64_t Bu = B + 64 * u;
+        const int rc = __popcll(__ballot(q.pre <= Bu)) - 1;
+        const int64_t d = q.pre - Bu;
+        const bool in = q.len > 0 && d > 0 && d < 64;
+        const int post = __builtin_amdgcn_ds_permute(in ? (int)d * 4 : 0, in ? lane + 1 : 0);
+        const int r = min(63, max(rc, wave_max_scan(post) - 1));
+        const int64_t bb = __shfl(q.base2, r, 64);
+        const int64_t qq = Bu + lane;
+        ok[u] = qq < q.T;
+        sg[u] = bb & 1;
+        e[u] = ok[u] ? max((int64_t)0, min((bb >> 1) + qq, nnz - 1)) : q.e_any;
+    }
+}
+
 // LDS-privatised variant: the whole bucket row of Y1 (n <= CSR_LDS_MAX) lives in
 // LDS; a workgroup handles positions [p0, p1) of the bucket's row list.
 // Entry-parallel: a wave takes a batch of 64 consecutive rows of the list
 // (batches are handed out through an LDS counter), scans their lengths, and
 // then walks the batch's entries 64 at a time, lane q taking the q-th entry of
 // the chunk, so the loads of val / colind are coalesced whatever the row
-// lengths are.  The row of an entry is the last row whose start is <= it: the
-// row running into the chunk comes from one ballot (rows are in start order),
-// each row starting inside the chunk announces its index at its start lane
-// with one forward permute, and a max-scan over the lanes hands every lane its
-// row.  CSR_U chunks are loaded before their LDS adds, so that many loads are
-// in flight.
+// lengths are (csr_batch, csr_chunk_entries).  CSR_U chunks are loaded before
+// their LDS adds, so that many loads are in flight.
 __global__ __launch_bounds__(CSR_THREADS) void cs_csr_lds_kernel(const int64_t* __restrict__ rowptr,
                                                                   const int32_t* __restrict__ colind,
                                                                   const double* __restrict__ val, int64_t m,
@@ -642,14 +694,7 @@ __global__ __launch_bounds__(CSR_THREADS) void cs_csr_lds_kernel(const int64_t* 
         code = have ? rows[p] : 0;
     }
     while (bi < nbat) {
-        // this batch: one row per lane
-        int64_t e0 = 0, len = 0;
-        if (have) {
-            const int64_t i = code >= 0 ? code : -(int64_t)code - 1;
-            e0 = rowptr[i];
-            len = rowptr[i + 1] - e0;
-        }
-        const bool neg = code < 0;
+        const CsrBatch q = csr_batch(rowptr, have, code, nnz);
         // next batch's row codes load while this one is summed
         const int bn = grab();
         bool have_n = false;
@@ -659,36 +704,11 @@ __global__ __launch_bounds__(CSR_THREADS) void cs_csr_lds_kernel(const int64_t* 
             have_n = p < p1;
             code_n = have_n ? rows[p] : 0;
         }
-        const int64_t inc = wave_incl_scan(len);
-        const int64_t T = __shfl(inc, 63, 64);
-        const int64_t pre = inc - len;  // start of this lane's row in the batch's entry sequence
-        // entry q of the batch is element (e0 - pre) + q of val / colind; the
-        // row's sign rides in the low bit
-        const int64_t base2 = 2 * (e0 - pre) + (neg ? 1 : 0);
-        // an entry every lane may load: the first entry of the batch
-        const uint64_t nz = __ballot(len > 0);
-        const int64_t e_any = nz ? min(__shfl(e0, __ffsll((unsigned long long)nz) - 1, 64), nnz - 1) : 0;
-        for (int64_t B = 0; B < T; B += 64 * CSR_U) {
-            // (1) entry index of every chunk (branch-free, so the searches of
-            //     the chunks interleave); lanes past the end load e_any
+        for (int64_t B = 0; B < q.T; B += 64 * CSR_U) {
+            // (1) entry index of every chunk
             int64_t e[CSR_U];
             bool ok[CSR_U], sg[CSR_U];
-#pragma unroll
-            for (int u = 0; u < CSR_U; ++u) {
-                const int64_t Bu = B + 64 * u;
-                // the row holding entry Bu: the last row with start <= Bu
-                const int rc = __popcll(__ballot(pre <= Bu)) - 1;
-                // rows starting at Bu + d, 0 < d < 64, post index + 1 at lane d
-                const int64_t d = pre - Bu;
-                const bool in = len > 0 && d > 0 && d < 64;
-                const int post = __builtin_amdgcn_ds_permute(in ? (int)d * 4 : 0, in ? lane + 1 : 0);
-                const int r = min(63, max(rc, wave_max_scan(post) - 1));
-                const int64_t bb = __shfl(base2, r, 64);
-                const int64_t q = Bu + lane;
-                ok[u] = q < T;
-                sg[u] = bb & 1;
-                e[u] = ok[u] ? max((int64_t)0, min((bb >> 1) + q, nnz - 1)) : e_any;
-            }
+            csr_chunk_entries(q, B, nnz, e, ok, sg);
             // (2) all loads in flight
             double v[CSR_U];
             int32_t c[CSR_U];
@@ -735,6 +755,88 @@ __global__ __launch_bounds__(256) void cs_csr_global_kernel(const int64_t* __res
     }
 }
 
+// Ordered variant (IDS_DETERMINISTIC): every entry of Y1 is the sum of its
+// bucket's signed entries in increasing row order, the entries of one row in
+// storage order -- the sequence of additions of the textbook definition, so
+// repeated runs agree bit for bit.  Workgroup (bucket, panel) of CSD_W waves;
+// wave w owns a contiguous range of at most CSD_WR columns and keeps their
+// sums in LDS, so no two waves ever add to one location.  Every wave walks all
+// rows of the bucket in list order (64-row batches, 64-entry chunks as above)
+// and keeps the entries of its own range.  Inside a chunk, entries that fall
+// on the same column are added in lane order, i.e. entry order: each round,
+// the lowest pending lane of every tag slot (slot = column mod CSD_SLOTS; a
+// minimum over the lane indices) adds its entry and leaves.  A wave's LDS
+// operations complete in issue order; the wavefront fences only keep the
+// compiler from moving them.  Every wave reads every entry of its bucket, so
+// the cost grows with the number of column ranges (n / CSD_WR).
+constexpr int CSD_W = 4;
+constexpr int CSD_WR = 2048;
+constexpr int CSD_SLOTS = 256;
+
+__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+__global__ __launch_bounds__(64 * CSD_W) void cs_csr_ordered_kernel(const int64_t* __restrict__ rowptr,
+                                                                    const int32_t* __restrict__ colind,
+                                                                    const double* __restrict__ val, int64_t m,
+                                                                    const int32_t* __restrict__ off,
+                                                                    const int32_t* __restrict__ rows, int npanel,
+                                                                    int64_t n, int64_t wr, double* __restrict__ Y,
+                                                                    int64_t rs, int64_t cs) {
+    __shared__ double acc[CSD_W][CSD_WR];
+    __shared__ int tag[CSD_W][CSD_SLOTS];
+    const int b = blockIdx.x / npanel;
+    const int pnl = blockIdx.x % npanel;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t c0 = ((int64_t)pnl * CSD_W + w) * wr;
+    const int64_t c1 = min(n, c0 + wr);
+    if (c0 >= c1) return;  // wave-uniform; the waves never synchronise with each other
+    double* my = acc[w];
+    int* tg = tag[w];
+    for (int64_t j = lane; j < c1 - c0; j += 64) __hip_atomic_store(my + j, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    for (int q = lane; q < CSD_SLOTS; q += 64) __hip_atomic_store(tg + q, 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    wave_fence();
+    const int beg = off[b], end = off[b + 1];
+    const int64_t nnz = rowptr[m];
+    for (int p0 = beg; p0 < end; p0 += 64) {
+        const int p = p0 + lane;
+        const bool have = p < end;
+        const CsrBatch q = csr_batch(rowptr, have, have ? rows[p] : 0, nnz);
+        for (int64_t B = 0; B < q.T; B += 64 * CSR_U) {
+            int64_t e[CSR_U];
+            bool ok[CSR_U], sg[CSR_U];
+            csr_chunk_entries(q, B, nnz, e, ok, sg);
+            double v[CSR_U];
+            int32_t c[CSR_U];
+#pragma unroll
+            for (int u = 0; u < CSR_U; ++u) {
+                v[u] = val[e[u]];
+                c[u] = colind[e[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < CSR_U; ++u) {
+                bool pend = ok[u] && c[u] >= c0 && c[u] < c1;
+                const double x = sg[u] ? -v[u] : v[u];
+                const int slot = c[u] & (CSD_SLOTS - 1);
+                double* dst = my + (pend ? c[u] - c0 : 0);
+                while (__ballot(pend)) {
+                    if (pend) __hip_atomic_fetch_min(tg + slot, lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    wave_fence();
+                    const bool go = pend && __hip_atomic_load(tg + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == lane;
+                    if (go) {
+                        const double y = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                        __hip_atomic_store(dst, y + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    }
+                    if (pend) __hip_atomic_store(tg + slot, 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    wave_fence();
+                    pend = pend && !go;
+                }
+            }
+        }
+    }
+    for (int64_t j = c0 + lane; j < c1; j += 64)
+        Y[(int64_t)b * rs + j * cs] = __hip_atomic_load(my + (j - c0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
 // bucket index of every position of the plan's row list
 __global__ void plan_bucket_of_pos_kernel(const int32_t* off, int64_t L, int32_t* bop) {
     const int b = blockIdx.x;
@@ -751,7 +853,20 @@ __global__ void fill_f64_kernel(double* y, int64_t rows, int64_t cols, int64_t r
 
 ids_status cs_csr(const int64_t* rowptr, const int32_t* colind, const double* val, int64_t m, int64_t n,
                   const PlanBufs& pb, int64_t L, double* Y, int64_t rs, int64_t cs, int32_t* scratch_bop,
-                  hipStream_t st) {
+                  bool ordered, hipStream_t st) {
+    if (ordered) {
+        // column ranges of at most CSD_WR, CSD_W of them per workgroup
+        const int64_t nr = (n + CSD_WR - 1) / CSD_WR;
+        const int npanel = (int)((nr + CSD_W - 1) / CSD_W);
+        const int64_t wr = (n + (int64_t)npanel * CSD_W - 1) / ((int64_t)npanel * CSD_W);
+        if (L * npanel > INT32_MAX) {
+            set_error("id_sketch: IDS_DETERMINISTIC: l1 * ceil(n / 8192) workgroups exceed the grid");
+            return IDS_EINVAL;
+        }
+        hipLaunchKernelGGL(cs_csr_ordered_kernel, dim3((unsigned)(L * npanel)), dim3(64 * CSD_W), 0, st, rowptr,
+                           colind, val, m, (const int32_t*)pb.off, (const int32_t*)pb.rows, npanel, n, wr, Y, rs, cs);
+        return check_launch("countsketch csr (ordered)");
+    }
     const size_t lds = sizeof(double) * (size_t)n;
     if (lds + 256 <= CSR_LDS_MAX_BYTES) {  // + the static batch counter
         // about one workgroup per compute unit (one fits, the LDS row is large);
