@@ -471,7 +471,7 @@ ids_status ids_select_plan_info(int64_t l, int64_t n, int64_t k, int32_t* info) 
     if ((s = select_plan(l, n, k, sp))) return s;
     info[0] = sp.steps ? 2 : (l <= 256 ? 0 : 1);
     info[1] = sp.steps ? 2 : sp.mode;           // the column-steps path exchanges nothing
-    info[2] = sp.steps ? (int32_t)((n + 3) / 4) : sp.nb;  // its update kernel: 4 columns per workgroup
+    info[2] = sp.steps ? (int32_t)steps_workgroups(l, n) : sp.nb;  // one column per wave
     info[3] = sp.steps ? 0 : sp.nh;
     return IDS_OK;
 }

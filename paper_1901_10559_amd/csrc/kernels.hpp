@@ -79,6 +79,7 @@ ids_status solve_blocked(int64_t n, int64_t k, const double* Rt, const double* R
                          const int64_t* keff, double* P, hipStream_t st);
 // the column-steps factorisation (cpqr_steps.hip): workspace bytes before Rt
 size_t steps_bytes(int64_t l, int64_t n, int64_t k, int64_t* ldw);
+int64_t steps_workgroups(int64_t l, int64_t n);  // workgroups of each column-steps kernel
 ids_status steps_factor(const void* Y, int32_t ydt, int64_t l, int64_t n, int64_t rs, int64_t cs, int64_t k,
                         int64_t* J, int64_t* keff, int32_t* status, double* Rt, double* R11c, int32_t* pos, char* ws,
                         hipStream_t st);

@@ -192,3 +192,42 @@ def test_batched_full_batch_4096(tmp_path):
     print(f"residual ratio over {nprob}: median {np.median(ratio):.6f} max {ratio.max():.6f} "
           f"(oracle {wall:.1f} s on {workers} processes)", flush=True)
     assert ratio.max() <= 2.0
+
+
+def test_sparse5way_paper_scale_I10000_R10000_K1000():
+    # the paper's synthetic tensor experiment at its own size (R = 10000 terms,
+    # target rank 1000; Section on tensor ID experiments, experiment 1) with
+    # CSC factors and J = 1024: sampled sketch columns against the direct
+    # convolution, then the oracle's Algorithm 1 on the library's sketch
+    # against the library's pivots, P and lambda_hat (this shape takes the
+    # column-steps QR and the blocked solve)
+    N, I, R, K, Jlen = 5, 10000, 10000, 1000, 1024
+    fac, lam = synth.cp_sparse(N=N, I=I, R=R, K=K, density=0.01, seed=0, fmt="csc")
+    d = [(dev(cp), dev(ri), dev(va), I) for cp, ri, va in fac]
+    print("paper-scale sparse 5-way tensor_id_csc R=10000 k=1000 J=1024", flush=True)
+    r = ids.tensor_id_csc(d, dev(lam), K, Jlen, seed=0, return_Y=True, check=True)
+    Yg = r["Y"].cpu().numpy()
+    cols = np.linspace(0, R - 1, 8).astype(np.int64)
+    dense = []
+    for cp, ri, va in fac:
+        F = np.zeros((I, cols.size))
+        for q, c in enumerate(cols):
+            F[ri[cp[c]:cp[c + 1]], q] = va[cp[c]:cp[c + 1]]
+        dense.append(F)
+    Yo = oracle.tensorsketch(dense, lam[cols], oracle.tensor_maps(0, [I] * N, Jlen), Jlen)
+    scale = np.linalg.norm(Yo, axis=0, keepdims=True)
+    assert np.max(np.abs(Yg[:, cols] - Yo) / scale) <= 1e-13
+    print("paper-scale: oracle Algorithm 1 on the 1024 x 10000 sketch", flush=True)
+    Jo, Po, ko, _, nu = oracle.cpqr_id(Yg, K, trace=True)
+    assert int(r["k_eff"].item()) == ko == K
+    Jg = r["J"].cpu().numpy()
+    if np.array_equal(Jg, Jo):
+        Pg = r["P"].cpu().numpy()
+        assert np.linalg.norm(Pg - Po) <= 1e-10 * np.linalg.norm(Po)
+        assert np.array_equal(Pg[:, Jg], np.eye(K))
+        lo = oracle.lambda_hat(Po, Jo, lam)
+        assert np.max(np.abs(r["lambda_hat"].cpu().numpy() - lo) / np.abs(lo)) <= 1e-10
+    else:
+        t = int(np.argmax(Jg != Jo))
+        row = np.sort(nu[t][nu[t] >= 0])[::-1]
+        assert len(row) > 1 and row[0] - row[1] <= 1e-12 * row[0], (t, row[:2])
