@@ -96,31 +96,3 @@ def test_fullrank_collision_probability():
     # and the plain-hash probability 1/L is rejected at this size
     assert abs(p_hat - 1.0 / L) > 3 * sd
 
-
-def _mix64_bigint(x: int) -> int:
-    # SplitMix64's output function (Steele, Lea and Flood, OOPSLA 2014), in
-    # Python's unbounded integers reduced mod 2^64 after every step
-    M = (1 << 64) - 1
-    x &= M
-    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & M
-    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & M
-    return x ^ (x >> 31)
-
-
-@pytest.mark.parametrize("seed,tag", [(1, 0), (0, 1), (12345, 678), ((1 << 63) + 5, 3), ((1 << 64) - 1, (1 << 63) | 9)])
-def test_keyed_stream_against_bigint(seed, tag):
-    # the keyed stream of every (seed, tag): key = mix64(seed ^ mix64(tag)),
-    # z_i = mix64(key + (i + 1) gamma), bucket = (z_i >> 32) L >> 32, sign from
-    # bit 0 -- recomputed here in arbitrary-precision integers, independent of
-    # the oracle's fixed-width C arithmetic
-    M = (1 << 64) - 1
-    gamma = 0x9E3779B97F4A7C15
-    key = _mix64_bigint(seed ^ _mix64_bigint(tag))
-    assert oracle.lib().orc_stream_key(seed, tag) == key
-    m = 700
-    zb = [_mix64_bigint((key + (i + 1) * gamma) & M) for i in range(m)]
-    assert [int(v) for v in oracle.stream(seed, tag, m)] == zb
-    for L in (1, 37, 480, 4096, 32768):
-        b, s = oracle.hash_maps(seed, tag, m, L)
-        assert [int(x) for x in b] == [((z >> 32) * L) >> 32 for z in zb]
-        assert [int(x) for x in s] == [1 if (z & 1) == 0 else -1 for z in zb]
