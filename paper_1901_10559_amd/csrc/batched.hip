@@ -507,6 +507,7 @@ __global__ __launch_bounds__(NT, RL ? 4 : 2) void batched_cpqr_kernel(BatchArgs 
         // and all are in flight together; masked after compiler barriers):
         // the LDS rows travel through y first, then the register rows
         static_assert(RL <= RR, "LDS rows are staged in y");
+        static_assert(RL % 4 == 0, "the pivot column is published in 16-byte stores");
         const float* colp = Yp + (int64_t)min(j, n - 1) * l;
 #pragma unroll
         for (int r = 0; r < RL; ++r) y[r] = colp[min(r, l - 1)];
@@ -593,22 +594,31 @@ __global__ __launch_bounds__(NT, RL ? 4 : 2) void batched_cpqr_kernel(BatchArgs 
         //      they are, its LDS rows and the other rows < RL are copied by the
         //      threads j < RL (thread t leaves row t to the owner).
         if (j == wj) {
+            // the register rows in 16-byte stores (RL is a multiple of 4)
 #pragma unroll
-            for (int r = 0; r < RR; ++r) xf[RL + r] = (RL + r < t) ? 0.f : y[r];
+            for (int r = 0; r + 3 < RR; r += 4) {
+                float4 q;
+                q.x = (RL + r < t) ? 0.f : y[r];
+                q.y = (RL + r + 1 < t) ? 0.f : y[r + 1];
+                q.z = (RL + r + 2 < t) ? 0.f : y[r + 2];
+                q.w = (RL + r + 3 < t) ? 0.f : y[r + 3];
+                *reinterpret_cast<float4*>(&xf[RL + r]) = q;
+            }
+#pragma unroll
+            for (int r = RR & ~3; r < RR; ++r) xf[RL + r] = (RL + r < t) ? 0.f : y[r];
             const double alpha = (double)((t < RL) ? ylds[t * NT + j] : xf[t]);
-            double tau_o, beta_o, scal_o;
+            double tss_o, beta_o;
             if (!(wnu > alpha * alpha)) {
-                tau_o = 0.0;
+                tss_o = 0.0;  // H = I
                 beta_o = alpha;
-                scal_o = 0.0;
             } else {
                 const double nrm = sqrt(wnu);
                 beta_o = (alpha >= 0.0) ? -nrm : nrm;
-                tau_o = (beta_o - alpha) / beta_o;
-                scal_o = 1.0 / (alpha - beta_o);
+                // tau scal^2 with tau = (beta - alpha) / beta, scal = 1 / (alpha - beta)
+                tss_o = -1.0 / (beta_o * (alpha - beta_o));
             }
             xf[t] = (float)(alpha - beta_o);
-            s_hh[0] = tau_o * scal_o * scal_o;  // H y = y - (tau scal^2 x'^T y) x'
+            s_hh[0] = tss_o;  // H y = y - (tau scal^2 x'^T y) x'
             s_hh[1] = beta_o;
         }
         if (j < RL && j != t) xf[j] = (j < t) ? 0.f : ylds[j * NT + wj];
@@ -630,30 +640,48 @@ __global__ __launch_bounds__(NT, RL ? 4 : 2) void batched_cpqr_kernel(BatchArgs 
                             if (RL + r < BS_LMAX) d[r & 3] = fmaf(xf[RL + r], y[r], d[r & 3]);
                     }
                 const float dt = (float)((double)((d[0] + d[1]) + (d[2] + d[3])) * tss);
+                // the update, with the new trailing norm (rows >= t + 1) summed
+                // as the rows are written: the same rows in the same FP32
+                // accumulators and order as norm_from(t + 1), without reading
+                // the LDS rows a second time
+                double s = 0.0;
                 if (t < RL) {
+                    float f[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 4
-                    for (int r = t; r < RL; ++r)
-                        ylds[r * NT + j] = fmaf(-dt, xf[r], ylds[r * NT + j]);
+                    for (int r = t; r < RL; ++r) {
+                        const float v = fmaf(-dt, xf[r], ylds[r * NT + j]);
+                        ylds[r * NT + j] = v;
+                        if (r > t) f[r & 3] = fmaf(v, v, f[r & 3]);
+                    }
+                    s = (double)((f[0] + f[1]) + (f[2] + f[3]));
                 }
 #pragma unroll
                 for (int c = 0; c < RR; c += 8)
                     if (RL + c + 8 > t) {
+                        float q = 0.f;
 #pragma unroll
-                        for (int r = c; r < c + 8 && r < RR; ++r)
+                        for (int r = c; r < c + 8 && r < RR; ++r) {
                             if (RL + r < BS_LMAX) y[r] = fmaf(-dt, xf[RL + r], y[r]);
+                            const float v = (RL + r > t) ? y[r] : 0.f;
+                            q = fmaf(v, v, q);
+                        }
+                        s += (double)q;
                     }
+                nu = s;
                 if (j == wj) {
                     alive = false;
                     a.pos[roff + j] = t;
                 }
             }
-            nu = norm_from(t + 1);
         }
         if (j == 0) {
             a.J[(int64_t)p * k + t] = wj;
             a.beta[(int64_t)p * k + t] = beta;
         }
-        __syncthreads();
+        // no barrier here: s_nu / s_j are read before the publication barrier
+        // and next written after it; xf and s_hh are read in this update and
+        // next written after the next step's argmax barrier, which every
+        // thread reaches only when its update is done
     }
     // top keff rows of every column -> Rt (FP64); the pivots' diagonal is beta
     if (j < n) {
