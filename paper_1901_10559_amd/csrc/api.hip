@@ -58,6 +58,7 @@ static bool tune_valid(const std::string& key, int64_t v) {
     if (key == "project.wgs") return v >= 32 && v <= 4096;
     if (key == "cs.dense.wpc") return v == 0 || (v >= 2 && v <= 8);
     if (key == "select.steps") return v == 0 || v == 1;
+    if (key == "cs.csr.bin") return v == 0 || v == 1;
     return false;
 }
 static std::mutex g_tune_mu;
@@ -176,7 +177,7 @@ static ids_status validate_sketch(const ids_matrix* A, const ids_sketch_cfg* c) 
 
 struct SketchLayout {
     PlanShape ps;
-    size_t plan, y1, bop, part, gdraw, total;
+    size_t plan, y1, bop, part, gdraw, bin, total;
     int splits;  // projection K split (1: one pass)
 };
 
@@ -192,7 +193,9 @@ static SketchLayout sketch_layout(const ids_matrix* A, const ids_sketch_cfg* c) 
     L.part = (L.splits > 1) ? align256(esize(c->acc) * (size_t)L.splits * c->l * A->n) : 0;
     // G drawn on the device when the caller passes none
     L.gdraw = (c->l < c->l1 && !c->G) ? align256(esize(c->acc) * (size_t)c->l * c->l1) : 0;
-    L.total = L.plan + L.y1 + L.bop + L.part + L.gdraw;
+    // IDS_DETERMINISTIC on CSR input: the binned entries of the ordered sketch
+    L.bin = (A->fmt == IDS_CSR && (c->flags & IDS_DETERMINISTIC)) ? csr_bin_bytes(A->m, A->n, A->nnz, c->l1) : 0;
+    L.total = L.plan + L.y1 + L.bop + L.part + L.gdraw + L.bin;
     return L;
 }
 
@@ -324,6 +327,8 @@ ids_status id_sketch(const ids_matrix* A, const ids_sketch_cfg* c, void* Y, int3
     void* part = p;
     p += L.part;
     void* gdraw = p;
+    p += L.gdraw;
+    char* bin = L.bin ? p : nullptr;
 
     const bool proj = c->l < c->l1;
     const uint64_t key = stream_key(c->seed, c->tag);
@@ -344,7 +349,7 @@ ids_status id_sketch(const ids_matrix* A, const ids_sketch_cfg* c, void* Y, int3
             s = cs_dense(A->dtype, c->acc, A->val, A->ld, A->n, pb, c->l1, dst, rs, cs, st);
         else
             s = cs_csr(A->rowptr, A->colind, (const double*)A->val, A->m, A->n, pb, c->l1, (double*)dst, rs, cs,
-                       bop, (c->flags & IDS_DETERMINISTIC) != 0, st);
+                       bop, (c->flags & IDS_DETERMINISTIC) != 0, A->nnz, bin, st);
     }
     if (s) return s;
     if (proj) {

@@ -837,6 +837,274 @@ __global__ __launch_bounds__(64 * CSD_W) void cs_csr_ordered_kernel(const int64_
         Y[(int64_t)b * rs + j * cs] = __hip_atomic_load(my + (j - c0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
+// Ordered sketch through a stable binning of the entries (IDS_DETERMINISTIC,
+// n <= CSB_WR * CSB_RMAX).  The unbinned kernel above makes every wave of a
+// bucket walk all of the bucket's entries; here the entries are walked twice
+// in all and then read once in sequence:
+//   1. csr_bin_count_kernel: wave (bucket b, row chunk ch) walks its rows of
+//      the bucket's list and counts its entries per column range r (ranges
+//      of wr <= CSB_WR columns) in LDS -> counts[(b R + r) C + ch];
+//   2. csr_bin_scan_kernel: exclusive prefix sum in that (b, r, ch) order;
+//   3. csr_bin_place_kernel: the same walk, each entry (column, signed value)
+//      stored at its range's running offset plus its rank among the chunk's
+//      lanes of the same range (lane order = entry order), so the entries of
+//      (b, r) end up contiguous, in increasing row order, a row's entries in
+//      storage order;
+//   4. csr_bin_sum_kernel: one wave per (b, r) adds its contiguous entries
+//      into its columns' LDS sums in that order (entries of one 64-entry
+//      chunk that share a column in lane order, as in the unbinned kernel)
+//      and writes row b of Y1 for those columns.
+constexpr int CSB_WR = 2048;         // columns per range
+constexpr int CSB_RMAX = 4096;       // ranges (LDS counters per wave)
+constexpr int CSB_ROWS = 256;        // rows per (bucket, chunk) walk, about
+constexpr int64_t CSB_CNT_MAX = int64_t(1) << 24;  // counters (L R C)
+
+struct CsrBinShape {
+    int64_t R, C, wr, ncnt;  // ranges, chunks per bucket, range width, counters
+    size_t cnt_b, col_b, val_b, total;
+};
+
+static CsrBinShape csr_bin_shape(int64_t m, int64_t n, int64_t nnz, int64_t L) {
+    CsrBinShape s{};
+    s.R = (n + CSB_WR - 1) / CSB_WR;
+    s.wr = (n + s.R - 1) / s.R;
+    s.C = std::min<int64_t>(64, std::max<int64_t>(1, (m / std::max<int64_t>(L, 1) + CSB_ROWS - 1) / CSB_ROWS));
+    while (s.C > 1 && L * s.R * s.C > CSB_CNT_MAX) s.C /= 2;
+    s.ncnt = L * s.R * s.C;
+    if (s.R > CSB_RMAX || s.ncnt > CSB_CNT_MAX) {
+        s.total = 0;  // too wide: the unbinned ordered kernel
+        return s;
+    }
+    s.cnt_b = align256(sizeof(int64_t) * (size_t)(s.ncnt + 1));
+    s.col_b = align256(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
+    s.val_b = align256(sizeof(double) * (size_t)std::max<int64_t>(nnz, 1));
+    s.total = s.cnt_b + s.col_b + s.val_b;
+    return s;
+}
+
+size_t csr_bin_bytes(int64_t m, int64_t n, int64_t nnz, int64_t L) { return csr_bin_shape(m, n, nnz, L).total; }
+
+struct CsrBinArgs {
+    const int64_t* rowptr;
+    const int32_t* colind;
+    const double* val;
+    int64_t m, n, nnz_cap;
+    const int32_t* off;   // plan: bucket offsets into rows
+    const int32_t* rows;  // plan: signed row codes grouped by bucket
+    int64_t L, R, C, wr;
+    int rbits;            // bits of a range index
+    int64_t* cnt;         // L R C + 1 counters -> offsets
+    int32_t* bcol;
+    double* bval;
+    double* Y;
+    int64_t rs, cs;
+};
+
+constexpr int CSB_W = 4;  // waves per workgroup in the binning walks
+
+// rows [p0, p1) of bucket b's list for chunk ch
+__device__ __forceinline__ void csb_chunk_rows(const CsrBinArgs& a, int64_t b, int64_t ch, int& p0, int& p1) {
+    const int beg = a.off[b], end = a.off[b + 1];
+    const int64_t cnt = end - beg;
+    p0 = beg + (int)(cnt * ch / a.C);
+    p1 = beg + (int)(cnt * (ch + 1) / a.C);
+}
+
+// every entry of the wave's rows, in order: f(in, col, signed value) is
+// called by all lanes for each 64-entry chunk (in: the lane holds an entry
+// with a column in [0, n))
+template <typename F>
+__device__ __forceinline__ void csb_walk(const CsrBinArgs& a, int p0, int p1, F&& f) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nnz = a.rowptr[a.m];
+    for (int q0 = p0; q0 < p1; q0 += 64) {
+        const int p = q0 + lane;
+        const bool have = p < p1;
+        const CsrBatch q = csr_batch(a.rowptr, have, have ? a.rows[p] : 0, nnz);
+        for (int64_t B = 0; B < q.T; B += 64 * CSR_U) {
+            int64_t e[CSR_U];
+            bool ok[CSR_U], sg[CSR_U];
+            csr_chunk_entries(q, B, nnz, e, ok, sg);
+            double v[CSR_U];
+            int32_t c[CSR_U];
+#pragma unroll
+            for (int u = 0; u < CSR_U; ++u) {
+                v[u] = a.val[e[u]];
+                c[u] = a.colind[e[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < CSR_U; ++u) {
+                const bool in = ok[u] && c[u] >= 0 && c[u] < a.n;
+                f(in, c[u], sg[u] ? -v[u] : v[u]);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(64 * CSB_W) void csr_bin_count_kernel(CsrBinArgs a) {
+    extern __shared__ int csb_hist[];  // CSB_W x R
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q = (int64_t)blockIdx.x * CSB_W + w;
+    if (q >= a.L * a.C) return;  // wave-uniform; no workgroup barrier here
+    const int64_t b = q / a.C, ch = q % a.C;
+    int* h = csb_hist + w * a.R;
+    for (int r = lane; r < a.R; r += 64) h[r] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    int p0, p1;
+    csb_chunk_rows(a, b, ch, p0, p1);
+    csb_walk(a, p0, p1, [&](bool in, int32_t c, double) {
+        if (in) __hip_atomic_fetch_add(h + c / a.wr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    });
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int r = lane; r < a.R; r += 64)
+        a.cnt[(b * a.R + r) * a.C + ch] = __hip_atomic_load(h + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// exclusive prefix sum of cnt[0 .. N) in place, cnt[N] = total; one workgroup
+constexpr int CSB_SCAN = 1024;
+__global__ __launch_bounds__(CSB_SCAN) void csr_bin_scan_kernel(int64_t* cnt, int64_t N) {
+    __shared__ int64_t part[CSB_SCAN];
+    const int t = threadIdx.x;
+    const int64_t per = (N + CSB_SCAN - 1) / CSB_SCAN;
+    const int64_t i0 = min(N, (int64_t)t * per), i1 = min(N, i0 + per);
+    int64_t sum = 0;
+    for (int64_t i = i0; i < i1; ++i) sum += cnt[i];
+    part[t] = sum;
+    __syncthreads();
+    // inclusive scan of the per-thread sums (Hillis-Steele)
+    for (int d = 1; d < CSB_SCAN; d <<= 1) {
+        const int64_t x = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += x;
+        __syncthreads();
+    }
+    int64_t run = part[t] - sum;
+    for (int64_t i = i0; i < i1; ++i) {
+        const int64_t c = cnt[i];
+        cnt[i] = run;
+        run += c;
+    }
+    if (t == CSB_SCAN - 1) cnt[N] = part[t];
+}
+
+__global__ __launch_bounds__(64 * CSB_W) void csr_bin_place_kernel(CsrBinArgs a) {
+    extern __shared__ int64_t csb_run[];  // CSB_W x R
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q = (int64_t)blockIdx.x * CSB_W + w;
+    if (q >= a.L * a.C) return;
+    const int64_t b = q / a.C, ch = q % a.C;
+    int64_t* o = csb_run + w * a.R;
+    for (int r = lane; r < a.R; r += 64) o[r] = a.cnt[(b * a.R + r) * a.C + ch];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));  // lanes below this one
+    int p0, p1;
+    csb_chunk_rows(a, b, ch, p0, p1);
+    csb_walk(a, p0, p1, [&](bool in, int32_t c, double x) {
+        const int rg = in ? c / (int)a.wr : 0;
+        // lanes holding an entry of the same range: one ballot per range bit
+        uint64_t peers = __ballot(in);
+        for (int bit = 0; bit < a.rbits; ++bit) {
+            const bool on = (rg >> bit) & 1;
+            const uint64_t mset = __ballot(on);
+            peers &= on ? mset : ~mset;
+        }
+        if (in) {
+            const int rank = __popcll(peers & lt);
+            const int64_t base = __hip_atomic_load(o + rg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            const int64_t dst = base + rank;
+            if (rank == 0)
+                __hip_atomic_store(o + rg, base + __popcll(peers), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            if (dst < a.nnz_cap) {
+                a.bcol[dst] = c;
+                a.bval[dst] = x;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    });
+}
+
+__global__ __launch_bounds__(64 * CSD_W) void csr_bin_sum_kernel(CsrBinArgs a) {
+    __shared__ double acc[CSD_W][CSB_WR];
+    __shared__ int tag[CSD_W][CSD_SLOTS];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t q = (int64_t)blockIdx.x * CSD_W + w;
+    if (q >= a.L * a.R) return;
+    const int64_t b = q / a.R, r = q % a.R;
+    const int64_t c0 = r * a.wr, c1 = min(a.n, c0 + a.wr);
+    double* my = acc[w];
+    int* tg = tag[w];
+    for (int64_t j = lane; j < c1 - c0; j += 64) __hip_atomic_store(my + j, 0.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    for (int s2 = lane; s2 < CSD_SLOTS; s2 += 64) __hip_atomic_store(tg + s2, 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    wave_fence();
+    const int64_t e0 = a.cnt[q * a.C], e1 = min(a.cnt[(q + 1) * a.C], a.nnz_cap);
+    for (int64_t B = e0; B < e1; B += 64 * CSR_U) {
+        int32_t c[CSR_U];
+        double x[CSR_U];
+        bool ok[CSR_U];
+#pragma unroll
+        for (int u = 0; u < CSR_U; ++u) {
+            const int64_t e = B + 64 * u + lane;
+            ok[u] = e < e1;
+            c[u] = ok[u] ? a.bcol[e] : (int32_t)c0;
+            x[u] = ok[u] ? a.bval[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < CSR_U; ++u) {
+            bool pend = ok[u] && c[u] >= c0 && c[u] < c1;
+            const int slot = c[u] & (CSD_SLOTS - 1);
+            double* dst = my + (pend ? c[u] - c0 : 0);
+            while (__ballot(pend)) {
+                if (pend) __hip_atomic_fetch_min(tg + slot, lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                wave_fence();
+                const bool go = pend && __hip_atomic_load(tg + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == lane;
+                if (go) {
+                    const double y = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    __hip_atomic_store(dst, y + x[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                }
+                if (pend) __hip_atomic_store(tg + slot, 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                wave_fence();
+                pend = pend && !go;
+            }
+        }
+    }
+    for (int64_t j = c0 + lane; j < c1; j += 64)
+        a.Y[b * a.rs + j * a.cs] = __hip_atomic_load(my + (j - c0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+static ids_status cs_csr_binned(const int64_t* rowptr, const int32_t* colind, const double* val, int64_t m,
+                                int64_t n, int64_t nnz, const PlanBufs& pb, int64_t L, double* Y, int64_t rs,
+                                int64_t cs, char* ws, hipStream_t st) {
+    const CsrBinShape sh = csr_bin_shape(m, n, nnz, L);
+    CsrBinArgs a;
+    a.rowptr = rowptr;
+    a.colind = colind;
+    a.val = val;
+    a.m = m;
+    a.n = n;
+    a.nnz_cap = std::max<int64_t>(nnz, 0);
+    a.off = (const int32_t*)pb.off;
+    a.rows = (const int32_t*)pb.rows;
+    a.L = L;
+    a.R = sh.R;
+    a.C = sh.C;
+    a.wr = sh.wr;
+    a.rbits = 0;
+    while ((int64_t(1) << a.rbits) < sh.R) ++a.rbits;
+    a.cnt = (int64_t*)ws;
+    a.bcol = (int32_t*)(ws + sh.cnt_b);
+    a.bval = (double*)(ws + sh.cnt_b + sh.col_b);
+    a.Y = Y;
+    a.rs = rs;
+    a.cs = cs;
+    const unsigned gw = (unsigned)((L * sh.C + CSB_W - 1) / CSB_W);
+    hipLaunchKernelGGL(csr_bin_count_kernel, dim3(gw), dim3(64 * CSB_W), sizeof(int) * CSB_W * sh.R, st, a);
+    hipLaunchKernelGGL(csr_bin_scan_kernel, dim3(1), dim3(CSB_SCAN), 0, st, a.cnt, sh.ncnt);
+    hipLaunchKernelGGL(csr_bin_place_kernel, dim3(gw), dim3(64 * CSB_W), sizeof(int64_t) * CSB_W * sh.R, st, a);
+    hipLaunchKernelGGL(csr_bin_sum_kernel, dim3((unsigned)((L * sh.R + CSD_W - 1) / CSD_W)), dim3(64 * CSD_W), 0,
+                       st, a);
+    return check_launch("countsketch csr (ordered, binned)");
+}
+
 // bucket index of every position of the plan's row list
 __global__ void plan_bucket_of_pos_kernel(const int32_t* off, int64_t L, int32_t* bop) {
     const int b = blockIdx.x;
@@ -853,7 +1121,11 @@ __global__ void fill_f64_kernel(double* y, int64_t rows, int64_t cols, int64_t r
 
 ids_status cs_csr(const int64_t* rowptr, const int32_t* colind, const double* val, int64_t m, int64_t n,
                   const PlanBufs& pb, int64_t L, double* Y, int64_t rs, int64_t cs, int32_t* scratch_bop,
-                  bool ordered, hipStream_t st) {
+                  bool ordered, int64_t nnz, char* bin_ws, hipStream_t st) {
+    // the binned form unless the shape is too wide for it or the cs.csr.bin
+    // knob selects the unbinned kernel (same results)
+    if (ordered && bin_ws && csr_bin_bytes(m, n, nnz, L) > 0 && tune_get("cs.csr.bin", 1))
+        return cs_csr_binned(rowptr, colind, val, m, n, nnz, pb, L, Y, rs, cs, bin_ws, st);
     if (ordered) {
         // column ranges of at most CSD_WR, CSD_W of them per workgroup
         const int64_t nr = (n + CSD_WR - 1) / CSD_WR;

@@ -50,7 +50,10 @@ ids_status cs_dense(int32_t dtype, int32_t acc, const void* A, int64_t lda, int6
                     int64_t L, void* Y, int64_t rs, int64_t cs, hipStream_t st);
 ids_status cs_csr(const int64_t* rowptr, const int32_t* colind, const double* val, int64_t m, int64_t n,
                   const PlanBufs& pb, int64_t L, double* Y, int64_t rs, int64_t cs, int32_t* scratch_bop,
-                  bool ordered, hipStream_t st);
+                  bool ordered, int64_t nnz, char* bin_ws, hipStream_t st);
+// workspace of the binned ordered CSR sketch (0: shape too wide, the unbinned
+// ordered kernel runs instead)
+size_t csr_bin_bytes(int64_t m, int64_t n, int64_t nnz, int64_t L);
 
 // ---- projection GEMM (MFMA): Y(col-major, ldy) = G (l x q) * Y1 (q x n, ld1) --
 ids_status project(int32_t dtype, int64_t l, int64_t q, int64_t n, const void* G, const void* Y1, int64_t ld1,

@@ -36,12 +36,12 @@ MARGIN = 0.03   # a knob leaves its hand-picked value only for a gain above this
 
 HAND_DEFAULTS = {f"select.gl.{lb}.{nb}": 0 for lb in L_BUCKETS for nb in N_BUCKETS}
 HAND_DEFAULTS.update({"trsm.k32": 1, "trsm.k64": 2, "trsm.k128": 4, "batched.rl512": 36, "batched.rl256": 36,
-                      "project.wgs": 256, "cs.dense.wpc": 0, "select.steps": 0})
+                      "project.wgs": 256, "cs.dense.wpc": 0, "select.steps": 0, "cs.csr.bin": 1})
 
 CANDIDATES = {f"select.gl.{lb}.{nb}": [0, 1] for lb in L_BUCKETS for nb in N_BUCKETS}
 CANDIDATES.update({"trsm.k32": [1, 2, 4], "trsm.k64": [2, 4], "trsm.k128": [4, 8],
                    "batched.rl512": [36, 0], "batched.rl256": [36, 0], "project.wgs": [128, 256, 512, 1024],
-                   "cs.dense.wpc": [0, 2, 3, 4], "select.steps": [0]})
+                   "cs.dense.wpc": [0, 2, 3, 4], "select.steps": [0], "cs.csr.bin": [1]})
 
 
 def _timed(torch, fn, reps: int) -> float:

@@ -21,8 +21,18 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
+@pytest.fixture(params=[1, 0], ids=["binned", "unbinned"])
+def path(request):
+    # cs.csr.bin selects the binned ordered kernels (1) or the unbinned one
+    # (0, the form wide matrices take); both must give the same bits
+    ids.tune_set("cs.csr.bin", request.param)
+    yield request.param
+    ids.tune_set("cs.csr.bin", -1)
+
+
 def sketch(rp, ci, v, n, L, seed, **kw):
-    print(f"ordered csr sketch m={rp.size - 1} n={n} nnz={ci.size} L={L} seed={seed}", flush=True)
+    print(f"ordered csr sketch m={rp.size - 1} n={n} nnz={ci.size} L={L} seed={seed} "
+          f"binned={ids.tune_get('cs.csr.bin')}", flush=True)
     return ids.id_sketch((dev(rp), dev(ci), dev(v), n), L, seed=seed, deterministic=True, **kw).cpu().numpy()
 
 
@@ -30,7 +40,7 @@ def sketch(rp, ci, v, n, L, seed, **kw):
 # L = 1 makes one bucket hold every row
 @pytest.mark.parametrize("m,n,L", [(2000, 300, 40), (20000, 1500, 240), (777, 21000, 16), (3000, 40000, 7),
                                    (5000, 64, 1), (1, 1, 1)])
-def test_ordered_csr_bit_exact(m, n, L):
+def test_ordered_csr_bit_exact(m, n, L, path):
     rp, ci, v = synth.csr_zipf(m=m, n=n, seed=2, kmax=min(681, n), rank=min(5, n), nplant_rows=min(200, m),
                                nplant_cols=min(100, n))
     Y = sketch(rp, ci, v, n, L, seed=4)
@@ -38,7 +48,7 @@ def test_ordered_csr_bit_exact(m, n, L):
     assert np.array_equal(Y, oracle.countsketch_csr(rp, ci, v, n, b, s, L))
 
 
-def test_ordered_csr_duplicates_unsorted_empty_and_long_rows():
+def test_ordered_csr_duplicates_unsorted_empty_and_long_rows(path):
     # unsorted column indices, repeated columns inside a row (several in one
     # 64-entry chunk, so the lane-order rounds run), empty rows and rows much
     # longer than a chunk
@@ -66,7 +76,7 @@ def test_ordered_csr_duplicates_unsorted_empty_and_long_rows():
     assert np.all(np.abs(Ya - Yo) <= 64 * 2.0 ** -52 * absum + 1e-300)
 
 
-def test_ordered_csr_single_entry():
+def test_ordered_csr_single_entry(path):
     m, n, L = 1000, 50, 9
     rp = np.zeros(m + 1, dtype=np.int64)
     rp[318:] = 1
@@ -79,7 +89,7 @@ def test_ordered_csr_single_entry():
     assert np.array_equal(Y, Yo)
 
 
-def test_ordered_matrix_id_repeats_bitwise_and_matches_oracle():
+def test_ordered_matrix_id_repeats_bitwise_and_matches_oracle(path):
     rp, ci, v = synth.csr_zipf(m=20000, n=2000, seed=3, rank=20, nplant_rows=2000, nplant_cols=300)
     A = (dev(rp), dev(ci), dev(v), 2000)
     k, l1 = 20, 120
