@@ -854,7 +854,7 @@ __global__ __launch_bounds__(64 * CSD_W) void cs_csr_ordered_kernel(const int64_
 //      into its columns' LDS sums in that order (entries of one 64-entry
 //      chunk that share a column in lane order, as in the unbinned kernel)
 //      and writes row b of Y1 for those columns.
-constexpr int CSB_WR = 2048;         // columns per range
+constexpr int CSB_WR = 1024;         // columns per range (4 workgroups of the summing pass per CU)
 constexpr int CSB_RMAX = 4096;       // ranges (LDS counters per wave)
 constexpr int CSB_ROWS = 256;        // rows per (bucket, chunk) walk, about
 constexpr int64_t CSB_CNT_MAX = int64_t(1) << 24;  // counters (L R C)
@@ -961,30 +961,40 @@ __global__ __launch_bounds__(64 * CSB_W) void csr_bin_count_kernel(CsrBinArgs a)
 }
 
 // exclusive prefix sum of cnt[0 .. N) in place, cnt[N] = total; one workgroup
+// walks tiles of CSB_SCAN * 8 counters (8 consecutive per thread, so the loads
+// are coalesced), scanned through the waves and carried from tile to tile
 constexpr int CSB_SCAN = 1024;
+constexpr int CSB_SCAN_ITEMS = 8;
 __global__ __launch_bounds__(CSB_SCAN) void csr_bin_scan_kernel(int64_t* cnt, int64_t N) {
-    __shared__ int64_t part[CSB_SCAN];
-    const int t = threadIdx.x;
-    const int64_t per = (N + CSB_SCAN - 1) / CSB_SCAN;
-    const int64_t i0 = min(N, (int64_t)t * per), i1 = min(N, i0 + per);
-    int64_t sum = 0;
-    for (int64_t i = i0; i < i1; ++i) sum += cnt[i];
-    part[t] = sum;
+    __shared__ int64_t wtot[CSB_SCAN / 64];
+    __shared__ int64_t s_carry;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (t == 0) s_carry = 0;
     __syncthreads();
-    // inclusive scan of the per-thread sums (Hillis-Steele)
-    for (int d = 1; d < CSB_SCAN; d <<= 1) {
-        const int64_t x = t >= d ? part[t - d] : 0;
+    for (int64_t base = 0; base < N; base += (int64_t)CSB_SCAN * CSB_SCAN_ITEMS) {
+        const int64_t i0 = base + (int64_t)t * CSB_SCAN_ITEMS;
+        int64_t v[CSB_SCAN_ITEMS];
+#pragma unroll
+        for (int q = 0; q < CSB_SCAN_ITEMS; ++q) v[q] = (i0 + q < N) ? cnt[i0 + q] : 0;
+        int64_t mine = 0;
+#pragma unroll
+        for (int q = 0; q < CSB_SCAN_ITEMS; ++q) mine += v[q];
+        const int64_t inc = wave_incl_scan(mine);
+        if (lane == 63) wtot[w] = inc;
         __syncthreads();
-        part[t] += x;
+        int64_t before = s_carry;  // this tile's start
+        for (int q = 0; q < w; ++q) before += wtot[q];
+        int64_t run = before + inc - mine;  // exclusive start of this thread's items
+#pragma unroll
+        for (int q = 0; q < CSB_SCAN_ITEMS; ++q) {
+            if (i0 + q < N) cnt[i0 + q] = run;
+            run += v[q];
+        }
+        __syncthreads();  // every thread has read s_carry and wtot
+        if (t == CSB_SCAN - 1) s_carry = run;  // the last thread's end = the tile's end
         __syncthreads();
     }
-    int64_t run = part[t] - sum;
-    for (int64_t i = i0; i < i1; ++i) {
-        const int64_t c = cnt[i];
-        cnt[i] = run;
-        run += c;
-    }
-    if (t == CSB_SCAN - 1) cnt[N] = part[t];
+    if (t == 0) cnt[N] = s_carry;
 }
 
 __global__ __launch_bounds__(64 * CSB_W) void csr_bin_place_kernel(CsrBinArgs a) {
