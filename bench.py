@@ -234,6 +234,26 @@ def measured_read_gbps(ids, torch, buf, reps: int = 10) -> float:
     return buf.numel() * buf.element_size() / sec / 1e9
 
 
+def measured_gemm_tflops(torch, dtype, n: int, reps: int = 10) -> float:
+    """Dense GEMM rate the platform library (torch.matmul on rocBLAS /
+    hipBLASLt) reaches on an n x n x n product here: the practical matrix-core
+    ceiling for that type, beside the datasheet peak."""
+    a = torch.randn(n, n, device="cuda", dtype=torch.float32).to(dtype)
+    b = torch.randn(n, n, device="cuda", dtype=torch.float32).to(dtype)
+    for _ in range(3):
+        c = torch.matmul(a, b)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        c = torch.matmul(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    del a, b, c
+    return 2.0 * n ** 3 / (e0.elapsed_time(e1) / 1e3 / reps) / 1e12
+
+
 def concurrent_ids(ids, torch, At, Gt, l1: int, l: int, steps: int, J_ref, nstreams: int = 3):
     """Independent IDs of the same input issued round-robin on `nstreams`
     streams (each call has its own workspace and outputs): one ID's pivoted QR,
@@ -589,6 +609,23 @@ def gaussian_baseline(ids, torch, At, Omega, cs_ms: float, steps: int = 10, A64=
                            "algorithmic_flops": flops},
            "countsketch_id_speedup": ms / cs_ms,
            "note": f"same GPU, same CPQR and solve; FP32 Gaussian sketch Omega A with l = {l}"}
+    # the platform library on the same product (torch.matmul, FP32, TF32 off)
+    for _ in range(3):
+        ref = torch.matmul(Om, At)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        ref = torch.matmul(Om, At)
+    e1.record()
+    torch.cuda.synchronize()
+    lib_ms = e0.elapsed_time(e1) / steps
+    del ref
+    lib_tf = flops / (lib_ms / 1e3) / 1e12
+    out["sketch_mfma"]["library_same_shape"] = {"ms": lib_ms, "TFLOPs": lib_tf, "ours_over_library": tf / lib_tf}
+    # the comparison with the faster of the two Gaussian sketches
+    out["countsketch_id_speedup_vs_library_sketch"] = (ms - st["gaussian_sketch"] + min(lib_ms, st["gaussian_sketch"])) / cs_ms
     if A64 is not None:
         import oracle
         r = ids.gaussian_id(At, K, Om)
@@ -797,10 +834,22 @@ def main():
         res_o = oracle.residual_fro(A64, oracle_out["J"], oracle_out["P"])
         out["residual"] = {"gpu": res_g, "oracle_f64": res_o, "ratio": res_g / res_o,
                            "J_overlap": int(len(set(Jg.tolist()) & set(oracle_out["J"].tolist())))}
+    # measured matrix-core ceilings (library GEMMs) beside the datasheet peaks
+    torch.backends.cuda.matmul.allow_tf32 = False
+    gemm = {"f32": measured_gemm_tflops(torch, torch.float32, 8192),
+            "bf16": measured_gemm_tflops(torch, torch.bfloat16, 8192),
+            "f64": measured_gemm_tflops(torch, torch.float64, 4096)}
+    out["measured_peaks"] = {
+        "hbm_read_GBps": read_gbps, "gemm_TFLOPs": gemm,
+        "datasheet": {"hbm_GBps": HBM_PEAK_GBPS, "f32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0, "f64_TFLOPs": 78.6},
+        "note": "read: ids_stream_read of the 1.6 GB input; GEMM: torch.matmul (rocBLAS / hipBLASLt), "
+                "8192^3 (FP32, BF16) and 4096^3 (FP64), TF32 off"}
     if Omega is not None:
         print("[bench] Gaussian-sketch ID baseline on the same input", flush=True)
         out["gaussian_baseline"] = gaussian_baseline(ids, torch, At, Omega, ms_per_step,
                                                      A64=None if args.no_check else A64)
+        sk = out["gaussian_baseline"]["sketch_mfma"]
+        sk["frac_of_measured_f32_gemm"] = sk["achieved"] / gemm["f32"]
         del Omega
     if not args.no_others:
         print("[bench] other workloads (dense 2000x1000, CSR 1e6x2e4, tensors)", flush=True)
