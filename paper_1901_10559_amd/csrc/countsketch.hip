@@ -775,6 +775,27 @@ constexpr int CSD_SLOTS = 256;
 
 __device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
+// *dst += x for the lanes with pend set (one 64-entry chunk), lanes that share
+// a column added in lane order: each round, the lowest pending lane of every
+// tag slot (slot = column mod CSD_SLOTS; tg holds the wave's CSD_SLOTS slots,
+// 64 = free, and is left free) adds its entry and leaves
+__device__ __forceinline__ void ordered_add(bool pend, int col, double* dst, double x, int* tg) {
+    const int lane = threadIdx.x & 63;
+    const int slot = col & (CSD_SLOTS - 1);
+    while (__ballot(pend)) {
+        if (pend) __hip_atomic_fetch_min(tg + slot, lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        wave_fence();
+        const bool go = pend && __hip_atomic_load(tg + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == lane;
+        if (go) {
+            const double y = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            __hip_atomic_store(dst, y + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+        if (pend) __hip_atomic_store(tg + slot, 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        wave_fence();
+        pend = pend && !go;
+    }
+}
+
 __global__ __launch_bounds__(64 * CSD_W) void cs_csr_ordered_kernel(const int64_t* __restrict__ rowptr,
                                                                     const int32_t* __restrict__ colind,
                                                                     const double* __restrict__ val, int64_t m,
@@ -814,22 +835,8 @@ __global__ __launch_bounds__(64 * CSD_W) void cs_csr_ordered_kernel(const int64_
             }
 #pragma unroll
             for (int u = 0; u < CSR_U; ++u) {
-                bool pend = ok[u] && c[u] >= c0 && c[u] < c1;
-                const double x = sg[u] ? -v[u] : v[u];
-                const int slot = c[u] & (CSD_SLOTS - 1);
-                double* dst = my + (pend ? c[u] - c0 : 0);
-                while (__ballot(pend)) {
-                    if (pend) __hip_atomic_fetch_min(tg + slot, lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                    wave_fence();
-                    const bool go = pend && __hip_atomic_load(tg + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == lane;
-                    if (go) {
-                        const double y = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                        __hip_atomic_store(dst, y + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                    }
-                    if (pend) __hip_atomic_store(tg + slot, 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                    wave_fence();
-                    pend = pend && !go;
-                }
+                const bool in = ok[u] && c[u] >= c0 && c[u] < c1;
+                ordered_add(in, c[u], my + (in ? c[u] - c0 : 0), sg[u] ? -v[u] : v[u], tg);
             }
         }
     }
@@ -1060,21 +1067,8 @@ __global__ __launch_bounds__(64 * CSD_W) void csr_bin_sum_kernel(CsrBinArgs a) {
         }
 #pragma unroll
         for (int u = 0; u < CSR_U; ++u) {
-            bool pend = ok[u] && c[u] >= c0 && c[u] < c1;
-            const int slot = c[u] & (CSD_SLOTS - 1);
-            double* dst = my + (pend ? c[u] - c0 : 0);
-            while (__ballot(pend)) {
-                if (pend) __hip_atomic_fetch_min(tg + slot, lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                wave_fence();
-                const bool go = pend && __hip_atomic_load(tg + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == lane;
-                if (go) {
-                    const double y = __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                    __hip_atomic_store(dst, y + x[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                }
-                if (pend) __hip_atomic_store(tg + slot, 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                wave_fence();
-                pend = pend && !go;
-            }
+            const bool in = ok[u] && c[u] >= c0 && c[u] < c1;
+            ordered_add(in, c[u], my + (in ? c[u] - c0 : 0), x[u], tg);
         }
     }
     for (int64_t j = c0 + lane; j < c1; j += 64)

@@ -38,8 +38,9 @@ def sketch(rp, ci, v, n, L, seed, **kw):
 
 # n > 8192 puts several column ranges on a bucket (and several workgroups);
 # L = 1 makes one bucket hold every row
+# (200000, 20000, 64): 64 x 20 x 13 = 16640 counters, two tiles of the counter scan
 @pytest.mark.parametrize("m,n,L", [(2000, 300, 40), (20000, 1500, 240), (777, 21000, 16), (3000, 40000, 7),
-                                   (5000, 64, 1), (1, 1, 1)])
+                                   (5000, 64, 1), (1, 1, 1), (200000, 20000, 64)])
 def test_ordered_csr_bit_exact(m, n, L, path):
     rp, ci, v = synth.csr_zipf(m=m, n=n, seed=2, kmax=min(681, n), rank=min(5, n), nplant_rows=min(200, m),
                                nplant_cols=min(100, n))

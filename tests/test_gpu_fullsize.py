@@ -81,6 +81,18 @@ def test_csr_matrix_id_1e6x2e4_fp64_parity():
     assert np.array_equal(Pg[:, Jg], np.eye(k))
 
 
+def test_csr_ordered_sketch_1e6x2e4_bit_exact():
+    # IDS_DETERMINISTIC at the CSR workload's full size (240 buckets x 20
+    # column ranges x 17 row chunks = 81600 counters, ten tiles of the counter
+    # scan): the sketch equals the oracle's row-order sums bit for bit
+    rp, ci, v = synth.csr_zipf()
+    A = (dev(rp), dev(ci), dev(v), 20000)
+    print("ordered CSR sketch 1e6 x 2e4, l1 = 240", flush=True)
+    Y = ids.id_sketch(A, 240, seed=0, deterministic=True).cpu().numpy()
+    b, s = oracle.hash_maps(0, 0, rp.size - 1, 240)
+    assert np.array_equal(Y, oracle.countsketch_csr(rp, ci, v, 20000, b, s, 240))
+
+
 def test_tensor_id_2000cubed_R2000_J4096():
     # Algorithm 3 at full size against the oracle's Algorithm 3: the whole
     # 4096 x 2000 sketch (direct circular convolutions, columns over a process
