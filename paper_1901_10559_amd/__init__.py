@@ -351,7 +351,9 @@ def gaussian_sketch(A, Omega, stream=None):
 
 
 def _status(torch, device, n: int = 1):
-    return torch.full((n,), -1, dtype=torch.int32, device=device)
+    # every call path writes its status word(s) on the call's stream, so no
+    # fill (which would run on torch's current stream) precedes it
+    return torch.empty((n,), dtype=torch.int32, device=device)
 
 
 def gaussian_id(A, k: int, Omega, stream=None):
