@@ -14,8 +14,10 @@
 //       recomputed in FP64 each step.
 //   With tol > 0 (fixed-accuracy ID) problem p stops at the first step t with
 //   |r_tt| <= tol |r_11| and returns k_eff_p = t (its adaptive rank).
-//   batched_trsm_kernel    one workgroup per problem: R11 in LDS, FP64
-//       axpy back-substitution, up to 4 lanes per column; writes P_p.
+//   batched_solve_kernel   one workgroup per problem: the interpolation
+//       matrix P_p by FP64 block back-substitution on the matrix cores
+//       (R11 blocks and their inverses in LDS), 16 consecutive columns of P_p
+//       per wave at a time.
 // Problem p draws its CountSketch from the stream (seed, tag = p) and uses
 // the first l1_p = min(m_p, l1max) columns of the shared l x l1max G.
 #include <algorithm>
@@ -708,15 +710,16 @@ __global__ __launch_bounds__(NT, RL ? 4 : 2) void batched_cpqr_kernel(BatchArgs 
 // pivot columns (Rt).  The workgroup stages the blocks R_il (l > i, negated)
 // and the inverses of the 16 x 16 diagonal blocks (back-substitution, one
 // thread per column) in LDS, every block column-major so that the MFMA A
-// operand of K slice q is the 64 consecutive doubles 64 q .. 64 q + 63.  The
-// non-pivot columns are gathered into a list; each wave then solves whole
-// 16-column tiles of that list on its own (no barrier): the tile's nb
+// operand of K slice q is the 64 consecutive doubles 64 q .. 64 q + 63.  Each
+// wave then takes tiles of 16 consecutive columns of P_p on its own (no
+// barrier), so its stores write whole 128-byte row segments: the tile's nb
 // accumulators stay in registers, v_mfma_f64_16x16x4f64 forms every product
 // (4 K slices per block), and since the FP64 result layout (register r: row
 // 4 r + lane / 16, column lane % 16) is the B operand layout of K slice r, a
 // solved block T_l feeds the later products without any exchange.  Columns
 // are independent in every product, so a column's result does not depend on
-// the tile it lands in.  Pivot column J[t] gets e_t exactly.
+// the tile it lands in; a pivot column J[t] in the tile gets e_t exactly
+// (its right-hand side is not loaded).  Two waves per SIMD (256 VGPRs).
 constexpr int BT_THREADS = 256;
 constexpr int BT_NBMAX = 8;  // 16-row blocks (k <= 128)
 typedef double v4f64 __attribute__((ext_vector_type(4)));
@@ -728,11 +731,9 @@ size_t batched_solve_lds(int64_t k) {
     return sizeof(double) * 256 * (size_t)(nb * (nb + 1) / 2);
 }
 
-__global__ __launch_bounds__(BT_THREADS) void batched_solve_kernel(BatchArgs a) {
+__global__ __launch_bounds__(BT_THREADS, 2) void batched_solve_kernel(BatchArgs a) {
     extern __shared__ __attribute__((aligned(16))) double blk[];  // nb (nb + 1) / 2 blocks of 256
     __shared__ int32_t Js[16 * BT_NBMAX];
-    __shared__ int16_t cl[1024];   // non-pivot columns
-    __shared__ int ncl;
     const int p = a.order[blockIdx.x];
     const BProb pr = a.prob[p];
     const int n = pr.n, k = (int)a.k;
@@ -744,11 +745,8 @@ __global__ __launch_bounds__(BT_THREADS) void batched_solve_kernel(BatchArgs a) 
     const double* Rt = a.Rt + pr.r_off * (int64_t)k;
     const int32_t* pos = a.pos + pr.r_off;
     double* P = a.P + pr.p_off;
-    if (tid == 0) ncl = 0;
     for (int t = tid; t < 16 * nb; t += BT_THREADS) Js[t] = t < keff ? (int32_t)J[t] : 0;
     __syncthreads();
-    for (int j = tid; j < n; j += BT_THREADS)
-        if (pos[j] < 0) cl[atomicAdd(&ncl, 1)] = (int16_t)j;
     // R11 blocks: element (m, kk) of block (i, l) = R11[16 i + m][16 l + kk] at
     // kk * 16 + m; thread tid holds element (tid & 15, tid >> 4) of every
     // block, and the loads of 8 blocks are issued before any is stored
@@ -807,21 +805,22 @@ __global__ __launch_bounds__(BT_THREADS) void batched_solve_kernel(BatchArgs a) 
         }
     }
     __syncthreads();
-    // pivot columns: P[:, J[t]] = e_t
-    for (int e = tid; e < keff * k; e += BT_THREADS) {
-        const int t = e / k, row = e - t * k;
-        P[(int64_t)row * n + Js[t]] = (row == t) ? 1.0 : 0.0;
-    }
-    const int m_cl = ncl, col = lane & 15, rq = lane >> 4;
-    for (int t0 = 16 * w; t0 < m_cl; t0 += 16 * (BT_THREADS / 64)) {
+    // tiles of 16 consecutive columns, so every store below writes four
+    // contiguous 128-byte row segments of P: a non-pivot column's lane solves
+    // R11 x = R[0:keff, j]; a pivot column's lane (chosen at step t) writes e_t
+    const int col = lane & 15, rq = lane >> 4;
+    for (int t0 = 16 * w; t0 < n; t0 += 16 * (BT_THREADS / 64)) {
         const int jj = t0 + col;
-        const int j = cl[min(jj, m_cl - 1)];
+        const int j = min(jj, n - 1);
+        const int pj = pos[j];
         v4f64 acc[BT_NBMAX];
-        // right-hand sides R[0:keff, j] (clamped loads, all in flight, then masked)
+        // right-hand sides R[0:keff, j] (clamped loads, all in flight, then
+        // masked); pivot columns load nothing
 #pragma unroll
         for (int i = 0; i < BT_NBMAX; ++i)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[i][r] = Rt[(int64_t)j * k + min(16 * i + 4 * r + rq, max(keff - 1, 0))];
+            for (int r = 0; r < 4; ++r)
+                acc[i][r] = (pj < 0) ? Rt[(int64_t)j * k + min(16 * i + 4 * r + rq, max(keff - 1, 0))] : 0.0;
         asm volatile("" ::: "memory");
 #pragma unroll
         for (int i = 0; i < BT_NBMAX; ++i)
@@ -843,13 +842,14 @@ __global__ __launch_bounds__(BT_THREADS) void batched_solve_kernel(BatchArgs a) 
             for (int q = 0; q < 4; ++q) x = __builtin_amdgcn_mfma_f64_16x16x4f64(Di[64 * q + lane], acc[i][q], x, 0, 0, 0);
             acc[i] = x;
         }
-        if (jj < m_cl) {
+        if (jj < n) {
 #pragma unroll
             for (int i = 0; i < BT_NBMAX; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = 16 * i + 4 * r + rq;
-                    if (row < k) P[(int64_t)row * n + j] = (row < keff) ? acc[i][r] : 0.0;
+                    if (row < k)
+                        P[(int64_t)row * n + j] = (pj >= 0) ? (row == pj ? 1.0 : 0.0) : (row < keff ? acc[i][r] : 0.0);
                 }
         }
     }
