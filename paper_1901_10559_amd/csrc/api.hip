@@ -59,6 +59,7 @@ static bool tune_valid(const std::string& key, int64_t v) {
     if (key == "cs.dense.wpc") return v == 0 || (v >= 2 && v <= 8);
     if (key == "select.steps") return v == 0 || v == 1;
     if (key == "cs.csr.bin") return v == 0 || v == 1;
+    if (key == "trsm.mfma") return v == 0 || v == 1;
     return false;
 }
 static std::mutex g_tune_mu;

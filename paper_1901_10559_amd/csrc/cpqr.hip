@@ -1398,6 +1398,9 @@ static ids_status solve_p(const SelectPlan& sp, const double* Rt, const double* 
     // lanes per column of the solve for k <= 128 (tuned knobs; GQ lanes hold
     // 32 slots each, so GQ = 1, 2, 4 serve k <= 32, 64, 128; 8 is the
     // 16-lane dot-product kernel)
+    // k <= 128: the one-kernel block solve on the FP64 matrix cores (tuned
+    // knob trsm.mfma), else the lane-per-column kernels below
+    if (sp.k <= 128 && tune_get("trsm.mfma", 0)) return solve_mfma_small(sp.n, sp.k, Rt, R11c, pos, keff, P, st);
     const size_t ax = sizeof(double) * (size_t)sp.k * (trsm_ax_ldk<4>() + 1);
     const int64_t gq = sp.k <= 32 ? tune_get("trsm.k32", 1) : sp.k <= 64 ? tune_get("trsm.k64", 2)
                                                                             : tune_get("trsm.k128", 4);

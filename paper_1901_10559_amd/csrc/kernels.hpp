@@ -78,6 +78,8 @@ struct SelectPlan {
 };
 // P from Rt / R11c / pos for large k: blocked back-substitution on the FP64
 // matrix cores, in place in P (solve_blk.hip)
+ids_status solve_mfma_small(int64_t n, int64_t k, const double* Rt, const double* R11c, const int32_t* pos,
+                            const int64_t* keff, double* P, hipStream_t st);  // k <= 128
 ids_status solve_blocked(int64_t n, int64_t k, const double* Rt, const double* R11c, const int32_t* pos,
                          const int64_t* keff, double* P, hipStream_t st);
 // the column-steps factorisation (cpqr_steps.hip): workspace bytes before Rt

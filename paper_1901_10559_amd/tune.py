@@ -36,12 +36,12 @@ MARGIN = 0.03   # a knob leaves its hand-picked value only for a gain above this
 
 HAND_DEFAULTS = {f"select.gl.{lb}.{nb}": 0 for lb in L_BUCKETS for nb in N_BUCKETS}
 HAND_DEFAULTS.update({"trsm.k32": 1, "trsm.k64": 2, "trsm.k128": 4, "batched.rl512": 36, "batched.rl256": 36,
-                      "project.wgs": 256, "cs.dense.wpc": 0, "select.steps": 0, "cs.csr.bin": 1})
+                      "project.wgs": 256, "cs.dense.wpc": 0, "select.steps": 0, "cs.csr.bin": 1, "trsm.mfma": 0})
 
 CANDIDATES = {f"select.gl.{lb}.{nb}": [0, 1] for lb in L_BUCKETS for nb in N_BUCKETS}
 CANDIDATES.update({"trsm.k32": [1, 2, 4], "trsm.k64": [2, 4], "trsm.k128": [4, 8],
                    "batched.rl512": [36, 0], "batched.rl256": [36, 0], "project.wgs": [128, 256, 512, 1024],
-                   "cs.dense.wpc": [0, 2, 3, 4], "select.steps": [0], "cs.csr.bin": [1]})
+                   "cs.dense.wpc": [0, 2, 3, 4], "select.steps": [0], "cs.csr.bin": [1], "trsm.mfma": [0, 1]})
 
 
 def _timed(torch, fn, reps: int) -> float:
@@ -129,6 +129,18 @@ def run(out_dir: str, reps: int = 20) -> dict:
         timings[key] = sweep(ids, torch, key, lambda: ids.id_select(Y, k), reps, stage="trsm")
         print(f"{key}: {timings[key]}", flush=True)
         del Y
+
+    # interpolation-matrix solve for k <= 128: the lane-per-column kernels
+    # (with the lane counts chosen above) against the one-kernel matrix-core
+    # solve, summed over one shape per k bucket
+    per = []
+    for l, n, k in ((30, 2000, 20), (60, 20000, 50), (120, 2000, 100)):
+        Y = torch.from_numpy(g.standard_normal((l, n))).to(dev)
+        per.append(sweep(ids, torch, "trsm.mfma", lambda: ids.id_select(Y, k), reps, stage="trsm"))
+        del Y
+    timings["trsm.mfma"] = {v: (sum(t[v] for t in per) if all(t[v] is not None for t in per) else None)
+                            for v in CANDIDATES["trsm.mfma"]}
+    print(f"trsm.mfma: {per}", flush=True)
 
     # projection K split: the dense FP32 sketch shape (l = 120, l1 = 480, n = 2000)
     A = torch.from_numpy(g.standard_normal((20000, 2000)).astype(np.float32)).to(dev)

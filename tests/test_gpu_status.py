@@ -178,17 +178,22 @@ def test_select_four_wave_variant(l, n, k):
     assert np.linalg.norm(P.cpu().numpy() - Po) <= 1e-10 * np.linalg.norm(Po)
 
 
-@pytest.mark.parametrize("key,value,l,n,k", [("trsm.k32", 2, 30, 700, 20), ("trsm.k32", 4, 30, 700, 20),
-                                             ("trsm.k64", 4, 60, 900, 50), ("trsm.k128", 8, 120, 1500, 100)])
+@pytest.mark.parametrize("key,value,l,n,k", [("trsm.k32", 1, 30, 700, 20), ("trsm.k32", 2, 30, 700, 20),
+                                             ("trsm.k32", 4, 30, 700, 20), ("trsm.k64", 2, 60, 900, 50),
+                                             ("trsm.k64", 4, 60, 900, 50), ("trsm.k128", 4, 120, 1500, 100),
+                                             ("trsm.k128", 8, 120, 1500, 100)])
 def test_solve_variants(key, value, l, n, k):
+    # the lane-per-column solves (trsm.mfma = 0), each lane count
     g = np.random.default_rng(k + value)
     Y = g.standard_normal((l, n))
+    ids.tune_set("trsm.mfma", 0)
     ids.tune_set(key, value)
     try:
         J, P, keff = ids.id_select(dev(Y), k)
         torch.cuda.synchronize()
     finally:
         ids.tune_set(key, None)
+        ids.tune_set("trsm.mfma", None)
     Jo, Po, ko, _, _ = oracle.cpqr_id(Y, k)
     assert np.array_equal(J.cpu().numpy(), Jo)
     assert np.linalg.norm(P.cpu().numpy() - Po) <= 1e-10 * np.linalg.norm(Po)
@@ -239,3 +244,43 @@ def test_select_wide_shape_falls_back_to_four_waves():
     Jo, Po, ko, _, _ = oracle.cpqr_id(Y, k)
     assert np.array_equal(J.cpu().numpy(), Jo)
     assert np.linalg.norm(P.cpu().numpy() - Po) <= 1e-10 * np.linalg.norm(Po)
+
+
+# the one-kernel block solve on the FP64 matrix cores (trsm.mfma = 1): k from
+# 1 to 128, partial blocks, n below one 16-column tile and off a tile
+# boundary, and a rank-deficient sketch (k_eff < k: rows past k_eff zero)
+@pytest.mark.parametrize("l,n,k,rank", [(30, 700, 20, None), (60, 900, 50, None), (120, 1500, 100, None),
+                                        (130, 2001, 128, None), (20, 300, 1, None), (40, 517, 17, None),
+                                        (12, 13, 5, None), (40, 600, 30, 12)])
+def test_solve_matrix_core_variant(l, n, k, rank):
+    g = np.random.default_rng(l + n + k)
+    Y = g.standard_normal((l, n))
+    if rank is not None:
+        # `rank` nonzero columns: the trailing norms are exactly zero after
+        # `rank` steps
+        Y = np.zeros((l, n))
+        Y[:, g.choice(n, rank, replace=False)] = g.standard_normal((l, rank))
+    print(f"matrix-core solve l={l} n={n} k={k} rank={rank}", flush=True)
+    ids.tune_set("trsm.mfma", 1)
+    try:
+        st = torch.full((1,), -1, dtype=torch.int32, device=DEV)
+        J, P, keff = ids.id_select(dev(Y), k, status=st)
+        torch.cuda.synchronize()
+    finally:
+        ids.tune_set("trsm.mfma", None)
+    Jo, Po, ko, _, nu = oracle.cpqr_id(Y, k, trace=True)
+    kg = int(keff.item())
+    assert kg == ko
+    Jg = J.cpu().numpy()
+    Pg = P.cpu().numpy()
+    if rank is None:
+        assert np.array_equal(Jg, Jo)
+        assert np.linalg.norm(Pg - Po) <= 1e-10 * np.linalg.norm(Po)
+        assert np.array_equal(Pg[:, Jo], np.eye(k))
+    else:
+        # k_eff = rank pivots, then rows k_eff.. of P are zero
+        assert kg == rank
+        assert np.array_equal(Jg[:kg], Jo[:ko]) and np.all(Jg[kg:] == -1)
+        assert np.linalg.norm(Pg[:kg] - Po[:ko]) <= 1e-10 * np.linalg.norm(Po[:ko])
+        assert np.all(Pg[kg:] == 0.0)
+        assert np.array_equal(Pg[:kg][:, Jg[:kg]], np.eye(kg))
