@@ -170,7 +170,7 @@ ids_status id_gaussian_sketch(const ids_matrix* A, int64_t l, const void* Omega,
  *   k      1 <= k < n and k <= l; l <= 4096.  Shapes the register-resident
  *          factorisation cannot hold (about 2000-8000 columns for long
  *          sketches, 30000-60000 for short ones) run as column steps
- *          (columns in HBM, two kernels per pivot step; same results).
+ *          (columns in HBM, one kernel per pivot step; same results).
  *   J      int64[k]   chosen columns (entries >= k_eff are set to -1).
  *   P      double[k*n] row-major (rows >= k_eff are zero).
  *   k_eff  int64[1]   number of pivots taken: k unless a zero trailing norm

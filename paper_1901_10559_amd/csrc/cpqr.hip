@@ -1214,7 +1214,7 @@ static size_t cpqr_lds(const SelectPlan& sp, const Inst& in) {
 // co-resident for this n
 static ids_status select_plan_variant(int64_t l, int64_t n, int64_t k, int variant, SelectPlan& sp);
 
-// the column-steps plan (columns in HBM, two kernels per pivot step)
+// the column-steps plan (columns in HBM, one kernel per pivot step)
 static ids_status steps_plan(int64_t l, int64_t n, int64_t k, SelectPlan& sp) {
     if (l > 4096) {
         set_error("id_select: l must be <= 4096");

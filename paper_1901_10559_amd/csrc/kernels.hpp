@@ -74,7 +74,7 @@ struct SelectPlan {
     int64_t RS;             // mailbox doubles per factorisation step
     int64_t CS;             // speculative mode: doubles per set of column slots (two sets)
     int variant;            // kernel variant (tuned knob)
-    int steps = 0;          // 1: columns in HBM, two kernels per pivot step
+    int steps = 0;          // 1: columns in HBM, one kernel per pivot step
 };
 // P from Rt / R11c / pos for large k: blocked back-substitution on the FP64
 // matrix cores, in place in P (solve_blk.hip)

@@ -1,4 +1,4 @@
-"""The column-steps pivoted QR (columns in HBM, two kernels per pivot step):
+"""The column-steps pivoted QR (columns in HBM, one kernel per pivot step):
 taken automatically by shapes too wide for the register-resident
 factorisation, and forced on ordinary shapes with the select.steps knob.
 Parity with the FP64 oracle's Algorithm 1 as for the other kernels."""
