@@ -717,10 +717,11 @@ __global__ __launch_bounds__(CSR_THREADS) void cs_csr_lds_kernel(const int64_t* 
                 v[u] = val[e[u]];
                 c[u] = colind[e[u]];
             }
-            // (3) signed adds into the LDS row
+            // (3) signed adds into the LDS row (a column index outside [0, n)
+            // is dropped rather than written outside the row)
 #pragma unroll
             for (int u = 0; u < CSR_U; ++u)
-                if (ok[u]) atomicAdd(&ybuf[c[u]], sg[u] ? -v[u] : v[u]);
+                if (ok[u] && (uint32_t)c[u] < (uint32_t)n) atomicAdd(&ybuf[c[u]], sg[u] ? -v[u] : v[u]);
         }
         bi = bn;
         code = code_n;

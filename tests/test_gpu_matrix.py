@@ -98,7 +98,8 @@ def test_countsketch_fullrank_hash():
     assert np.array_equal(Y, oracle.countsketch_dense(A, b, s, L))
 
 
-@pytest.mark.parametrize("m,n,L", [(2000, 300, 40), (20000, 1500, 240), (777, 21000, 16)])
+# n = 21000 and 200000: rows wider than LDS, summed with global atomics
+@pytest.mark.parametrize("m,n,L", [(2000, 300, 40), (20000, 1500, 240), (777, 21000, 16), (2000, 200000, 16)])
 def test_countsketch_csr(m, n, L):
     rp, ci, v = synth.csr_zipf(m=m, n=n, seed=1, kmax=min(681, n), rank=5, nplant_rows=min(200, m),
                                nplant_cols=min(100, n))
