@@ -15,7 +15,11 @@
 //      the accumulation type is FP64).
 //   3. CSR: workgroup (bucket, row chunk) scatters the stored entries of its
 //      rows into an LDS copy of the bucket's Y1 row (FP64 LDS atomics), then
-//      adds it to Y1 in HBM.
+//      adds it to Y1 in HBM (rows wider than LDS: global atomics).
+//   4. CSR with IDS_DETERMINISTIC: the entries are binned stably by (bucket,
+//      column range) and each range's sums are formed in row order, entries
+//      sharing a column in lane order -- the definition's order, so the FP64
+//      result equals a sequential evaluation bit for bit.
 #include <algorithm>
 #include "common.hpp"
 #include "kernels.hpp"
