@@ -120,3 +120,14 @@ def test_tune_knobs_without_gpu():
     for key, val in tune.HAND_DEFAULTS.items():
         assert L.ids_tune_get(key.encode(), ct.byref(v)) == 0, key
         assert val in tune.CANDIDATES[key]
+    # the compiled table holds exactly the tuner's knobs, each at a value the
+    # knob accepts
+    import os
+    import re
+    inc = open(os.path.join(os.path.dirname(tune.__file__), "csrc", "tuned_table.inc")).read()
+    table = {k: int(x) for k, x in re.findall(r'\{"([^"]+)", (-?\d+)\}', inc)}
+    assert set(table) == set(tune.HAND_DEFAULTS)
+    for key, val in table.items():
+        assert L.ids_tune_set(key.encode(), val) == 0, key
+        assert L.ids_tune_get(key.encode(), ct.byref(v)) == 0 and v.value == val
+        assert L.ids_tune_set(key.encode(), -1) == 0
