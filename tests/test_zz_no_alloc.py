@@ -56,6 +56,26 @@ def test_noalloc_row_band_then_small():
         assert np.array_equal(P1.cpu().numpy(), P0.cpu().numpy())
 
 
+def test_noalloc_column_steps_then_small():
+    # the column-steps factorisation (forced by the select.steps knob) with its
+    # working copy, partials and counters in the static buffer; the second
+    # call smaller
+    g = np.random.default_rng(13)
+    ids.tune_set("select.steps", 1)
+    try:
+        for (l, n, k) in [(120, 2000, 100), (40, 700, 25)]:
+            Y = torch.from_numpy(g.standard_normal((l, n))).to(DEV)
+            print(f"noalloc column steps: l={l} n={n} k={k}", flush=True)
+            J0, P0, k0 = ids.id_select(Y, k)
+            J1, P1, k1, st = run_noalloc(Y, k)
+            torch.cuda.synchronize()
+            assert int(k1.item()) == int(k0.item()) == k and int(st.item()) == ids.OK
+            assert np.array_equal(J1.cpu().numpy(), J0.cpu().numpy())
+            assert np.array_equal(P1.cpu().numpy(), P0.cpu().numpy())
+    finally:
+        ids.tune_set("select.steps", None)
+
+
 def test_noalloc_rejects_shape_beyond_scratch():
     # 4096 x 2000 with k = 1000 needs more than the static buffer holds:
     # rejected on the host before any launch
