@@ -844,6 +844,27 @@ def main():
         "datasheet": {"hbm_GBps": HBM_PEAK_GBPS, "f32_TFLOPs": 157.3, "bf16_TFLOPs": 2500.0, "f64_TFLOPs": 78.6},
         "note": "read: ids_stream_read of the 1.6 GB input; GEMM: torch.matmul (rocBLAS / hipBLASLt), "
                 "8192^3 (FP32, BF16) and 4096^3 (FP64), TF32 off"}
+    # the projection stage's own product, 120 x 480 x 2000 FP32, by the library
+    # (a small GEMM: latency, not the matrix cores' rate, bounds it)
+    Y1r = torch.randn(l1, N, device="cuda", dtype=torch.float32)
+    for _ in range(3):
+        pr = torch.matmul(Gt, Y1r)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(20):
+        pr = torch.matmul(Gt, Y1r)
+    e1.record()
+    torch.cuda.synchronize()
+    lib_ms = e0.elapsed_time(e1) / 20
+    pflops = 2.0 * l * l1 * N
+    out["projection"] = {"ms": stages["project"], "TFLOPs": pflops / (stages["project"] / 1e3) / 1e12,
+                         "library_same_shape_ms": lib_ms,
+                         "library_TFLOPs": pflops / (lib_ms / 1e3) / 1e12,
+                         "note": "stage time of the K-split MFMA projection (with its partial-sum pass) beside "
+                                 "torch.matmul on the same 120 x 480 x 2000 FP32 product"}
+    del Y1r, pr
     if Omega is not None:
         print("[bench] Gaussian-sketch ID baseline on the same input", flush=True)
         out["gaussian_baseline"] = gaussian_baseline(ids, torch, At, Omega, ms_per_step,
