@@ -31,6 +31,21 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
+def test_binding_constants_match_the_header():
+    # the binding restates the header's enums and flag bits by hand
+    text = re.sub(r"/\*.*?\*/", "", open(HDR).read(), flags=re.S)
+    consts = {m: int(v) for m, v in re.findall(r"\b(IDS_[A-Z0-9_]+)\s*=\s*(\d+)", text)}
+    consts.update({m: int(v) for m, v in re.findall(r"#define\s+(IDS_[A-Z0-9_]+)\s+(\d+)u", text)})
+    want = {"IDS_OK": ids.OK, "IDS_EINVAL": ids.EINVAL, "IDS_EDTYPE": ids.EDTYPE,
+            "IDS_EWORKSPACE": ids.EWORKSPACE, "IDS_EHIP": ids.EHIP, "IDS_ETIMEOUT": ids.ETIMEOUT,
+            "IDS_ERANKDEF": ids.ERANKDEF, "IDS_ENONFINITE": ids.ENONFINITE,
+            "IDS_F64": ids.F64, "IDS_F32": ids.F32, "IDS_BF16": ids.BF16, "IDS_DENSE": ids.DENSE,
+            "IDS_CSR": ids.CSR, "IDS_HASH_FULLRANK": ids.HASH_FULLRANK, "IDS_CHECK_FINITE": ids.CHECK_FINITE,
+            "IDS_DETERMINISTIC": ids.DETERMINISTIC}
+    for name, val in want.items():
+        assert consts.get(name) == val, name
+
+
 def test_status_strings():
     L = ids.lib()
     assert L.ids_status_string(0) == b"IDS_OK"
